@@ -1,0 +1,157 @@
+"""Throughput of the FRE LBM step on one MI355X.
+
+Workload: the D3Q19 shear droplet lattice 256x128x128 (walls in z moving at
+-+u_w, periodic x, y), droplet R=25, xi=2, Ca=0.1, Re=1 (A=5.89e-3,
+kappa=A xi^2, M=5.26 from Pe=0.43, tau_f=1, tau_g=1.74 for Cahn-Hilliard
+stability), FP32 population storage; synthetic seeded
+inputs, already resident in HBM when timing starts.  A step is one full
+time step of the method (all kernels).  Prints one JSON line.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import math
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+PEAK_HBM_GBS = 8000.0
+
+
+def workload(storage: int):
+    from paper_2212_01617_amd import frelbm as F
+    from paper_2212_01617_amd import synth
+    from paper_2212_01617_amd.params import derive_params
+    nx, ny, nz = 256, 128, 128
+    xi, R = 2.0, 25.0
+    dp = derive_params(Re=1.0, Ca=0.1, radius=R, xi=xi, H=nz, Pe=0.43)
+    gamma, uw = dp.rate, dp.wall_u
+    wu = np.zeros((3, 2, 3)); wu[2, 0, 0] = -uw; wu[2, 1, 0] = uw
+    sh = (nz, ny, nx)
+    phi0 = synth.droplet_phi(sh, R, xi, noise=1e-4, seed=0)
+    u0 = synth.shear_velocity(sh, gamma, axis_normal=2)
+    phys = dp.phys()
+    p = F.make_params(F.FRE_D3Q19, (nx, ny, nz), storage=storage, bc=(0, 0, 1), wall_u=wu, **phys)
+    return p, phi0, u0, dict(shape=(nx, ny, nz), wall_u=wu, phys=phys)
+
+
+def bytes_per_lu(q: int, storage: int) -> int:
+    """Algorithmic bytes per lattice update: every population of f and g read
+    once and written once (FP16 storage keeps g_0 in FP32)."""
+    if storage == 0:
+        return 2 * 2 * q * 4
+    return 2 * (q * 2 + (q - 1) * 2 + 4)
+
+
+def time_steps(L, steps, warmup, reps):
+    import torch
+    L.step(warmup)
+    torch.cuda.synchronize()
+    times = []
+    for _ in range(reps):
+        e0 = torch.cuda.Event(enable_timing=True)
+        e1 = torch.cuda.Event(enable_timing=True)
+        torch.cuda.synchronize()
+        e0.record(L.stream)
+        L.step(steps)
+        e1.record(L.stream)
+        torch.cuda.synchronize()
+        times.append(e0.elapsed_time(e1) / steps)
+    return float(np.median(times)), times
+
+
+def cpu_baseline(p_gpu, phi0, u0, meta, steps=20):
+    from oracle import oracle as O
+    nx, ny, nz = meta["shape"]
+    po = O.make_params(1, (nx, ny, nz), bc=(0, 0, 1), wall_u=meta["wall_u"], **meta["phys"])
+    L = O.Lattice(po, phi0, None, u0)
+    L.step(1)  # first touch
+    t0 = time.perf_counter()
+    L.step(steps)
+    dt = time.perf_counter() - t0
+    cores = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
+    return {"value": round(nx * ny * nz * steps / dt / 1e6, 3), "unit": "MLUPS", "cores": cores,
+            "kind": "oracle",
+            "sample": f"{steps} steps of the full 256x128x128 D3Q19 lattice (FP64 oracle, OpenMP, {dt:.1f} s)"}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=1000)
+    ap.add_argument("--warmup", type=int, default=50)
+    ap.add_argument("--reps", type=int, default=5)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-fp16", action="store_true")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print("bench.py runs on one GPU only: this build has no multi-GPU path "
+              "(one lattice per GPU; see the sharding notes in DESIGN.md)", file=sys.stderr)
+        sys.exit(2)
+    import torch
+    from paper_2212_01617_amd import frelbm as F
+    if not os.path.exists(F.LIB_PATH):
+        from paper_2212_01617_amd import build
+        build.build()
+    torch.cuda.init()
+    stream = torch.cuda.Stream()
+
+    res = {}
+    for storage in ((0,) if args.no_fp16 else (0, 1)):
+        p, phi0, u0, meta = workload(storage)
+        L = F.Lattice(p, phi0, None, u0, stream=stream)
+        ms, all_ms = time_steps(L, args.steps, args.warmup, args.reps)
+        n_fluid = meta["shape"][0] * meta["shape"][1] * meta["shape"][2]
+        prof = L.profile(20)
+        ok = L.reduce()
+        res[storage] = dict(ms=ms, all_ms=all_ms, n=n_fluid, prof=prof, L=L, meta=meta,
+                            p=p, phi0=phi0, u0=u0, sums=ok)
+
+    r = res[0]
+    n = r["n"]
+    mlups = n / (r["ms"] * 1e-3) / 1e6
+    b = bytes_per_lu(19, 0)
+    dom = max(r["prof"], key=r["prof"].get)
+    dom_ms = r["prof"][dom]
+    achieved = b * n / (dom_ms * 1e-3) / 1e9
+    out = {
+        "metric": "MLUPS and %HBM roofline (D3Q19 FP32 vs FP16-store); p50/p99 run latency",
+        "value": round(mlups, 1),
+        "unit": "MLUPS",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(r["ms"], 5),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32",
+        "data": "synthetic",
+        "config": {"workload": "D3Q19 shear droplet 256x128x128, walls in z, R=25, xi=2, Ca=0.1, Re=1, FP32 storage",
+                   "storage": "fp32", "fluid_cells": n, "bytes_per_lu": b},
+        "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": PEAK_HBM_GBS, "unit": "GB/s",
+                     "frac": round(achieved / PEAK_HBM_GBS, 4), "traffic": None,
+                     "kernel": dom, "kernel_ms": round(dom_ms, 5),
+                     "step_frac": round(mlups * 1e6 * b / 1e9 / PEAK_HBM_GBS, 4)},
+        "kernels_ms": {k: round(v, 5) for k, v in r["prof"].items()},
+    }
+    if 1 in res:
+        r16 = res[1]
+        m16 = r16["n"] / (r16["ms"] * 1e-3) / 1e6
+        b16 = bytes_per_lu(19, 1)
+        out["fp16_store"] = {"value": round(m16, 1), "unit": "MLUPS", "ms_per_step": round(r16["ms"], 5),
+                             "bytes_per_lu": b16, "step_frac": round(m16 * 1e6 * b16 / 1e9 / PEAK_HBM_GBS, 4),
+                             "kernels_ms": {k: round(v, 5) for k, v in r16["prof"].items()}}
+    if not args.no_cpu_baseline:
+        out["cpu_baseline"] = cpu_baseline(r["p"], r["phi0"], r["u0"], r["meta"])
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

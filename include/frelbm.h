@@ -1,0 +1,188 @@
+/*
+ * frelbm.h -- C ABI of the MI355X free-energy lattice Boltzmann library.
+ *
+ * The library advances a binary-mixture lattice with the free-energy LBM of
+ * Simonis et al., "Binary mixture flow with free energy lattice Boltzmann
+ * methods" (arXiv 2212.01617): a Navier-Stokes population f (BGK with Guo
+ * forcing, Sec. 2.2 eqs. LBE, bgk, feq, Fi) and a Cahn-Hilliard population g
+ * (Sec. 2.2 eqs. LBEg, geq), coupled by the thermodynamic force (eq. F) built
+ * from the chemical potentials (eqs. mu_rho, mu_phi), on D2Q9 or D3Q19,
+ * collide-then-stream as in Sec. 2.3 and Algorithm 1.
+ *
+ * Conventions shared by every call:
+ *  - Fields on the host are double, shaped (nz, ny, nx) with x fastest:
+ *    cell = x + nx*(y + ny*z).  Vector fields are component-major [3][N].
+ *  - Device memory is owned by the caller.  The library only borrows the
+ *    buffer given to fre_lattice_init / fre_batch_create for the handle's
+ *    lifetime and never frees it.  Host buffers are the caller's.
+ *  - All device work is enqueued on the caller's HIP stream (hipStream_t
+ *    passed as void*; NULL = the default stream).  fre_step is asynchronous;
+ *    every call that returns host data synchronises that stream first.
+ *  - Every call returns a fre_status; on failure fre_last_error() gives a
+ *    thread-local message.  Nothing throws across the ABI.  Parameters are
+ *    validated before any device work is enqueued.
+ *  - One handle per stream; calls on one handle are not re-entrant.
+ */
+#ifndef FRELBM_H
+#define FRELBM_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef int32_t fre_status;
+#define FRE_OK 0
+#define FRE_EINVAL (-1)   /* bad argument or parameter                     */
+#define FRE_ENOMEM (-2)   /* caller buffer too small                       */
+#define FRE_EDEVICE (-3)  /* a HIP call failed                             */
+#define FRE_ESTATE (-4)   /* handle is in the failed state                 */
+#define FRE_ENUMERIC (-5) /* a non-finite value was found on the lattice   */
+
+#define FRE_D2Q9 0
+#define FRE_D3Q19 1
+
+#define FRE_FP32 0 /* populations stored as float                           */
+#define FRE_FP16 1 /* f_i - w_i and g_i (i>0) as half, g_0 as float          */
+
+#define FRE_PERIODIC 0
+#define FRE_WALL 1 /* halfway bounce-back wall at both ends of the axis     */
+
+/* Solid-mask codes (uint8 per fluid-domain cell). */
+#define FRE_MASK_FLUID 0
+#define FRE_MASK_SOLID 1  /* static obstacle                                */
+#define FRE_MASK_ROLLER0 2 /* 2+k: cell moves with roller k (k < 4)          */
+
+/* Field bits for fre_read_moments, written in this order, N doubles each
+ * (FRE_F_U writes 3N: ux, uy, uz). */
+#define FRE_F_RHO 1u
+#define FRE_F_PHI 2u
+#define FRE_F_U 4u
+#define FRE_F_MU_RHO 8u
+#define FRE_F_MU_PHI 16u
+#define FRE_F_P 32u
+
+/* A staircase cylinder (rotating roller): the cells whose mask code is 2+k
+ * move rigidly with angular velocity omega about the line through `center`
+ * parallel to axis `axis` (0=x, 1=y, 2=z).  The mask itself is an input;
+ * `radius` is informational (tip-speed check). */
+typedef struct fre_roller {
+  double center[3];
+  double radius;
+  double omega;
+  int32_t axis;
+  int32_t reserved;
+} fre_roller;
+
+/* Per-instance parameters (Sec. 2.2).
+ *  kind, nx, ny, nz, storage, bc: shape and layout (nz = 1, bc[2] periodic
+ *    for D2Q9).
+ *  wall_u[a][s][b]: velocity component b of the wall closing axis a at its
+ *    low (s=0) or high (s=1) end; used when bc[a] == FRE_WALL.
+ *  Free energy, eq. (functional): with use_paper_form = 0 the symmetric
+ *    binary energy A/4 (phi^2-1)^2 + kappa/2 |grad phi|^2 is mapped to
+ *    kappa1 = kappa2 = 4A, alpha = sqrt(kappa / (2A)); with
+ *    use_paper_form = 1, kappa1, kappa2, alpha are used as given.
+ *  tau_f, tau_g > 1/2: relaxation times; M > 0: mobility, with
+ *    Gamma = M / (tau_g - 1/2) (Sec. 2.2, mobility relation).
+ * Validation: tau > 1/2, kappa1, kappa2, alpha > 0 (A, kappa > 0), M > 0,
+ * |wall_u| <= 0.1 and |omega| * radius <= 0.1 (Mach guard), sizes >= 1,
+ * storage/kind/bc codes in range. */
+typedef struct fre_params {
+  int32_t kind;
+  int32_t nx, ny, nz;
+  int32_t storage;
+  int32_t bc[3];
+  double wall_u[3][2][3];
+  int32_t n_rollers;
+  int32_t reserved0;
+  fre_roller rollers[4];
+  double A, kappa;
+  double kappa1, kappa2, alpha;
+  int32_t use_paper_form;
+  int32_t reserved1;
+  double tau_f, tau_g, M;
+} fre_params;
+
+typedef struct fre_lattice fre_lattice;
+typedef struct fre_batch fre_batch;
+
+/* Device bytes fre_lattice_init needs for these parameters (populations in
+ * place, coupling fields, mask and scratch).  No device work. */
+fre_status fre_footprint(const fre_params *p, size_t *device_bytes);
+
+/* Create a lattice in the caller's device buffer (>= fre_footprint bytes,
+ * 256-byte aligned) and initialise it at equilibrium (Sec. 2.3):
+ * f = f^eq(rho0, u0), g = g^eq(phi0, mu_phi(rho0, phi0), u0).
+ *  phi0: N doubles (required, finite).  rho0: N doubles or NULL (= 1).
+ *  u0: 3N doubles or NULL (= 0).  solid_mask: N bytes or NULL (= all fluid),
+ *  codes FRE_MASK_*; roller codes must be < 2 + n_rollers.
+ * Synchronises the stream before returning.  *out is freed with
+ * fre_lattice_destroy. */
+fre_status fre_lattice_init(const fre_params *p, void *device_buf, size_t bytes,
+                            void *hip_stream, const double *phi0,
+                            const double *rho0, const double *u0,
+                            const uint8_t *solid_mask, fre_lattice **out);
+
+/* Replace the physical parameters (free energy, tau, M, wall and roller
+ * velocities) of an existing lattice; shape, storage and bc must not change.
+ * Takes effect for the next step. */
+fre_status fre_set_params(fre_lattice *L, const fre_params *p);
+
+/* Advance n >= 0 time steps (Algorithm 1 at every fluid node, then
+ * streaming with moving bounce-back), asynchronously on the bound stream.
+ * Returns FRE_ESTATE if the lattice has failed. */
+fre_status fre_step(fre_lattice *L, int64_t n);
+
+/* Observables at the current time, without stepping: the fields selected by
+ * field_mask (FRE_F_*) in bit order, each N doubles (U: 3N), into host_out
+ * of n_doubles.  u includes F/2 (eq. veloMoment); P is the bulk pressure
+ * cs^2 rho + rho mu_rho + phi mu_phi - psi_b.  Solid cells read 0.  Syncs. */
+fre_status fre_read_moments(fre_lattice *L, uint32_t field_mask,
+                            double *host_out, size_t n_doubles);
+
+/* The populations f_i, g_i (unshifted, post-streaming at the current time),
+ * layout [q][N] each, into host arrays of n_doubles_each = q*N.  Solid
+ * cells read 0.  Syncs. */
+fre_status fre_read_populations(fre_lattice *L, double *f_out, double *g_out,
+                                size_t n_doubles_each);
+
+/* Global sums over fluid cells, accumulated in FP64 on the device from
+ * compensated FP32 partials: out[0] sum rho, [1] sum phi, [2] sum |phi|,
+ * [3..5] sum rho u (with F/2), [6] number of cells with a non-finite value,
+ * [7] number of fluid cells.  A non-zero out[6] puts the lattice in the
+ * failed state and returns FRE_ENUMERIC.  Syncs. */
+fre_status fre_reduce(fre_lattice *L, double out[8]);
+
+/* Current step count and state (0 ok, 1 failed). */
+fre_status fre_info(const fre_lattice *L, int64_t *step, int32_t *state);
+
+/* Checkpoint: raw populations at storage precision, step count and the
+ * parameters.  fre_state_bytes gives the host size; fre_save writes it
+ * (syncs), fre_load restores it into a lattice of identical shape/storage
+ * (a restored run continues bitwise as the uninterrupted one). */
+fre_status fre_state_bytes(const fre_lattice *L, size_t *bytes);
+fre_status fre_save(fre_lattice *L, void *host, size_t bytes);
+fre_status fre_load(fre_lattice *L, const void *host, size_t bytes);
+
+/* Measurement: advance n >= 1 steps launching each kernel of the step
+ * separately with HIP events around it on the bound stream (no graph), and
+ * write the mean duration in ms of each kernel per step into kernel_ms
+ * (max_kernels entries); *n_kernels receives the number of kernels per step.
+ * fre_kernel_name(k) names kernel k (NULL beyond the last).  Syncs. */
+fre_status fre_profile_step(fre_lattice *L, int64_t n, double *kernel_ms,
+                            int32_t max_kernels, int32_t *n_kernels);
+const char *fre_kernel_name(int32_t k);
+
+/* Release the handle (accepts NULL).  Never frees caller memory. */
+void fre_lattice_destroy(fre_lattice *L);
+
+/* Thread-local message of the last failing call on this thread. */
+const char *fre_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* FRELBM_H */

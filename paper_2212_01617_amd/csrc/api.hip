@@ -1,0 +1,589 @@
+// api.hip -- host side of the C ABI declared in include/frelbm.h.
+//
+// A lattice lives entirely in the caller's device buffer: population planes
+// (structure of arrays, one plane per direction, each plane padded to 256 B),
+// the cell mask, the coupling fields (rho - 1, phi), (mu_rho, mu_phi), Pi, an
+// auxiliary float4 field, the list of solid cells next to fluid, and the
+// reduction partials.  Steps are enqueued on the caller's stream; on a
+// non-default stream a pair of steps (even + odd AA parity) is captured once
+// into a HIP graph and replayed.
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <string>
+#include <vector>
+
+#include "../../include/frelbm.h"
+#include "kernels.h"
+
+using namespace frelbm;
+
+namespace {
+
+thread_local std::string g_err;
+
+fre_status fail(fre_status s, const char *fmt, ...) __attribute__((format(printf, 2, 3)));
+fre_status fail(fre_status s, const char *fmt, ...) {
+  char buf[512];
+  va_list ap;
+  va_start(ap, fmt);
+  vsnprintf(buf, sizeof buf, fmt, ap);
+  va_end(ap);
+  g_err = buf;
+  return s;
+}
+
+#define HIP_TRY(expr)                                                               \
+  do {                                                                              \
+    hipError_t e_ = (expr);                                                         \
+    if (e_ != hipSuccess)                                                           \
+      return fail(FRE_EDEVICE, "%s failed: %s", #expr, hipGetErrorString(e_));      \
+  } while (0)
+
+constexpr size_t kAlign = 256;
+size_t align_up(size_t v, size_t a) { return (v + a - 1) / a * a; }
+
+struct Plan {
+  int q;
+  int ext[3];
+  int per[3];
+  int off[3];
+  long long ncell, np;
+  size_t o_f, o_g, o_g0, o_mask, o_M, o_MU, o_PI, o_AUX, o_fill, o_part, total;
+};
+
+fre_status validate(const fre_params *p) {
+  if (!p) return fail(FRE_EINVAL, "params is NULL");
+  if (p->kind != FRE_D2Q9 && p->kind != FRE_D3Q19) return fail(FRE_EINVAL, "kind %d not D2Q9/D3Q19", p->kind);
+  if (p->storage != FRE_FP32 && p->storage != FRE_FP16) return fail(FRE_EINVAL, "storage %d", p->storage);
+  if (p->nx < 1 || p->ny < 1 || p->nz < 1) return fail(FRE_EINVAL, "sizes must be >= 1");
+  for (int a = 0; a < 3; ++a)
+    if (p->bc[a] != FRE_PERIODIC && p->bc[a] != FRE_WALL) return fail(FRE_EINVAL, "bc[%d]=%d", a, p->bc[a]);
+  if (p->kind == FRE_D2Q9 && (p->nz != 1 || p->bc[2] != FRE_PERIODIC))
+    return fail(FRE_EINVAL, "D2Q9 needs nz = 1 and a periodic z axis");
+  double cells = (double)(p->nx + 2) * (p->ny + 2) * (p->nz + 2);
+  if (cells > 2.0e9) return fail(FRE_EINVAL, "lattice too large for 32-bit cell indices");
+  if (!(p->tau_f > 0.5) || !(p->tau_g > 0.5)) return fail(FRE_EINVAL, "tau_f, tau_g must exceed 1/2");
+  if (!(p->M > 0.0) || !std::isfinite(p->M)) return fail(FRE_EINVAL, "mobility M must be > 0");
+  if (p->use_paper_form) {
+    if (!(p->kappa1 > 0) || !(p->kappa2 > 0) || !(p->alpha > 0))
+      return fail(FRE_EINVAL, "kappa1, kappa2, alpha must be > 0");
+  } else if (!(p->A > 0) || !(p->kappa > 0)) {
+    return fail(FRE_EINVAL, "A and kappa must be > 0");
+  }
+  for (int a = 0; a < 3; ++a)
+    for (int s = 0; s < 2; ++s) {
+      const double *u = p->wall_u[a][s];
+      double m = std::sqrt(u[0] * u[0] + u[1] * u[1] + u[2] * u[2]);
+      if (!(m <= 0.1)) return fail(FRE_EINVAL, "wall speed %g exceeds 0.1 (Mach guard)", m);
+    }
+  if (p->n_rollers < 0 || p->n_rollers > 4) return fail(FRE_EINVAL, "n_rollers must be 0..4");
+  for (int k = 0; k < p->n_rollers; ++k) {
+    const fre_roller &r = p->rollers[k];
+    if (r.axis < 0 || r.axis > 2) return fail(FRE_EINVAL, "roller %d axis", k);
+    if (!std::isfinite(r.omega) || !(std::fabs(r.omega) * r.radius <= 0.1))
+      return fail(FRE_EINVAL, "roller %d tip speed exceeds 0.1 (Mach guard)", k);
+  }
+  return FRE_OK;
+}
+
+Plan make_plan(const fre_params *p) {
+  Plan P{};
+  P.q = p->kind == FRE_D2Q9 ? 9 : 19;
+  int n[3] = {p->nx, p->ny, p->nz};
+  P.ncell = 1;
+  for (int a = 0; a < 3; ++a) {
+    P.per[a] = p->bc[a] == FRE_PERIODIC;
+    P.off[a] = P.per[a] ? 0 : 1;
+    P.ext[a] = n[a] + 2 * P.off[a];
+    P.ncell *= P.ext[a];
+  }
+  P.np = (long long)align_up((size_t)P.ncell, 128);  // 256 B planes for half, 512 B for float
+  size_t es = p->storage == FRE_FP32 ? 4 : 2;
+  size_t o = 0;
+  auto take = [&](size_t bytes) { size_t at = o; o = align_up(o + bytes, kAlign); return at; };
+  P.o_f = take((size_t)P.q * P.np * es);
+  if (p->storage == FRE_FP32) {
+    P.o_g = take((size_t)P.q * P.np * 4);
+    P.o_g0 = 0;
+  } else {
+    P.o_g = take((size_t)(P.q - 1) * P.np * 2);
+    P.o_g0 = take((size_t)P.np * 4);
+  }
+  P.o_mask = take((size_t)P.ncell);
+  P.o_M = take((size_t)P.ncell * 8);
+  P.o_MU = take((size_t)P.ncell * 8);
+  P.o_PI = take((size_t)P.ncell * 4);
+  P.o_AUX = take((size_t)P.ncell * 16);
+  P.o_fill = take((size_t)P.ncell * 4);
+  P.o_part = take((size_t)reduce_blocks() * 8 * sizeof(double));
+  P.total = o;
+  return P;
+}
+
+Phys make_phys(const fre_params *p) {
+  Phys ph{};
+  double k1, k2, al;
+  if (p->use_paper_form) {
+    k1 = p->kappa1; k2 = p->kappa2; al = p->alpha;
+  } else {
+    k1 = k2 = 4.0 * p->A;
+    al = std::sqrt(p->kappa / (2.0 * p->A));
+  }
+  ph.k1 = (float)k1;
+  ph.k2 = (float)k2;
+  ph.a2q = (float)(al * al / 4.0);
+  ph.om_f = (float)(1.0 / p->tau_f);
+  ph.om_g = (float)(1.0 / p->tau_g);
+  ph.guo = (float)(1.0 - 0.5 / p->tau_f);
+  ph.gam3 = (float)(3.0 * p->M / (p->tau_g - 0.5));
+  for (int a = 0; a < 3; ++a)
+    for (int s = 0; s < 2; ++s)
+      for (int b = 0; b < 3; ++b) ph.wall_u[a][s][b] = (float)p->wall_u[a][s][b];
+  ph.n_rollers = p->n_rollers;
+  for (int k = 0; k < p->n_rollers; ++k) {
+    for (int a = 0; a < 3; ++a) ph.rc[k][a] = (float)p->rollers[k].center[a];
+    ph.rom[k] = (float)p->rollers[k].omega;
+    ph.rax[k] = p->rollers[k].axis;
+  }
+  return ph;
+}
+
+}  // namespace
+
+struct fre_lattice {
+  fre_params p;
+  Plan plan;
+  LaunchArgs a;
+  uint8_t *base;
+  long long n_user;
+  int64_t t;
+  int state;  // 0 ok, 1 failed
+  std::vector<int> fill_host;
+  hipGraphExec_t graph;  // two steps starting at even parity
+  bool graph_ok;
+};
+
+namespace {
+
+void reset_graph(fre_lattice *L) {
+  if (L->graph_ok) (void)hipGraphExecDestroy(L->graph);
+  L->graph_ok = false;
+}
+
+long long ext_index(const Plan &P, int x, int y, int z) {
+  return (long long)(x + P.off[0]) + (long long)P.ext[0] * ((long long)(y + P.off[1]) + (long long)P.ext[1] * (z + P.off[2]));
+}
+
+fre_status build_mask(fre_lattice *L, const uint8_t *user_mask, std::vector<uint8_t> &mask) {
+  const Plan &P = L->plan;
+  const fre_params &p = L->p;
+  mask.assign((size_t)P.ncell, CELL_GHOST);
+  for (int z = 0; z < p.nz; ++z)
+    for (int y = 0; y < p.ny; ++y)
+      for (int x = 0; x < p.nx; ++x) {
+        long long u = x + (long long)p.nx * (y + (long long)p.ny * z);
+        uint8_t code = user_mask ? user_mask[u] : 0;
+        if (code > 1 && code >= 2 + p.n_rollers)
+          return fail(FRE_EINVAL, "mask code %d at cell %lld: no such roller", code, u);
+        mask[ext_index(P, x, y, z)] = code;
+      }
+  // solid cells with at least one fluid neighbour get stencil fills
+  auto dir = [&](int i, int a) {
+    if (P.q == 9) return a == 0 ? VSet<9>::cx(i) : a == 1 ? VSet<9>::cy(i) : VSet<9>::cz(i);
+    return a == 0 ? VSet<19>::cx(i) : a == 1 ? VSet<19>::cy(i) : VSet<19>::cz(i);
+  };
+  L->fill_host.clear();
+  for (int z = 0; z < P.ext[2]; ++z)
+    for (int y = 0; y < P.ext[1]; ++y)
+      for (int x = 0; x < P.ext[0]; ++x) {
+        long long s = x + (long long)P.ext[0] * (y + (long long)P.ext[1] * z);
+        if (mask[s] == CELL_FLUID) continue;
+        bool near = false;
+        for (int i = 1; i < P.q && !near; ++i) {
+          int v[3] = {x + dir(i, 0), y + dir(i, 1), z + dir(i, 2)};
+          bool ok = true;
+          for (int a = 0; a < 3; ++a) {
+            if (P.per[a]) v[a] = (v[a] % P.ext[a] + P.ext[a]) % P.ext[a];
+            else if (v[a] < 0 || v[a] >= P.ext[a]) ok = false;
+          }
+          if (!ok) continue;
+          long long n = v[0] + (long long)P.ext[0] * (v[1] + (long long)P.ext[1] * v[2]);
+          near = mask[n] == CELL_FLUID;
+        }
+        if (near) L->fill_host.push_back((int)s);
+      }
+  return FRE_OK;
+}
+
+void bind_args(fre_lattice *L) {
+  const Plan &P = L->plan;
+  LaunchArgs &a = L->a;
+  a.q = P.q;
+  a.storage = L->p.storage;
+  a.G.ex = P.ext[0]; a.G.ey = P.ext[1]; a.G.ez = P.ext[2];
+  for (int k = 0; k < 3; ++k) { a.G.per[k] = P.per[k]; a.G.off[k] = P.off[k]; }
+  a.G.np = P.np;
+  a.G.ncell = P.ncell;
+  a.ph = make_phys(&L->p);
+  a.f = L->base + P.o_f;
+  a.g = L->base + P.o_g;
+  a.g0 = L->p.storage == FRE_FP16 ? (float *)(L->base + P.o_g0) : nullptr;
+  a.mask = L->base + P.o_mask;
+  a.M = (float2 *)(L->base + P.o_M);
+  a.MU = (float2 *)(L->base + P.o_MU);
+  a.PI = (float *)(L->base + P.o_PI);
+  a.AUX = (float4 *)(L->base + P.o_AUX);
+  a.fill_list = (int *)(L->base + P.o_fill);
+  a.n_fill = (int)L->fill_host.size();
+}
+
+size_t pops_bytes(const Plan &P, int storage) { return P.o_mask - P.o_f; }
+
+fre_status observe(fre_lattice *L) {
+  launch_observe(L->a, (int)(L->t & 1));
+  HIP_TRY(hipGetLastError());
+  return FRE_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+const char *fre_last_error(void) { return g_err.c_str(); }
+
+fre_status fre_footprint(const fre_params *p, size_t *device_bytes) {
+  fre_status s = validate(p);
+  if (s != FRE_OK) return s;
+  if (!device_bytes) return fail(FRE_EINVAL, "device_bytes is NULL");
+  *device_bytes = make_plan(p).total;
+  return FRE_OK;
+}
+
+fre_status fre_lattice_init(const fre_params *p, void *device_buf, size_t bytes, void *hip_stream,
+                            const double *phi0, const double *rho0, const double *u0,
+                            const uint8_t *solid_mask, fre_lattice **out) {
+  if (!out) return fail(FRE_EINVAL, "out is NULL");
+  *out = nullptr;
+  fre_status s = validate(p);
+  if (s != FRE_OK) return s;
+  if (!phi0) return fail(FRE_EINVAL, "phi0 is NULL");
+  if (!device_buf) return fail(FRE_EINVAL, "device_buf is NULL");
+  if ((uintptr_t)device_buf % kAlign) return fail(FRE_EINVAL, "device_buf must be 256-byte aligned");
+  Plan P = make_plan(p);
+  if (bytes < P.total) return fail(FRE_ENOMEM, "buffer of %zu bytes < footprint %zu", bytes, P.total);
+  long long N = (long long)p->nx * p->ny * p->nz;
+  for (long long u = 0; u < N; ++u) {
+    if (!std::isfinite(phi0[u]) || (rho0 && !(std::isfinite(rho0[u]) && rho0[u] > 0)) ||
+        (u0 && !(std::isfinite(u0[u]) && std::isfinite(u0[N + u]) && std::isfinite(u0[2 * N + u]))))
+      return fail(FRE_EINVAL, "non-finite or non-positive initial value at cell %lld", u);
+  }
+  fre_lattice *L = new fre_lattice();
+  L->p = *p;
+  L->plan = P;
+  L->base = (uint8_t *)device_buf;
+  L->n_user = N;
+  L->t = 0;
+  L->state = 0;
+  L->graph_ok = false;
+  std::vector<uint8_t> mask;
+  s = build_mask(L, solid_mask, mask);
+  if (s != FRE_OK) { delete L; return s; }
+  bind_args(L);
+  L->a.stream = (hipStream_t)hip_stream;
+  // initial fields in storage layout
+  std::vector<float> M((size_t)P.ncell * 2, 0.0f), U((size_t)P.ncell * 4, 0.0f);
+  for (int z = 0; z < p->nz; ++z)
+    for (int y = 0; y < p->ny; ++y)
+      for (int x = 0; x < p->nx; ++x) {
+        long long u = x + (long long)p->nx * (y + (long long)p->ny * z);
+        long long e = ext_index(P, x, y, z);
+        if (mask[e] != CELL_FLUID) continue;
+        M[2 * e] = rho0 ? (float)(rho0[u] - 1.0) : 0.0f;
+        M[2 * e + 1] = (float)phi0[u];
+        if (u0)
+          for (int k = 0; k < 3; ++k) U[4 * e + k] = (float)u0[(long long)k * N + u];
+      }
+  hipStream_t st = L->a.stream;
+  auto cleanup = [&](fre_status r) { if (r != FRE_OK) delete L; return r; };
+#define INIT_TRY(expr)                                                             \
+  do {                                                                             \
+    hipError_t e_ = (expr);                                                        \
+    if (e_ != hipSuccess)                                                          \
+      return cleanup(fail(FRE_EDEVICE, "%s failed: %s", #expr, hipGetErrorString(e_))); \
+  } while (0)
+  INIT_TRY(hipMemsetAsync(L->base + P.o_f, 0, pops_bytes(P, p->storage), st));
+  INIT_TRY(hipMemcpyAsync(L->a.mask, mask.data(), mask.size(), hipMemcpyHostToDevice, st));
+  INIT_TRY(hipMemcpyAsync(L->a.M, M.data(), M.size() * 4, hipMemcpyHostToDevice, st));
+  INIT_TRY(hipMemcpyAsync(L->a.AUX, U.data(), U.size() * 4, hipMemcpyHostToDevice, st));
+  if (!L->fill_host.empty())
+    INIT_TRY(hipMemcpyAsync(L->a.fill_list, L->fill_host.data(), L->fill_host.size() * 4, hipMemcpyHostToDevice, st));
+  INIT_TRY(hipMemsetAsync(L->a.MU, 0, (size_t)P.ncell * 8, st));
+  INIT_TRY(hipMemsetAsync(L->a.PI, 0, (size_t)P.ncell * 4, st));
+  launch_init(L->a);
+  INIT_TRY(hipGetLastError());
+  INIT_TRY(hipStreamSynchronize(st));
+#undef INIT_TRY
+  *out = L;
+  return FRE_OK;
+}
+
+fre_status fre_set_params(fre_lattice *L, const fre_params *p) {
+  if (!L) return fail(FRE_EINVAL, "lattice is NULL");
+  fre_status s = validate(p);
+  if (s != FRE_OK) return s;
+  const fre_params &o = L->p;
+  if (p->kind != o.kind || p->nx != o.nx || p->ny != o.ny || p->nz != o.nz || p->storage != o.storage ||
+      p->bc[0] != o.bc[0] || p->bc[1] != o.bc[1] || p->bc[2] != o.bc[2] || p->n_rollers != o.n_rollers)
+    return fail(FRE_EINVAL, "shape, storage, bc and roller count cannot change");
+  L->p = *p;
+  L->a.ph = make_phys(p);
+  reset_graph(L);
+  return FRE_OK;
+}
+
+fre_status fre_step(fre_lattice *L, int64_t n) {
+  if (!L) return fail(FRE_EINVAL, "lattice is NULL");
+  if (n < 0) return fail(FRE_EINVAL, "negative step count");
+  if (L->state) return fail(FRE_ESTATE, "lattice is in the failed state");
+  hipStream_t st = L->a.stream;
+  auto one = [&]() -> fre_status {
+    launch_step(L->a, (int)(L->t & 1));
+    HIP_TRY(hipGetLastError());
+    L->t += 1;
+    return FRE_OK;
+  };
+  if (st == nullptr || n < 4) {
+    for (int64_t k = 0; k < n; ++k) {
+      fre_status s = one();
+      if (s != FRE_OK) return s;
+    }
+    return FRE_OK;
+  }
+  if (L->t & 1) {
+    fre_status s = one();
+    if (s != FRE_OK) return s;
+    --n;
+  }
+  if (!L->graph_ok) {
+    hipGraph_t g;
+    HIP_TRY(hipStreamBeginCapture(st, hipStreamCaptureModeThreadLocal));
+    launch_step(L->a, 0);
+    launch_step(L->a, 1);
+    hipError_t e = hipStreamEndCapture(st, &g);
+    if (e != hipSuccess) return fail(FRE_EDEVICE, "graph capture failed: %s", hipGetErrorString(e));
+    e = hipGraphInstantiate(&L->graph, g, nullptr, nullptr, 0);
+    (void)hipGraphDestroy(g);
+    if (e != hipSuccess) return fail(FRE_EDEVICE, "graph instantiate failed: %s", hipGetErrorString(e));
+    L->graph_ok = true;
+  }
+  for (int64_t k = 0; k + 1 < n; k += 2) {
+    HIP_TRY(hipGraphLaunch(L->graph, st));
+    L->t += 2;
+  }
+  if (n & 1) return one();
+  return FRE_OK;
+}
+
+fre_status fre_read_moments(fre_lattice *L, uint32_t field_mask, double *host_out, size_t n_doubles) {
+  if (!L || !host_out) return fail(FRE_EINVAL, "NULL argument");
+  if (field_mask == 0 || (field_mask & ~63u)) return fail(FRE_EINVAL, "bad field mask 0x%x", field_mask);
+  size_t need = 0;
+  const long long N = L->n_user;
+  for (int b = 0; b < 6; ++b)
+    if (field_mask & (1u << b)) need += (b == 2 ? 3 : 1) * (size_t)N;
+  if (n_doubles < need) return fail(FRE_EINVAL, "output holds %zu doubles, need %zu", n_doubles, need);
+  const Plan &P = L->plan;
+  fre_status s = observe(L);
+  if (s != FRE_OK) return s;
+  std::vector<float> M((size_t)P.ncell * 2), MU((size_t)P.ncell * 2), AUX((size_t)P.ncell * 4);
+  std::vector<uint8_t> mask((size_t)P.ncell);
+  hipStream_t st = L->a.stream;
+  HIP_TRY(hipMemcpyAsync(M.data(), L->a.M, M.size() * 4, hipMemcpyDeviceToHost, st));
+  HIP_TRY(hipMemcpyAsync(MU.data(), L->a.MU, MU.size() * 4, hipMemcpyDeviceToHost, st));
+  HIP_TRY(hipMemcpyAsync(AUX.data(), L->a.AUX, AUX.size() * 4, hipMemcpyDeviceToHost, st));
+  HIP_TRY(hipMemcpyAsync(mask.data(), L->a.mask, mask.size(), hipMemcpyDeviceToHost, st));
+  HIP_TRY(hipStreamSynchronize(st));
+  const fre_params &p = L->p;
+  double *o = host_out;
+  for (int b = 0; b < 6; ++b) {
+    if (!(field_mask & (1u << b))) continue;
+    int ncomp = b == 2 ? 3 : 1;
+    for (int k = 0; k < ncomp; ++k) {
+      for (int z = 0; z < p.nz; ++z)
+        for (int y = 0; y < p.ny; ++y)
+          for (int x = 0; x < p.nx; ++x) {
+            long long u = x + (long long)p.nx * (y + (long long)p.ny * z);
+            long long e = ext_index(P, x, y, z);
+            double v = 0.0;
+            if (mask[e] == CELL_FLUID) {
+              switch (b) {
+                case 0: v = 1.0 + (double)M[2 * e]; break;
+                case 1: v = M[2 * e + 1]; break;
+                case 2: v = AUX[4 * e + k]; break;
+                case 3: v = MU[2 * e]; break;
+                case 4: v = MU[2 * e + 1]; break;
+                default: v = AUX[4 * e + 3]; break;
+              }
+            }
+            o[u] = v;
+          }
+      o += N;
+    }
+  }
+  return FRE_OK;
+}
+
+fre_status fre_read_populations(fre_lattice *L, double *f_out, double *g_out, size_t n_doubles_each) {
+  if (!L || !f_out || !g_out) return fail(FRE_EINVAL, "NULL argument");
+  const Plan &P = L->plan;
+  const long long N = L->n_user;
+  if (n_doubles_each < (size_t)P.q * N) return fail(FRE_EINVAL, "outputs need q*N doubles each");
+  float *tmp = nullptr;
+  size_t nb = (size_t)2 * P.q * P.ncell * sizeof(float);
+  HIP_TRY(hipMalloc(&tmp, nb));
+  launch_read_pops(L->a, (int)(L->t & 1), tmp);
+  std::vector<float> h((size_t)2 * P.q * P.ncell);
+  hipError_t e = hipGetLastError();
+  if (e == hipSuccess) e = hipMemcpyAsync(h.data(), tmp, nb, hipMemcpyDeviceToHost, L->a.stream);
+  if (e == hipSuccess) e = hipStreamSynchronize(L->a.stream);
+  (void)hipFree(tmp);
+  if (e != hipSuccess) return fail(FRE_EDEVICE, "population readback failed: %s", hipGetErrorString(e));
+  const fre_params &p = L->p;
+  for (int i = 0; i < P.q; ++i)
+    for (int z = 0; z < p.nz; ++z)
+      for (int y = 0; y < p.ny; ++y)
+        for (int x = 0; x < p.nx; ++x) {
+          long long u = x + (long long)p.nx * (y + (long long)p.ny * z);
+          long long ee = ext_index(P, x, y, z);
+          f_out[(long long)i * N + u] = h[(size_t)i * P.ncell + ee];
+          g_out[(long long)i * N + u] = h[(size_t)(P.q + i) * P.ncell + ee];
+        }
+  return FRE_OK;
+}
+
+fre_status fre_reduce(fre_lattice *L, double out[8]) {
+  if (!L || !out) return fail(FRE_EINVAL, "NULL argument");
+  fre_status s = observe(L);
+  if (s != FRE_OK) return s;
+  double *part = (double *)(L->base + L->plan.o_part);
+  launch_reduce(L->a, part);
+  HIP_TRY(hipGetLastError());
+  std::vector<double> h((size_t)reduce_blocks() * 8);
+  HIP_TRY(hipMemcpyAsync(h.data(), part, h.size() * 8, hipMemcpyDeviceToHost, L->a.stream));
+  HIP_TRY(hipStreamSynchronize(L->a.stream));
+  double acc[8] = {0, 0, 0, 0, 0, 0, 0, 0};
+  for (int b = 0; b < reduce_blocks(); ++b)
+    for (int k = 0; k < 8; ++k) acc[k] += h[(size_t)b * 8 + k];
+  out[0] = acc[7] + acc[0];  // sum rho = n_fluid + sum (rho - 1)
+  for (int k = 1; k < 8; ++k) out[k] = acc[k];
+  if (acc[6] > 0) {
+    L->state = 1;
+    return fail(FRE_ENUMERIC, "%.0f fluid cells hold non-finite values at step %lld", acc[6], (long long)L->t);
+  }
+  return FRE_OK;
+}
+
+fre_status fre_info(const fre_lattice *L, int64_t *step, int32_t *state) {
+  if (!L) return fail(FRE_EINVAL, "lattice is NULL");
+  if (step) *step = L->t;
+  if (state) *state = L->state;
+  return FRE_OK;
+}
+
+namespace {
+struct CkptHeader {
+  char magic[8];
+  int32_t version, kind, nx, ny, nz, storage;
+  int64_t step;
+  uint64_t pops_bytes;
+  fre_params params;
+};
+}  // namespace
+
+fre_status fre_state_bytes(const fre_lattice *L, size_t *bytes) {
+  if (!L || !bytes) return fail(FRE_EINVAL, "NULL argument");
+  *bytes = sizeof(CkptHeader) + pops_bytes(L->plan, L->p.storage);
+  return FRE_OK;
+}
+
+fre_status fre_save(fre_lattice *L, void *host, size_t bytes) {
+  size_t need;
+  fre_status s = fre_state_bytes(L, &need);
+  if (s != FRE_OK) return s;
+  if (!host || bytes < need) return fail(FRE_EINVAL, "checkpoint buffer needs %zu bytes", need);
+  CkptHeader h{};
+  memcpy(h.magic, "FRELBM01", 8);
+  h.version = 1;
+  h.kind = L->p.kind; h.nx = L->p.nx; h.ny = L->p.ny; h.nz = L->p.nz; h.storage = L->p.storage;
+  h.step = L->t;
+  h.pops_bytes = pops_bytes(L->plan, L->p.storage);
+  h.params = L->p;
+  memcpy(host, &h, sizeof h);
+  HIP_TRY(hipMemcpyAsync((uint8_t *)host + sizeof h, L->base + L->plan.o_f, h.pops_bytes, hipMemcpyDeviceToHost, L->a.stream));
+  HIP_TRY(hipStreamSynchronize(L->a.stream));
+  return FRE_OK;
+}
+
+fre_status fre_load(fre_lattice *L, const void *host, size_t bytes) {
+  if (!L || !host || bytes < sizeof(CkptHeader)) return fail(FRE_EINVAL, "bad checkpoint buffer");
+  CkptHeader h;
+  memcpy(&h, host, sizeof h);
+  if (memcmp(h.magic, "FRELBM01", 8) != 0 || h.version != 1) return fail(FRE_EINVAL, "not a checkpoint");
+  if (h.kind != L->p.kind || h.nx != L->p.nx || h.ny != L->p.ny || h.nz != L->p.nz || h.storage != L->p.storage ||
+      h.pops_bytes != pops_bytes(L->plan, L->p.storage) || bytes < sizeof h + h.pops_bytes)
+    return fail(FRE_EINVAL, "checkpoint shape/storage does not match this lattice");
+  fre_status s = fre_set_params(L, &h.params);
+  if (s != FRE_OK) return s;
+  HIP_TRY(hipMemcpyAsync(L->base + L->plan.o_f, (const uint8_t *)host + sizeof h, h.pops_bytes, hipMemcpyHostToDevice, L->a.stream));
+  HIP_TRY(hipStreamSynchronize(L->a.stream));
+  L->t = h.step;
+  L->state = 0;
+  return FRE_OK;
+}
+
+fre_status fre_profile_step(fre_lattice *L, int64_t n, double *kernel_ms, int32_t max_kernels,
+                            int32_t *n_kernels) {
+  if (!L || !kernel_ms || !n_kernels) return fail(FRE_EINVAL, "NULL argument");
+  if (n < 1) return fail(FRE_EINVAL, "n must be >= 1");
+  if (L->state) return fail(FRE_ESTATE, "lattice is in the failed state");
+  const int K = step_kernel_count();
+  if (max_kernels < K) return fail(FRE_EINVAL, "kernel_ms needs %d entries", K);
+  std::vector<hipEvent_t> ev((size_t)(K + 1) * n);
+  for (auto &e : ev) HIP_TRY(hipEventCreate(&e));
+  for (int k = 0; k < K; ++k) kernel_ms[k] = 0.0;
+  fre_status st = FRE_OK;
+  for (int64_t s = 0; s < n; ++s) {
+    launch_step_events(L->a, (int)(L->t & 1), &ev[(size_t)s * (K + 1)]);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) { st = fail(FRE_EDEVICE, "launch failed: %s", hipGetErrorString(e)); break; }
+    L->t += 1;
+  }
+  if (st == FRE_OK) {
+    hipError_t e = hipStreamSynchronize(L->a.stream);
+    if (e != hipSuccess) st = fail(FRE_EDEVICE, "sync failed: %s", hipGetErrorString(e));
+  }
+  if (st == FRE_OK)
+    for (int64_t s = 0; s < n; ++s)
+      for (int k = 0; k < K; ++k) {
+        float ms = 0.0f;
+        (void)hipEventElapsedTime(&ms, ev[(size_t)s * (K + 1) + k], ev[(size_t)s * (K + 1) + k + 1]);
+        kernel_ms[k] += ms / (double)n;
+      }
+  for (auto &e : ev) (void)hipEventDestroy(e);
+  *n_kernels = K;
+  return st;
+}
+
+const char *fre_kernel_name(int32_t k) { return step_kernel_name(k); }
+
+void fre_lattice_destroy(fre_lattice *L) {
+  if (!L) return;
+  reset_graph(L);
+  delete L;
+}
+
+}  // extern "C"

@@ -1,0 +1,475 @@
+// kernels.hip -- HIP kernels (gfx950) of the free-energy LBM step.
+//
+// One time step (Algorithm 1 of Simonis et al., arXiv 2212.01617, then
+// streaming, Sec. 2.3) is five launches over the storage grid:
+//   k_moments   rho - 1, phi at fluid cells             (eqs. densMoment, ordeMoment)
+//   k_fill<2>   rho, phi at solid cells next to fluid   (fluid-neighbour mean)
+//   k_potential mu_rho, mu_phi and Pi = rho mu_rho + phi mu_phi   (eqs. mu_rho, mu_phi)
+//   k_fill<1>   Pi at solid cells next to fluid
+//   k_collide   force (eq. F), velocity (eq. veloMoment), BGK collision of f
+//               with Guo forcing (eqs. bgk, feq, Fi) and of g (eqs. LBEg,
+//               geq), streaming with moving bounce-back, in place.
+//
+// Streaming is in place with the AA access pattern: at even time steps a
+// cell reads and writes only its own slots (writing direction i into slot
+// opp(i)); at odd steps it reads from and writes to its neighbours' slots.
+// Each slot is read and written by the same thread within a step, so the
+// update is race-free without a second population buffer.
+#include "lbm_device.h"
+#include "kernels.h"
+
+namespace frelbm {
+
+constexpr int BX = 64, BY = 4;
+
+__device__ __forceinline__ bool cell_of_thread(const Geom &G, int &x, int &y, int &z, long long &c) {
+  x = blockIdx.x * BX + threadIdx.x;
+  y = blockIdx.y * BY + threadIdx.y;
+  z = blockIdx.z;
+  if (x >= G.ex || y >= G.ey) return false;
+  c = (long long)x + (long long)G.ex * ((long long)y + (long long)G.ey * z);
+  return true;
+}
+
+// Load the q populations of fluid cell c at time parity `odd` (AA pattern).
+template <int Q, int S>
+__device__ __forceinline__ void load_pops(const Pops<S> &P, const int *nb, long long c, int odd,
+                                          float *df, float *g) {
+#pragma unroll
+  for (int i = 0; i < Q; ++i) {
+    if (!odd) {
+      df[i] = P.ldf(i, c);
+      g[i] = P.ldg(i, c);
+    } else {
+      // f_i(x) = f_i*(x - c_i), written by x - c_i into its slot opp(i)
+      long long s = i == 0 ? c : nb[opp(i)];
+      df[i] = P.ldf(opp(i), s);
+      g[i] = P.ldg(opp(i), s);
+    }
+  }
+}
+
+template <int Q>
+__device__ __forceinline__ void neighbours(const Geom &G, int x, int y, int z, int *nb) {
+  using V = VSet<Q>;
+#pragma unroll
+  for (int i = 0; i < Q; ++i) nb[i] = nb_fluid<V>(G, x, y, z, i);
+}
+
+// ---------------------------------------------------------------------------
+template <int Q, int S>
+__global__ __launch_bounds__(BX *BY) void k_moments(Pops<S> P, const uint8_t *__restrict__ mask,
+                                                    float2 *__restrict__ M, Geom G, int odd) {
+  int x, y, z;
+  long long c;
+  if (!cell_of_thread(G, x, y, z, c)) return;
+  if (mask[c] != CELL_FLUID) return;
+  int nb[Q];
+  neighbours<Q>(G, x, y, z, nb);
+  float df[Q], g[Q];
+  load_pops<Q, S>(P, nb, c, odd, df, g);
+  float drho = 0.0f, phi = 0.0f;
+#pragma unroll
+  for (int i = 0; i < Q; ++i) {
+    drho += df[i];
+    phi += g[i];
+  }
+  M[c] = make_float2(drho, phi);
+}
+
+// Solid cells next to fluid take the lattice-weighted mean of their fluid
+// neighbours (for rho, phi and Pi alike).  NC = 2: float2 field, NC = 1: float.
+template <int Q, int NC>
+__global__ __launch_bounds__(256) void k_fill(float *__restrict__ X, const int *__restrict__ list, int n,
+                                              const uint8_t *__restrict__ mask, Geom G) {
+  using V = VSet<Q>;
+  int k = blockIdx.x * blockDim.x + threadIdx.x;
+  if (k >= n) return;
+  int s = list[k];
+  int x = s % G.ex;
+  int r = s / G.ex;
+  int y = r % G.ey;
+  int z = r / G.ey;
+  float num0 = 0.0f, num1 = 0.0f, den = 0.0f;
+#pragma unroll
+  for (int i = 1; i < Q; ++i) {
+    int xn = x + V::cx(i), yn = y + V::cy(i), zn = z + V::cz(i);
+    if (G.per[0]) xn = wrap(xn, G.ex); else if (xn < 0 || xn >= G.ex) continue;
+    if (G.per[1]) yn = wrap(yn, G.ey); else if (yn < 0 || yn >= G.ey) continue;
+    if (V::D == 3) {
+      if (G.per[2]) zn = wrap(zn, G.ez); else if (zn < 0 || zn >= G.ez) continue;
+    }
+    long long n2 = (long long)xn + (long long)G.ex * ((long long)yn + (long long)G.ey * zn);
+    if (mask[n2] != CELL_FLUID) continue;
+    float w = V::w(i);
+    num0 += w * X[NC * n2];
+    if (NC == 2) num1 += w * X[NC * n2 + 1];
+    den += w;
+  }
+  float inv = den > 0.0f ? 1.0f / den : 0.0f;
+  X[NC * (long long)s] = num0 * inv;
+  if (NC == 2) X[NC * (long long)s + 1] = num1 * inv;
+}
+
+template <int Q>
+__device__ __forceinline__ void laplacians(const float2 *__restrict__ M, const int *nb, float2 m0,
+                                           float &lr, float &lp) {
+  using V = VSet<Q>;
+  float ar = 0.0f, ap = 0.0f;
+#pragma unroll
+  for (int i = 1; i < Q; ++i) {
+    float2 m = M[nb[i]];
+    ar += V::w(i) * (m.x - m0.x);
+    ap += V::w(i) * (m.y - m0.y);
+  }
+  lr = 6.0f * ar;  // 2 / cs^2
+  lp = 6.0f * ap;
+}
+
+template <int Q>
+__global__ __launch_bounds__(BX *BY) void k_potential(const float2 *__restrict__ M,
+                                                      const uint8_t *__restrict__ mask,
+                                                      float2 *__restrict__ MU, float *__restrict__ PI,
+                                                      Geom G, Phys P) {
+  int x, y, z;
+  long long c;
+  if (!cell_of_thread(G, x, y, z, c)) return;
+  if (mask[c] != CELL_FLUID) return;
+  int nb[Q];
+  neighbours<Q>(G, x, y, z, nb);
+  float2 m0 = M[c];
+  float lr, lp;
+  laplacians<Q>(M, nb, m0, lr, lp);
+  float mr, mp;
+  chem_pot(P, m0.x, m0.y, lr, lp, mr, mp);
+  MU[c] = make_float2(mr, mp);
+  PI[c] = (1.0f + m0.x) * mr + m0.y * mp;
+}
+
+// Force of eq. (F) in product-rule form:
+//   -rho grad mu_rho - phi grad mu_phi
+//     = mu_rho grad rho + mu_phi grad phi - grad(rho mu_rho + phi mu_phi),
+// gradients by the lattice stencil (1/cs^2) sum_i w_i c_i X(x + c_i).
+template <int Q>
+__device__ __forceinline__ void force(const float2 *__restrict__ M, const float *__restrict__ PI,
+                                      const int *nb, float2 mu, float F[3]) {
+  using V = VSet<Q>;
+  float gr[3] = {0, 0, 0}, gp[3] = {0, 0, 0}, gq[3] = {0, 0, 0};
+#pragma unroll
+  for (int i = 1; i < Q; ++i) {
+    float2 m = M[nb[i]];
+    float pi = PI[nb[i]];
+    float w = 3.0f * V::w(i);
+    if (V::cx(i)) { gr[0] += V::cx(i) * w * m.x; gp[0] += V::cx(i) * w * m.y; gq[0] += V::cx(i) * w * pi; }
+    if (V::cy(i)) { gr[1] += V::cy(i) * w * m.x; gp[1] += V::cy(i) * w * m.y; gq[1] += V::cy(i) * w * pi; }
+    if (V::cz(i)) { gr[2] += V::cz(i) * w * m.x; gp[2] += V::cz(i) * w * m.y; gq[2] += V::cz(i) * w * pi; }
+  }
+#pragma unroll
+  for (int a = 0; a < 3; ++a) F[a] = mu.x * gr[a] + mu.y * gp[a] - gq[a];
+}
+
+template <int Q, int S>
+__global__ __launch_bounds__(BX *BY) void k_collide(Pops<S> P, const uint8_t *__restrict__ mask,
+                                                    const float2 *__restrict__ M,
+                                                    const float2 *__restrict__ MU,
+                                                    const float *__restrict__ PI, Geom G, Phys ph,
+                                                    int odd) {
+  using V = VSet<Q>;
+  int x, y, z;
+  long long c;
+  if (!cell_of_thread(G, x, y, z, c)) return;
+  if (mask[c] != CELL_FLUID) return;
+  int nb[Q];
+  neighbours<Q>(G, x, y, z, nb);
+  float df[Q], g[Q];
+  load_pops<Q, S>(P, nb, c, odd, df, g);
+
+  // zeroth and first moments (df_i = f_i - w_i; sum w_i = 1, sum w_i c_i = 0)
+  float drho = 0.0f, phi = 0.0f, j[3] = {0, 0, 0};
+#pragma unroll
+  for (int i = 0; i < Q; ++i) {
+    drho += df[i];
+    phi += g[i];
+    j[0] += V::cx(i) * df[i];
+    j[1] += V::cy(i) * df[i];
+    j[2] += V::cz(i) * df[i];
+  }
+  float rho = 1.0f + drho;
+  float F[3];
+  force<Q>(M, PI, nb, MU[c], F);
+  float mu_phi = MU[c].y;
+  float inv_rho = 1.0f / rho;
+  float u[3] = {(j[0] + 0.5f * F[0]) * inv_rho, (j[1] + 0.5f * F[1]) * inv_rho,
+                (j[2] + 0.5f * F[2]) * inv_rho};
+  float uu = u[0] * u[0] + u[1] * u[1] + u[2] * u[2];
+  float uF = u[0] * F[0] + u[1] * F[1] + u[2] * F[2];
+
+  // collision (eqs. bgk, feq, Fi for f; LBEg, geq for g)
+  float fs[Q], gs[Q];
+  float geq_rest = 0.0f;
+#pragma unroll
+  for (int i = 0; i < Q; ++i) {
+    float cu = V::cx(i) * u[0] + V::cy(i) * u[1] + V::cz(i) * u[2];
+    float cF = V::cx(i) * F[0] + V::cy(i) * F[1] + V::cz(i) * F[2];
+    float wi = V::w(i);
+    float poly = 3.0f * cu + 4.5f * cu * cu - 1.5f * uu;
+    float dfeq = wi * (drho + rho * poly);                       // f_i^eq - w_i
+    float src = ph.guo * wi * (3.0f * (cF - uF) + 9.0f * cu * cF);  // Guo term
+    fs[i] = df[i] + ph.om_f * (dfeq - df[i]) + src;
+    if (i > 0) {
+      float geq = wi * (ph.gam3 * mu_phi + phi * poly);
+      geq_rest += geq;
+      gs[i] = g[i] + ph.om_g * (geq - g[i]);
+    }
+  }
+  gs[0] = g[0] + ph.om_g * ((phi - geq_rest) - g[0]);
+
+  // streaming with moving halfway bounce-back (AA in place)
+#pragma unroll
+  for (int i = 0; i < Q; ++i) {
+    long long n = nb[i];
+    uint8_t code = i == 0 ? CELL_FLUID : mask[n];
+    if (code == CELL_FLUID) {
+      if (!odd) { P.stf(opp(i), c, fs[i]); P.stg(opp(i), c, gs[i]); }
+      else { P.stf(i, n, fs[i]); P.stg(i, n, gs[i]); }
+    } else {
+      int xs = wrap(x + V::cx(i), G.ex), ys = wrap(y + V::cy(i), G.ey);
+      int zs = V::D == 3 ? wrap(z + V::cz(i), G.ez) : z;
+      float uw[3];
+      body_velocity<V>(G, ph, code, x, y, z, xs, ys, zs, i, uw);
+      float cw = V::cx(i) * uw[0] + V::cy(i) * uw[1] + V::cz(i) * uw[2];
+      float k = 6.0f * V::w(i) * cw;  // 2 w_i (c_i . u_w) / cs^2
+      float fb = fs[i] - k * rho, gb = gs[i] - k * phi;
+      // f_opp(i)(x, t+1): read next step from slot (x + c_i, i) after an
+      // even step, from slot (x, opp(i)) after an odd step
+      if (!odd) { P.stf(i, n, fb); P.stg(i, n, gb); }
+      else { P.stf(opp(i), c, fb); P.stg(opp(i), c, gb); }
+    }
+  }
+}
+
+// Initialisation at equilibrium (Sec. 2.3).  M holds (rho0 - 1, phi0) with
+// solid cells filled; U0 holds u0.  Writes the parity-0 layout.
+template <int Q, int S>
+__global__ __launch_bounds__(BX *BY) void k_init(Pops<S> P, const uint8_t *__restrict__ mask,
+                                                 const float2 *__restrict__ M,
+                                                 const float4 *__restrict__ U0, Geom G, Phys ph) {
+  using V = VSet<Q>;
+  int x, y, z;
+  long long c;
+  if (!cell_of_thread(G, x, y, z, c)) return;
+  if (mask[c] != CELL_FLUID) return;
+  int nb[Q];
+  neighbours<Q>(G, x, y, z, nb);
+  float2 m0 = M[c];
+  float lr, lp, mr, mp;
+  laplacians<Q>(M, nb, m0, lr, lp);
+  chem_pot(ph, m0.x, m0.y, lr, lp, mr, mp);
+  float4 u4 = U0[c];
+  float u[3] = {u4.x, u4.y, u4.z};
+  float uu = u[0] * u[0] + u[1] * u[1] + u[2] * u[2];
+  float drho = m0.x, rho = 1.0f + drho, phi = m0.y;
+  float rest = 0.0f;
+#pragma unroll
+  for (int i = 0; i < Q; ++i) {
+    float cu = V::cx(i) * u[0] + V::cy(i) * u[1] + V::cz(i) * u[2];
+    float poly = 3.0f * cu + 4.5f * cu * cu - 1.5f * uu;
+    P.stf(i, c, V::w(i) * (drho + rho * poly));
+    if (i > 0) {
+      float geq = V::w(i) * (ph.gam3 * mp + phi * poly);
+      rest += geq;
+      P.stg(i, c, geq);
+    }
+  }
+  P.stg(0, c, phi - rest);
+}
+
+// Observables (u with F/2, bulk pressure) at the current time; M, MU, PI
+// must be current.  OUT[c] = (ux, uy, uz, P).
+template <int Q, int S>
+__global__ __launch_bounds__(BX *BY) void k_observe(Pops<S> P, const uint8_t *__restrict__ mask,
+                                                    const float2 *__restrict__ M,
+                                                    const float2 *__restrict__ MU,
+                                                    const float *__restrict__ PI,
+                                                    float4 *__restrict__ OUT, Geom G, Phys ph, int odd) {
+  using V = VSet<Q>;
+  int x, y, z;
+  long long c;
+  if (!cell_of_thread(G, x, y, z, c)) return;
+  if (mask[c] != CELL_FLUID) {
+    OUT[c] = make_float4(0, 0, 0, 0);
+    return;
+  }
+  int nb[Q];
+  neighbours<Q>(G, x, y, z, nb);
+  float df[Q], g[Q];
+  load_pops<Q, S>(P, nb, c, odd, df, g);
+  float j[3] = {0, 0, 0};
+#pragma unroll
+  for (int i = 0; i < Q; ++i) {
+    j[0] += V::cx(i) * df[i];
+    j[1] += V::cy(i) * df[i];
+    j[2] += V::cz(i) * df[i];
+  }
+  float2 m0 = M[c];
+  float2 mu = MU[c];
+  float F[3];
+  force<Q>(M, PI, nb, mu, F);
+  float rho = 1.0f + m0.x;
+  float inv = 1.0f / rho;
+  float pres = rho / 3.0f + rho * mu.x + m0.y * mu.y - psi_bulk(ph, rho, m0.y);
+  OUT[c] = make_float4((j[0] + 0.5f * F[0]) * inv, (j[1] + 0.5f * F[1]) * inv,
+                       (j[2] + 0.5f * F[2]) * inv, pres);
+}
+
+// Unshifted populations in the natural layout, [2q][ncell] floats.
+template <int Q, int S>
+__global__ __launch_bounds__(BX *BY) void k_read_pops(Pops<S> P, const uint8_t *__restrict__ mask,
+                                                      float *__restrict__ out, Geom G, int odd) {
+  using V = VSet<Q>;
+  int x, y, z;
+  long long c;
+  if (!cell_of_thread(G, x, y, z, c)) return;
+  if (mask[c] != CELL_FLUID) {
+    for (int i = 0; i < 2 * Q; ++i) out[i * G.ncell + c] = 0.0f;
+    return;
+  }
+  int nb[Q];
+  neighbours<Q>(G, x, y, z, nb);
+  float df[Q], g[Q];
+  load_pops<Q, S>(P, nb, c, odd, df, g);
+#pragma unroll
+  for (int i = 0; i < Q; ++i) {
+    out[i * G.ncell + c] = df[i] + V::w(i);
+    out[(Q + i) * G.ncell + c] = g[i];
+  }
+}
+
+// Global sums over fluid cells: compensated FP32 per thread, FP64 across the
+// block; one partial per block (summed on the host in FP64).
+// part[b*8 + k]: k = 0 sum(rho-1), 1 sum phi, 2 sum |phi|, 3..5 sum rho u,
+// 6 non-finite count, 7 fluid count.
+__device__ __forceinline__ void kahan(float &s, float &comp, float v) {
+  float y = v - comp;
+  float t = s + y;
+  comp = (t - s) - y;
+  s = t;
+}
+
+__global__ __launch_bounds__(256) void k_reduce(const float2 *__restrict__ M, const float4 *__restrict__ OUT,
+                                                const uint8_t *__restrict__ mask, long long ncell,
+                                                double *__restrict__ part) {
+  float s[6] = {0, 0, 0, 0, 0, 0}, e[6] = {0, 0, 0, 0, 0, 0};
+  unsigned bad = 0, nfl = 0;
+  for (long long c = (long long)blockIdx.x * blockDim.x + threadIdx.x; c < ncell;
+       c += (long long)gridDim.x * blockDim.x) {
+    if (mask[c] != CELL_FLUID) continue;
+    float2 m = M[c];
+    float4 o = OUT[c];
+    float rho = 1.0f + m.x;
+    float v[6] = {m.x, m.y, fabsf(m.y), rho * o.x, rho * o.y, rho * o.z};
+    bool fin = isfinite(m.x) && isfinite(m.y) && isfinite(o.x) && isfinite(o.y) && isfinite(o.z);
+    bad += fin ? 0u : 1u;
+    ++nfl;
+    if (fin)
+#pragma unroll
+      for (int k = 0; k < 6; ++k) kahan(s[k], e[k], v[k]);
+  }
+  __shared__ double red[8][256];
+  for (int k = 0; k < 6; ++k) red[k][threadIdx.x] = (double)s[k] - (double)e[k];
+  red[6][threadIdx.x] = (double)bad;
+  red[7][threadIdx.x] = (double)nfl;
+  __syncthreads();
+  for (int w = blockDim.x / 2; w > 0; w >>= 1) {
+    if ((int)threadIdx.x < w)
+      for (int k = 0; k < 8; ++k) red[k][threadIdx.x] += red[k][threadIdx.x + w];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0)
+    for (int k = 0; k < 8; ++k) part[blockIdx.x * 8 + k] = red[k][0];
+}
+
+// ---------------------------------------------------------------------------
+// host launchers
+// ---------------------------------------------------------------------------
+static dim3 cell_grid(const Geom &G) { return dim3((G.ex + BX - 1) / BX, (G.ey + BY - 1) / BY, G.ez); }
+static dim3 cell_block() { return dim3(BX, BY, 1); }
+
+template <int Q, int S>
+static void step_impl(const LaunchArgs &a, int odd) {
+  Pops<S> P = make_pops<S>(a);
+  dim3 gr = cell_grid(a.G), bl = cell_block();
+  k_moments<Q, S><<<gr, bl, 0, a.stream>>>(P, a.mask, a.M, a.G, odd);
+  if (a.n_fill) k_fill<Q, 2><<<(a.n_fill + 255) / 256, 256, 0, a.stream>>>((float *)a.M, a.fill_list, a.n_fill, a.mask, a.G);
+  k_potential<Q><<<gr, bl, 0, a.stream>>>(a.M, a.mask, a.MU, a.PI, a.G, a.ph);
+  if (a.n_fill) k_fill<Q, 1><<<(a.n_fill + 255) / 256, 256, 0, a.stream>>>(a.PI, a.fill_list, a.n_fill, a.mask, a.G);
+  k_collide<Q, S><<<gr, bl, 0, a.stream>>>(P, a.mask, a.M, a.MU, a.PI, a.G, a.ph, odd);
+}
+
+// The same five launches as step_impl, each bracketed by events on the
+// stream (ev[k] before launch k, ev[5] after the last).
+template <int Q, int S>
+static void step_events_impl(const LaunchArgs &a, int odd, hipEvent_t *ev) {
+  Pops<S> P = make_pops<S>(a);
+  dim3 gr = cell_grid(a.G), bl = cell_block();
+  (void)hipEventRecord(ev[0], a.stream);
+  k_moments<Q, S><<<gr, bl, 0, a.stream>>>(P, a.mask, a.M, a.G, odd);
+  (void)hipEventRecord(ev[1], a.stream);
+  if (a.n_fill) k_fill<Q, 2><<<(a.n_fill + 255) / 256, 256, 0, a.stream>>>((float *)a.M, a.fill_list, a.n_fill, a.mask, a.G);
+  (void)hipEventRecord(ev[2], a.stream);
+  k_potential<Q><<<gr, bl, 0, a.stream>>>(a.M, a.mask, a.MU, a.PI, a.G, a.ph);
+  (void)hipEventRecord(ev[3], a.stream);
+  if (a.n_fill) k_fill<Q, 1><<<(a.n_fill + 255) / 256, 256, 0, a.stream>>>(a.PI, a.fill_list, a.n_fill, a.mask, a.G);
+  (void)hipEventRecord(ev[4], a.stream);
+  k_collide<Q, S><<<gr, bl, 0, a.stream>>>(P, a.mask, a.M, a.MU, a.PI, a.G, a.ph, odd);
+  (void)hipEventRecord(ev[5], a.stream);
+}
+
+template <int Q, int S>
+static void observe_impl(const LaunchArgs &a, int odd) {
+  Pops<S> P = make_pops<S>(a);
+  dim3 gr = cell_grid(a.G), bl = cell_block();
+  k_moments<Q, S><<<gr, bl, 0, a.stream>>>(P, a.mask, a.M, a.G, odd);
+  if (a.n_fill) k_fill<Q, 2><<<(a.n_fill + 255) / 256, 256, 0, a.stream>>>((float *)a.M, a.fill_list, a.n_fill, a.mask, a.G);
+  k_potential<Q><<<gr, bl, 0, a.stream>>>(a.M, a.mask, a.MU, a.PI, a.G, a.ph);
+  if (a.n_fill) k_fill<Q, 1><<<(a.n_fill + 255) / 256, 256, 0, a.stream>>>(a.PI, a.fill_list, a.n_fill, a.mask, a.G);
+  k_observe<Q, S><<<gr, bl, 0, a.stream>>>(P, a.mask, a.M, a.MU, a.PI, a.AUX, a.G, a.ph, odd);
+}
+
+template <int Q, int S>
+static void init_impl(const LaunchArgs &a) {
+  Pops<S> P = make_pops<S>(a);
+  if (a.n_fill) k_fill<Q, 2><<<(a.n_fill + 255) / 256, 256, 0, a.stream>>>((float *)a.M, a.fill_list, a.n_fill, a.mask, a.G);
+  k_init<Q, S><<<cell_grid(a.G), cell_block(), 0, a.stream>>>(P, a.mask, a.M, a.AUX, a.G, a.ph);
+}
+
+template <int Q, int S>
+static void read_pops_impl(const LaunchArgs &a, int odd, float *out) {
+  k_read_pops<Q, S><<<cell_grid(a.G), cell_block(), 0, a.stream>>>(make_pops<S>(a), a.mask, out, a.G, odd);
+}
+
+#define FRE_DISPATCH(fn, ...)                                   \
+  do {                                                          \
+    if (a.q == 9 && a.storage == 0) fn<9, 0>(__VA_ARGS__);      \
+    else if (a.q == 9) fn<9, 1>(__VA_ARGS__);                   \
+    else if (a.storage == 0) fn<19, 0>(__VA_ARGS__);            \
+    else fn<19, 1>(__VA_ARGS__);                                \
+  } while (0)
+
+void launch_step(const LaunchArgs &a, int odd) { FRE_DISPATCH(step_impl, a, odd); }
+void launch_step_events(const LaunchArgs &a, int odd, hipEvent_t *ev) { FRE_DISPATCH(step_events_impl, a, odd, ev); }
+int step_kernel_count() { return 5; }
+const char *step_kernel_name(int k) {
+  static const char *names[5] = {"k_moments", "k_fill_moments", "k_potential", "k_fill_pi", "k_collide"};
+  return (k >= 0 && k < 5) ? names[k] : nullptr;
+}
+void launch_observe(const LaunchArgs &a, int odd) { FRE_DISPATCH(observe_impl, a, odd); }
+void launch_init(const LaunchArgs &a) { FRE_DISPATCH(init_impl, a); }
+void launch_read_pops(const LaunchArgs &a, int odd, float *out) { FRE_DISPATCH(read_pops_impl, a, odd, out); }
+
+int reduce_blocks() { return 1024; }
+void launch_reduce(const LaunchArgs &a, double *part) {
+  k_reduce<<<reduce_blocks(), 256, 0, a.stream>>>(a.M, a.AUX, a.mask, a.G.ncell, part);
+}
+
+}  // namespace frelbm

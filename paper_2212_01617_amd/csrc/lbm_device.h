@@ -1,0 +1,195 @@
+// lbm_device.h -- compile-time velocity sets and per-node arithmetic of the
+// free-energy LBM step (Simonis et al., arXiv 2212.01617, Sec. 2.2 and
+// Algorithm 1), FP32, for the HIP kernels of this library.
+//
+// Populations of f are kept shifted by their lattice weights, df_i = f_i - w_i,
+// so that FP32 (and FP16) storage carries only the deviation from rest.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <hip/hip_fp16.h>
+#include <stdint.h>
+
+namespace frelbm {
+
+// ---------------------------------------------------------------------------
+// Velocity sets: rest direction first, then opposite pairs side by side
+// (opposite of i is i+1 for odd i, i-1 for even i > 0); cs^2 = 1/3.
+// ---------------------------------------------------------------------------
+template <int Q> struct VSet;
+
+template <> struct VSet<9> {
+  static constexpr int D = 2;
+  __host__ __device__ static constexpr int cx(int i) {
+    return (i == 1 || i == 5 || i == 7) ? 1 : (i == 2 || i == 6 || i == 8) ? -1 : 0;
+  }
+  __host__ __device__ static constexpr int cy(int i) {
+    return (i == 3 || i == 5 || i == 8) ? 1 : (i == 4 || i == 6 || i == 7) ? -1 : 0;
+  }
+  __host__ __device__ static constexpr int cz(int) { return 0; }
+  __host__ __device__ static constexpr float w(int i) {
+    return i == 0 ? 4.0f / 9.0f : (i < 5 ? 1.0f / 9.0f : 1.0f / 36.0f);
+  }
+};
+
+template <> struct VSet<19> {
+  static constexpr int D = 3;
+  // directions 1..6 are the axes, 7..10 the xy diagonals, 11..14 the xz
+  // diagonals, 15..18 the yz diagonals
+  __host__ __device__ static constexpr int cx(int i) {
+    return (i == 1 || i == 7 || i == 9 || i == 11 || i == 13)    ? 1
+           : (i == 2 || i == 8 || i == 10 || i == 12 || i == 14) ? -1
+                                                                 : 0;
+  }
+  __host__ __device__ static constexpr int cy(int i) {
+    return (i == 3 || i == 7 || i == 10 || i == 15 || i == 17)   ? 1
+           : (i == 4 || i == 8 || i == 9 || i == 16 || i == 18)  ? -1
+                                                                 : 0;
+  }
+  __host__ __device__ static constexpr int cz(int i) {
+    return (i == 5 || i == 11 || i == 14 || i == 15 || i == 18)  ? 1
+           : (i == 6 || i == 12 || i == 13 || i == 16 || i == 17) ? -1
+                                                                  : 0;
+  }
+  __host__ __device__ static constexpr float w(int i) {
+    return i == 0 ? 1.0f / 3.0f : (i < 7 ? 1.0f / 18.0f : 1.0f / 36.0f);
+  }
+};
+
+__host__ __device__ constexpr int opp(int i) { return i == 0 ? 0 : ((i & 1) ? i + 1 : i - 1); }
+
+// ---------------------------------------------------------------------------
+// Geometry of one lattice in device memory.  The storage grid is the fluid
+// domain plus one ghost layer at both ends of every wall axis; a cell index is
+// x + ex*(y + ey*z) and population i of cell c lives at i*np + c.
+// ---------------------------------------------------------------------------
+enum : uint8_t { CELL_FLUID = 0, CELL_SOLID = 1, CELL_ROLLER0 = 2, CELL_GHOST = 8 };
+
+struct Geom {
+  int ex, ey, ez;   // storage grid
+  int per[3];       // 1 if the axis is periodic
+  int off[3];       // ghost offset (1 on wall axes)
+  long long np;     // stride between direction planes (elements)
+  long long ncell;  // ex*ey*ez
+};
+
+struct Phys {
+  float k1, k2;       // kappa1, kappa2
+  float a2q;          // alpha^2 / 4
+  float om_f, om_g;   // 1/tau_f, 1/tau_g
+  float guo;          // 1 - 1/(2 tau_f)
+  float gam3;         // Gamma / cs^2 = 3 Gamma
+  float wall_u[3][2][3];
+  int n_rollers;
+  float rc[4][3];
+  float rom[4];
+  int rax[4];
+};
+
+__device__ __forceinline__ int wrap(int v, int n) { return v < 0 ? v + n : (v >= n ? v - n : v); }
+
+// Neighbour of a fluid cell: every wall axis has a ghost layer, so only the
+// periodic wrap is needed.
+template <class V>
+__device__ __forceinline__ int nb_fluid(const Geom &G, int x, int y, int z, int i) {
+  int xn = wrap(x + V::cx(i), G.ex);
+  int yn = wrap(y + V::cy(i), G.ey);
+  int zn = V::D == 3 ? wrap(z + V::cz(i), G.ez) : z;
+  return xn + G.ex * (yn + G.ey * zn);
+}
+
+// ---------------------------------------------------------------------------
+// Population storage.  S = 0: FP32 for f and g.  S = 1: f as half, g_0 as
+// float, g_1.. as half (round to nearest even).
+// ---------------------------------------------------------------------------
+template <int S> struct Pops;
+
+template <> struct Pops<0> {
+  float *f, *g;
+  long long np;
+  __device__ __forceinline__ float ldf(int i, long long c) const { return f[i * np + c]; }
+  __device__ __forceinline__ float ldg(int i, long long c) const { return g[i * np + c]; }
+  __device__ __forceinline__ void stf(int i, long long c, float v) const { f[i * np + c] = v; }
+  __device__ __forceinline__ void stg(int i, long long c, float v) const { g[i * np + c] = v; }
+};
+
+template <> struct Pops<1> {
+  __half *f, *g;  // g holds directions 1..q-1 at (i-1)*np
+  float *g0;
+  long long np;
+  __device__ __forceinline__ float ldf(int i, long long c) const { return __half2float(f[i * np + c]); }
+  __device__ __forceinline__ float ldg(int i, long long c) const {
+    return i == 0 ? g0[c] : __half2float(g[(i - 1) * np + c]);
+  }
+  __device__ __forceinline__ void stf(int i, long long c, float v) const { f[i * np + c] = __float2half_rn(v); }
+  __device__ __forceinline__ void stg(int i, long long c, float v) const {
+    if (i == 0) g0[c] = v; else g[(i - 1) * np + c] = __float2half_rn(v);
+  }
+};
+
+// ---------------------------------------------------------------------------
+// Per-node formulas
+// ---------------------------------------------------------------------------
+
+// Bulk chemical-potential polynomial of eqs. (mu_rho, mu_phi):
+// s (s-1) (s-2) with s = 1 + a, written as a (a-1) (a+1) for accuracy near
+// the bulk values a = 0, +-1.
+__device__ __forceinline__ float cubic_shifted(float a) { return a * (a - 1.0f) * (a + 1.0f); }
+
+// mu_rho, mu_phi of eqs. (mu_rho, mu_phi) from drho = rho - 1, phi and the
+// Laplacians of rho and phi.
+__device__ __forceinline__ void chem_pot(const Phys &P, float drho, float phi, float lap_rho,
+                                         float lap_phi, float &mu_rho, float &mu_phi) {
+  float ps = cubic_shifted(drho + phi);  // rho + phi = 1 + (drho + phi)
+  float pt = cubic_shifted(drho - phi);  // rho - phi = 1 + (drho - phi)
+  float bs = 0.125f * P.k1 * ps, bt = 0.125f * P.k2 * pt;
+  float ksum = P.k1 + P.k2, kdif = P.k2 - P.k1;
+  mu_rho = bs + bt + P.a2q * (kdif * lap_phi - ksum * lap_rho);
+  mu_phi = bs - bt + P.a2q * (kdif * lap_rho - ksum * lap_phi);
+}
+
+// Bulk free-energy density of eq. (functional) without gradient terms.
+__device__ __forceinline__ float psi_bulk(const Phys &P, float rho, float phi) {
+  float s = rho + phi, t = rho - phi;
+  return 0.03125f * (P.k1 * s * s * (s - 2.0f) * (s - 2.0f) + P.k2 * t * t * (t - 2.0f) * (t - 2.0f));
+}
+
+// Velocity of the solid body owning cell (xs, ys, zs) at the midpoint of the
+// link from fluid cell (x, y, z) along direction i (halfway bounce-back).
+template <class V>
+__device__ __forceinline__ void body_velocity(const Geom &G, const Phys &P, uint8_t code, int x,
+                                              int y, int z, int xs, int ys, int zs, int i,
+                                              float uw[3]) {
+  uw[0] = uw[1] = uw[2] = 0.0f;
+  if (code == CELL_GHOST) {
+    const int sc[3] = {xs, ys, zs};
+    const int ext[3] = {G.ex, G.ey, G.ez};
+    int n = 0;
+#pragma unroll
+    for (int a = 0; a < 3; ++a) {
+      if (G.per[a]) continue;
+      int side = sc[a] == 0 ? 0 : (sc[a] == ext[a] - 1 ? 1 : -1);
+      if (side < 0) continue;
+      uw[0] += P.wall_u[a][side][0];
+      uw[1] += P.wall_u[a][side][1];
+      uw[2] += P.wall_u[a][side][2];
+      ++n;
+    }
+    if (n > 1) {
+      float inv = 1.0f / (float)n;
+      uw[0] *= inv; uw[1] *= inv; uw[2] *= inv;
+    }
+    return;
+  }
+  int r = (int)code - CELL_ROLLER0;
+  if (r < 0 || r >= P.n_rollers) return;
+  float d0 = (float)(x - G.off[0]) + 0.5f * V::cx(i) - P.rc[r][0];
+  float d1 = (float)(y - G.off[1]) + 0.5f * V::cy(i) - P.rc[r][1];
+  float d2 = (float)(z - G.off[2]) + 0.5f * V::cz(i) - P.rc[r][2];
+  float om = P.rom[r];
+  if (P.rax[r] == 0) { uw[1] = -om * d2; uw[2] = om * d1; }
+  else if (P.rax[r] == 1) { uw[0] = om * d2; uw[2] = -om * d0; }
+  else { uw[0] = -om * d1; uw[1] = om * d0; }
+}
+
+}  // namespace frelbm

@@ -1,0 +1,242 @@
+"""ctypes binding of the C ABI in ``include/frelbm.h`` (argument marshalling
+only: every step of the method runs in the HIP kernels of libfrelbm.so).
+
+The functions keep the C names.  ``Lattice`` is a small convenience wrapper
+that allocates the device buffer as a torch uint8 tensor and passes the torch
+stream; it does no arithmetic of the method.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libfrelbm.so")
+
+FRE_OK, FRE_EINVAL, FRE_ENOMEM, FRE_EDEVICE, FRE_ESTATE, FRE_ENUMERIC = 0, -1, -2, -3, -4, -5
+FRE_D2Q9, FRE_D3Q19 = 0, 1
+FRE_FP32, FRE_FP16 = 0, 1
+FRE_PERIODIC, FRE_WALL = 0, 1
+FRE_F_RHO, FRE_F_PHI, FRE_F_U, FRE_F_MU_RHO, FRE_F_MU_PHI, FRE_F_P = 1, 2, 4, 8, 16, 32
+FIELDS = (("rho", FRE_F_RHO), ("phi", FRE_F_PHI), ("u", FRE_F_U),
+          ("mu_rho", FRE_F_MU_RHO), ("mu_phi", FRE_F_MU_PHI), ("P", FRE_F_P))
+
+
+class FreError(RuntimeError):
+    def __init__(self, status, msg):
+        super().__init__(f"frelbm status {status}: {msg}")
+        self.status = status
+
+
+class fre_roller(C.Structure):
+    _fields_ = [("center", C.c_double * 3), ("radius", C.c_double), ("omega", C.c_double),
+                ("axis", C.c_int32), ("reserved", C.c_int32)]
+
+
+class fre_params(C.Structure):
+    _fields_ = [
+        ("kind", C.c_int32), ("nx", C.c_int32), ("ny", C.c_int32), ("nz", C.c_int32),
+        ("storage", C.c_int32), ("bc", C.c_int32 * 3),
+        ("wall_u", ((C.c_double * 3) * 2) * 3),
+        ("n_rollers", C.c_int32), ("reserved0", C.c_int32),
+        ("rollers", fre_roller * 4),
+        ("A", C.c_double), ("kappa", C.c_double),
+        ("kappa1", C.c_double), ("kappa2", C.c_double), ("alpha", C.c_double),
+        ("use_paper_form", C.c_int32), ("reserved1", C.c_int32),
+        ("tau_f", C.c_double), ("tau_g", C.c_double), ("M", C.c_double),
+    ]
+
+
+_lib = None
+
+# (name, restype, argtypes)
+_SIGS = [
+    ("fre_footprint", C.c_int32, [C.POINTER(fre_params), C.POINTER(C.c_size_t)]),
+    ("fre_lattice_init", C.c_int32, [C.POINTER(fre_params), C.c_void_p, C.c_size_t, C.c_void_p,
+                                     C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p,
+                                     C.POINTER(C.c_void_p)]),
+    ("fre_set_params", C.c_int32, [C.c_void_p, C.POINTER(fre_params)]),
+    ("fre_step", C.c_int32, [C.c_void_p, C.c_int64]),
+    ("fre_read_moments", C.c_int32, [C.c_void_p, C.c_uint32, C.c_void_p, C.c_size_t]),
+    ("fre_read_populations", C.c_int32, [C.c_void_p, C.c_void_p, C.c_void_p, C.c_size_t]),
+    ("fre_reduce", C.c_int32, [C.c_void_p, C.c_void_p]),
+    ("fre_info", C.c_int32, [C.c_void_p, C.POINTER(C.c_int64), C.POINTER(C.c_int32)]),
+    ("fre_state_bytes", C.c_int32, [C.c_void_p, C.POINTER(C.c_size_t)]),
+    ("fre_save", C.c_int32, [C.c_void_p, C.c_void_p, C.c_size_t]),
+    ("fre_load", C.c_int32, [C.c_void_p, C.c_void_p, C.c_size_t]),
+    ("fre_profile_step", C.c_int32, [C.c_void_p, C.c_int64, C.c_void_p, C.c_int32,
+                                     C.POINTER(C.c_int32)]),
+    ("fre_kernel_name", C.c_char_p, [C.c_int32]),
+    ("fre_lattice_destroy", None, [C.c_void_p]),
+    ("fre_last_error", C.c_char_p, []),
+]
+
+
+def lib():
+    """Load libfrelbm.so; fails loudly if it has not been built."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise ImportError(f"{LIB_PATH} is missing: build it with `python -m paper_2212_01617_amd.build`")
+        L = C.CDLL(LIB_PATH)
+        for name, res, args in _SIGS:
+            fn = getattr(L, name)
+            fn.restype = res
+            fn.argtypes = args
+        _lib = L
+    return _lib
+
+
+def _check(status):
+    if status != FRE_OK:
+        raise FreError(status, lib().fre_last_error().decode())
+
+
+def _ptr(a: np.ndarray):
+    return a.ctypes.data_as(C.c_void_p)
+
+
+def make_params(kind, shape, *, storage=FRE_FP32, bc=(0, 0, 0), wall_u=None, rollers=(),
+                A=None, kappa=None, kappa1=None, kappa2=None, alpha=None,
+                tau_f=1.0, tau_g=1.0, M=0.1) -> fre_params:
+    """shape = (nx, ny, nz); rollers = [(center(3), omega, axis, radius)];
+    give either (A, kappa) or (kappa1, kappa2, alpha)."""
+    p = fre_params()
+    p.kind = kind
+    p.nx, p.ny, p.nz = shape
+    p.storage = storage
+    for a in range(3):
+        p.bc[a] = bc[a]
+    if wall_u is not None:
+        wu = np.asarray(wall_u, dtype=np.float64).reshape(3, 2, 3)
+        for a in range(3):
+            for s in range(2):
+                for b in range(3):
+                    p.wall_u[a][s][b] = wu[a, s, b]
+    p.n_rollers = len(rollers)
+    for k, r in enumerate(rollers):
+        cen, om, ax = r[0], r[1], r[2]
+        rad = r[3] if len(r) > 3 else 0.0
+        for a in range(3):
+            p.rollers[k].center[a] = cen[a]
+        p.rollers[k].omega = om
+        p.rollers[k].axis = ax
+        p.rollers[k].radius = rad
+    if kappa1 is not None:
+        p.use_paper_form = 1
+        p.kappa1, p.kappa2, p.alpha = kappa1, kappa2, alpha
+    else:
+        p.use_paper_form = 0
+        p.A, p.kappa = A, kappa
+    p.tau_f, p.tau_g, p.M = tau_f, tau_g, M
+    return p
+
+
+def footprint(p: fre_params) -> int:
+    n = C.c_size_t()
+    _check(lib().fre_footprint(C.byref(p), C.byref(n)))
+    return n.value
+
+
+class Lattice:
+    """A lattice in a torch-allocated device buffer, bound to a torch stream.
+    Host fields are numpy arrays shaped (nz, ny, nx)."""
+
+    def __init__(self, params: fre_params, phi0, rho0=None, u0=None, mask=None,
+                 device="cuda:0", stream=None):
+        import torch  # device memory and streams only
+        self.params = params
+        self.shape = (params.nz, params.ny, params.nx)
+        self.N = params.nx * params.ny * params.nz
+        self.q = 9 if params.kind == FRE_D2Q9 else 19
+        nbytes = footprint(params)
+        self.buf = torch.empty(nbytes + 256, dtype=torch.uint8, device=device)
+        off = (-self.buf.data_ptr()) % 256
+        self._base = self.buf.data_ptr() + off
+        self._nbytes = nbytes
+        self.stream = stream if stream is not None else torch.cuda.current_stream(device)
+        phi0 = np.ascontiguousarray(np.asarray(phi0, np.float64).reshape(-1))
+        rho0 = None if rho0 is None else np.ascontiguousarray(np.asarray(rho0, np.float64).reshape(-1))
+        u0 = None if u0 is None else np.ascontiguousarray(np.asarray(u0, np.float64).reshape(-1))
+        mask = None if mask is None else np.ascontiguousarray(np.asarray(mask, np.uint8).reshape(-1))
+        h = C.c_void_p()
+        _check(lib().fre_lattice_init(C.byref(params), C.c_void_p(self._base), nbytes,
+                                      C.c_void_p(self.stream.cuda_stream), _ptr(phi0),
+                                      None if rho0 is None else _ptr(rho0),
+                                      None if u0 is None else _ptr(u0),
+                                      None if mask is None else _ptr(mask), C.byref(h)))
+        self._h = h
+
+    def close(self):
+        if getattr(self, "_h", None):
+            lib().fre_lattice_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        self.close()
+
+    @property
+    def handle(self):
+        return self._h
+
+    def step(self, n=1):
+        _check(lib().fre_step(self._h, int(n)))
+        return self
+
+    def set_params(self, params: fre_params):
+        _check(lib().fre_set_params(self._h, C.byref(params)))
+        self.params = params
+
+    def read(self, fields=("rho", "phi", "u", "mu_rho", "mu_phi", "P")) -> dict:
+        mask = 0
+        for name, bit in FIELDS:
+            if name in fields:
+                mask |= bit
+        n = sum((3 if name == "u" else 1) * self.N for name, bit in FIELDS if mask & bit)
+        out = np.empty(n)
+        _check(lib().fre_read_moments(self._h, mask, _ptr(out), n))
+        res, o = {}, 0
+        for name, bit in FIELDS:
+            if mask & bit:
+                k = 3 if name == "u" else 1
+                a = out[o:o + k * self.N]
+                res[name] = a.reshape((3,) + self.shape) if k == 3 else a.reshape(self.shape)
+                o += k * self.N
+        return res
+
+    def populations(self):
+        f = np.empty(self.q * self.N)
+        g = np.empty(self.q * self.N)
+        _check(lib().fre_read_populations(self._h, _ptr(f), _ptr(g), self.q * self.N))
+        return f.reshape((self.q,) + self.shape), g.reshape((self.q,) + self.shape)
+
+    def reduce(self) -> np.ndarray:
+        out = np.zeros(8)
+        _check(lib().fre_reduce(self._h, _ptr(out)))
+        return out
+
+    def info(self):
+        t, s = C.c_int64(), C.c_int32()
+        _check(lib().fre_info(self._h, C.byref(t), C.byref(s)))
+        return t.value, s.value
+
+    def profile(self, n: int) -> dict:
+        """Mean per-step duration (ms) of each kernel of the step, from HIP
+        events recorded around every launch on this lattice's stream."""
+        ms = np.zeros(16)
+        k = C.c_int32()
+        _check(lib().fre_profile_step(self._h, int(n), _ptr(ms), 16, C.byref(k)))
+        return {lib().fre_kernel_name(i).decode(): float(ms[i]) for i in range(k.value)}
+
+    def save(self) -> bytes:
+        n = C.c_size_t()
+        _check(lib().fre_state_bytes(self._h, C.byref(n)))
+        buf = np.empty(n.value, np.uint8)
+        _check(lib().fre_save(self._h, _ptr(buf), n.value))
+        return buf.tobytes()
+
+    def load(self, blob: bytes):
+        buf = np.frombuffer(blob, np.uint8).copy()
+        _check(lib().fre_load(self._h, _ptr(buf), buf.size))
