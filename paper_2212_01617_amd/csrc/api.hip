@@ -51,8 +51,9 @@ struct Plan {
   int ext[3];
   int per[3];
   int off[3];
-  long long ncell, np;
-  size_t o_f, o_g, o_g0, o_mask, o_M, o_MU, o_PI, o_AUX, o_fill, o_part, total;
+  int px;          // row pitch: ext[0] rounded up to a multiple of 64
+  long long ncell;  // px * ext[1] * ext[2]
+  size_t o_f, o_g, o_g0, o_mask, o_nbm, o_M, o_C, o_MUP, o_AUX, o_fill, o_part, total;
 };
 
 fre_status validate(const fre_params *p) {
@@ -94,29 +95,29 @@ Plan make_plan(const fre_params *p) {
   Plan P{};
   P.q = p->kind == FRE_D2Q9 ? 9 : 19;
   int n[3] = {p->nx, p->ny, p->nz};
-  P.ncell = 1;
   for (int a = 0; a < 3; ++a) {
     P.per[a] = p->bc[a] == FRE_PERIODIC;
     P.off[a] = P.per[a] ? 0 : 1;
     P.ext[a] = n[a] + 2 * P.off[a];
-    P.ncell *= P.ext[a];
   }
-  P.np = (long long)align_up((size_t)P.ncell, 128);  // 256 B planes for half, 512 B for float
+  P.px = (int)align_up((size_t)P.ext[0], 64);
+  P.ncell = (long long)P.px * P.ext[1] * P.ext[2];  // a multiple of 64
   size_t es = p->storage == FRE_FP32 ? 4 : 2;
   size_t o = 0;
   auto take = [&](size_t bytes) { size_t at = o; o = align_up(o + bytes, kAlign); return at; };
-  P.o_f = take((size_t)P.q * P.np * es);
+  P.o_f = take((size_t)P.q * P.ncell * es);
   if (p->storage == FRE_FP32) {
-    P.o_g = take((size_t)P.q * P.np * 4);
+    P.o_g = take((size_t)P.q * P.ncell * 4);
     P.o_g0 = 0;
   } else {
-    P.o_g = take((size_t)(P.q - 1) * P.np * 2);
-    P.o_g0 = take((size_t)P.np * 4);
+    P.o_g = take((size_t)(P.q - 1) * P.ncell * 2);
+    P.o_g0 = take((size_t)P.ncell * 4);
   }
   P.o_mask = take((size_t)P.ncell);
+  P.o_nbm = take((size_t)P.ncell * 4);
   P.o_M = take((size_t)P.ncell * 8);
-  P.o_MU = take((size_t)P.ncell * 8);
-  P.o_PI = take((size_t)P.ncell * 4);
+  P.o_C = take((size_t)P.ncell * 16);
+  P.o_MUP = take((size_t)P.ncell * 4);
   P.o_AUX = take((size_t)P.ncell * 16);
   P.o_fill = take((size_t)P.ncell * 4);
   P.o_part = take((size_t)reduce_blocks() * 8 * sizeof(double));
@@ -175,13 +176,16 @@ void reset_graph(fre_lattice *L) {
 }
 
 long long ext_index(const Plan &P, int x, int y, int z) {
-  return (long long)(x + P.off[0]) + (long long)P.ext[0] * ((long long)(y + P.off[1]) + (long long)P.ext[1] * (z + P.off[2]));
+  return (long long)(x + P.off[0]) + (long long)P.px * ((long long)(y + P.off[1]) + (long long)P.ext[1] * (z + P.off[2]));
 }
 
-fre_status build_mask(fre_lattice *L, const uint8_t *user_mask, std::vector<uint8_t> &mask) {
+fre_status build_mask(fre_lattice *L, const uint8_t *user_mask, std::vector<uint8_t> &mask,
+                      std::vector<uint32_t> &nbm) {
   const Plan &P = L->plan;
   const fre_params &p = L->p;
   mask.assign((size_t)P.ncell, CELL_GHOST);
+  for (long long c = 0; c < P.ncell; ++c)
+    if (c % P.px >= P.ext[0]) mask[c] = CELL_PAD;
   for (int z = 0; z < p.nz; ++z)
     for (int y = 0; y < p.ny; ++y)
       for (int x = 0; x < p.nx; ++x) {
@@ -197,11 +201,22 @@ fre_status build_mask(fre_lattice *L, const uint8_t *user_mask, std::vector<uint
     return a == 0 ? VSet<19>::cx(i) : a == 1 ? VSet<19>::cy(i) : VSet<19>::cz(i);
   };
   L->fill_host.clear();
+  nbm.assign((size_t)P.ncell, NB_SELF_SOLID);
   for (int z = 0; z < P.ext[2]; ++z)
     for (int y = 0; y < P.ext[1]; ++y)
       for (int x = 0; x < P.ext[0]; ++x) {
-        long long s = x + (long long)P.ext[0] * (y + (long long)P.ext[1] * z);
-        if (mask[s] == CELL_FLUID) continue;
+        long long s = x + (long long)P.px * (y + (long long)P.ext[1] * z);
+        if (mask[s] == CELL_FLUID) {
+          uint32_t bits = 0;
+          for (int i = 1; i < P.q; ++i) {
+            int v[3] = {x + dir(i, 0), y + dir(i, 1), z + dir(i, 2)};
+            for (int a = 0; a < 3; ++a) v[a] = (v[a] % P.ext[a] + P.ext[a]) % P.ext[a];
+            long long n = v[0] + (long long)P.px * (v[1] + (long long)P.ext[1] * v[2]);
+            if (mask[n] != CELL_FLUID) bits |= 1u << i;
+          }
+          nbm[s] = bits;
+          continue;
+        }
         bool near = false;
         for (int i = 1; i < P.q && !near; ++i) {
           int v[3] = {x + dir(i, 0), y + dir(i, 1), z + dir(i, 2)};
@@ -211,7 +226,7 @@ fre_status build_mask(fre_lattice *L, const uint8_t *user_mask, std::vector<uint
             else if (v[a] < 0 || v[a] >= P.ext[a]) ok = false;
           }
           if (!ok) continue;
-          long long n = v[0] + (long long)P.ext[0] * (v[1] + (long long)P.ext[1] * v[2]);
+          long long n = v[0] + (long long)P.px * (v[1] + (long long)P.ext[1] * v[2]);
           near = mask[n] == CELL_FLUID;
         }
         if (near) L->fill_host.push_back((int)s);
@@ -226,16 +241,17 @@ void bind_args(fre_lattice *L) {
   a.storage = L->p.storage;
   a.G.ex = P.ext[0]; a.G.ey = P.ext[1]; a.G.ez = P.ext[2];
   for (int k = 0; k < 3; ++k) { a.G.per[k] = P.per[k]; a.G.off[k] = P.off[k]; }
-  a.G.np = P.np;
+  a.G.px = P.px;
   a.G.ncell = P.ncell;
   a.ph = make_phys(&L->p);
   a.f = L->base + P.o_f;
   a.g = L->base + P.o_g;
   a.g0 = L->p.storage == FRE_FP16 ? (float *)(L->base + P.o_g0) : nullptr;
   a.mask = L->base + P.o_mask;
+  a.nbm = (uint32_t *)(L->base + P.o_nbm);
   a.M = (float2 *)(L->base + P.o_M);
-  a.MU = (float2 *)(L->base + P.o_MU);
-  a.PI = (float *)(L->base + P.o_PI);
+  a.C = (float4 *)(L->base + P.o_C);
+  a.MUP = (float *)(L->base + P.o_MUP);
   a.AUX = (float4 *)(L->base + P.o_AUX);
   a.fill_list = (int *)(L->base + P.o_fill);
   a.n_fill = (int)L->fill_host.size();
@@ -290,7 +306,8 @@ fre_status fre_lattice_init(const fre_params *p, void *device_buf, size_t bytes,
   L->state = 0;
   L->graph_ok = false;
   std::vector<uint8_t> mask;
-  s = build_mask(L, solid_mask, mask);
+  std::vector<uint32_t> nbm;
+  s = build_mask(L, solid_mask, mask, nbm);
   if (s != FRE_OK) { delete L; return s; }
   bind_args(L);
   L->a.stream = (hipStream_t)hip_stream;
@@ -321,8 +338,9 @@ fre_status fre_lattice_init(const fre_params *p, void *device_buf, size_t bytes,
   INIT_TRY(hipMemcpyAsync(L->a.AUX, U.data(), U.size() * 4, hipMemcpyHostToDevice, st));
   if (!L->fill_host.empty())
     INIT_TRY(hipMemcpyAsync(L->a.fill_list, L->fill_host.data(), L->fill_host.size() * 4, hipMemcpyHostToDevice, st));
-  INIT_TRY(hipMemsetAsync(L->a.MU, 0, (size_t)P.ncell * 8, st));
-  INIT_TRY(hipMemsetAsync(L->a.PI, 0, (size_t)P.ncell * 4, st));
+  INIT_TRY(hipMemcpyAsync(L->a.nbm, nbm.data(), nbm.size() * 4, hipMemcpyHostToDevice, st));
+  INIT_TRY(hipMemsetAsync(L->a.C, 0, (size_t)P.ncell * 16, st));
+  INIT_TRY(hipMemsetAsync(L->a.MUP, 0, (size_t)P.ncell * 4, st));
   launch_init(L->a);
   INIT_TRY(hipGetLastError());
   INIT_TRY(hipStreamSynchronize(st));
@@ -399,11 +417,11 @@ fre_status fre_read_moments(fre_lattice *L, uint32_t field_mask, double *host_ou
   const Plan &P = L->plan;
   fre_status s = observe(L);
   if (s != FRE_OK) return s;
-  std::vector<float> M((size_t)P.ncell * 2), MU((size_t)P.ncell * 2), AUX((size_t)P.ncell * 4);
+  std::vector<float> Cv((size_t)P.ncell * 4), MUP((size_t)P.ncell), AUX((size_t)P.ncell * 4);
   std::vector<uint8_t> mask((size_t)P.ncell);
   hipStream_t st = L->a.stream;
-  HIP_TRY(hipMemcpyAsync(M.data(), L->a.M, M.size() * 4, hipMemcpyDeviceToHost, st));
-  HIP_TRY(hipMemcpyAsync(MU.data(), L->a.MU, MU.size() * 4, hipMemcpyDeviceToHost, st));
+  HIP_TRY(hipMemcpyAsync(Cv.data(), L->a.C, Cv.size() * 4, hipMemcpyDeviceToHost, st));
+  HIP_TRY(hipMemcpyAsync(MUP.data(), L->a.MUP, MUP.size() * 4, hipMemcpyDeviceToHost, st));
   HIP_TRY(hipMemcpyAsync(AUX.data(), L->a.AUX, AUX.size() * 4, hipMemcpyDeviceToHost, st));
   HIP_TRY(hipMemcpyAsync(mask.data(), L->a.mask, mask.size(), hipMemcpyDeviceToHost, st));
   HIP_TRY(hipStreamSynchronize(st));
@@ -421,11 +439,11 @@ fre_status fre_read_moments(fre_lattice *L, uint32_t field_mask, double *host_ou
             double v = 0.0;
             if (mask[e] == CELL_FLUID) {
               switch (b) {
-                case 0: v = 1.0 + (double)M[2 * e]; break;
-                case 1: v = M[2 * e + 1]; break;
+                case 0: v = 1.0 + (double)Cv[4 * e]; break;
+                case 1: v = Cv[4 * e + 1]; break;
                 case 2: v = AUX[4 * e + k]; break;
-                case 3: v = MU[2 * e]; break;
-                case 4: v = MU[2 * e + 1]; break;
+                case 3: v = Cv[4 * e + 3]; break;
+                case 4: v = MUP[e]; break;
                 default: v = AUX[4 * e + 3]; break;
               }
             }

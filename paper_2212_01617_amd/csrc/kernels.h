@@ -15,34 +15,24 @@ struct LaunchArgs {
   int storage;  // 0 FP32, 1 FP16
   Geom G;
   Phys ph;
-  void *f, *g;  // population planes (float or half)
+  void *f, *g;  // population blocks (float or half)
   float *g0;    // FP16 storage only: g_0 plane
   uint8_t *mask;
+  uint32_t *nbm;  // per cell: non-fluid neighbour bits, NB_SELF_SOLID
   float2 *M;    // (rho - 1, phi)
-  float2 *MU;   // (mu_rho, mu_phi)
-  float *PI;    // rho mu_rho + phi mu_phi
+  float4 *C;    // (rho - 1, phi, Pi = rho mu_rho + phi mu_phi, mu_rho)
+  float *MUP;   // mu_phi
   float4 *AUX;  // u0 at init; (ux, uy, uz, P) after observe
   int *fill_list;
   int n_fill;
   hipStream_t stream;
 };
 
-template <int S> inline Pops<S> make_pops(const LaunchArgs &a);
-template <> inline Pops<0> make_pops<0>(const LaunchArgs &a) {
-  Pops<0> p;
-  p.f = (float *)a.f;
-  p.g = (float *)a.g;
-  p.np = a.G.np;
-  return p;
-}
-template <> inline Pops<1> make_pops<1>(const LaunchArgs &a) {
-  Pops<1> p;
-  p.f = (__half *)a.f;
-  p.g = (__half *)a.g;
-  p.g0 = a.g0;
-  p.np = a.G.np;
-  return p;
-}
+template <int Q, int S> inline Pops<Q, S> make_pops(const LaunchArgs &a);
+template <> inline Pops<9, 0> make_pops<9, 0>(const LaunchArgs &a) { return Pops<9, 0>{(float *)a.f, (float *)a.g}; }
+template <> inline Pops<19, 0> make_pops<19, 0>(const LaunchArgs &a) { return Pops<19, 0>{(float *)a.f, (float *)a.g}; }
+template <> inline Pops<9, 1> make_pops<9, 1>(const LaunchArgs &a) { return Pops<9, 1>{(__half *)a.f, (__half *)a.g, a.g0}; }
+template <> inline Pops<19, 1> make_pops<19, 1>(const LaunchArgs &a) { return Pops<19, 1>{(__half *)a.f, (__half *)a.g, a.g0}; }
 
 void launch_step(const LaunchArgs &a, int odd);
 void launch_step_events(const LaunchArgs &a, int odd, hipEvent_t *ev);

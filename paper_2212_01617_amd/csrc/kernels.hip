@@ -1,11 +1,11 @@
 // kernels.hip -- HIP kernels (gfx950) of the free-energy LBM step.
 //
 // One time step (Algorithm 1 of Simonis et al., arXiv 2212.01617, then
-// streaming, Sec. 2.3) is five launches over the storage grid:
+// streaming, Sec. 2.3) is a short sequence of launches over the storage grid:
 //   k_moments   rho - 1, phi at fluid cells             (eqs. densMoment, ordeMoment)
-//   k_fill<2>   rho, phi at solid cells next to fluid   (fluid-neighbour mean)
+//   k_fill_m    rho, phi at solid cells next to fluid   (fluid-neighbour mean)
 //   k_potential mu_rho, mu_phi and Pi = rho mu_rho + phi mu_phi   (eqs. mu_rho, mu_phi)
-//   k_fill<1>   Pi at solid cells next to fluid
+//   k_fill_c    Pi (and rho, phi) at solid cells next to fluid
 //   k_collide   force (eq. F), velocity (eq. veloMoment), BGK collision of f
 //               with Guo forcing (eqs. bgk, feq, Fi) and of g (eqs. LBEg,
 //               geq), streaming with moving bounce-back, in place.
@@ -15,6 +15,10 @@
 // opp(i)); at odd steps it reads from and writes to its neighbours' slots.
 // Each slot is read and written by the same thread within a step, so the
 // update is race-free without a second population buffer.
+//
+// The coupling fields a fluid cell needs from its neighbours are packed into
+// one float4 per cell, C = (rho - 1, phi, Pi, mu_rho), with mu_phi in a
+// plane of its own; a 32-bit word per cell flags its non-fluid neighbours.
 #include "lbm_device.h"
 #include "kernels.h"
 
@@ -27,13 +31,13 @@ __device__ __forceinline__ bool cell_of_thread(const Geom &G, int &x, int &y, in
   y = blockIdx.y * BY + threadIdx.y;
   z = blockIdx.z;
   if (x >= G.ex || y >= G.ey) return false;
-  c = (long long)x + (long long)G.ex * ((long long)y + (long long)G.ey * z);
+  c = (long long)x + (long long)G.px * ((long long)y + (long long)G.ey * z);
   return true;
 }
 
 // Load the q populations of fluid cell c at time parity `odd` (AA pattern).
 template <int Q, int S>
-__device__ __forceinline__ void load_pops(const Pops<S> &P, const int *nb, long long c, int odd,
+__device__ __forceinline__ void load_pops(const Pops<Q, S> &P, const int *nb, long long c, int odd,
                                           float *df, float *g) {
 #pragma unroll
   for (int i = 0; i < Q; ++i) {
@@ -58,12 +62,12 @@ __device__ __forceinline__ void neighbours(const Geom &G, int x, int y, int z, i
 
 // ---------------------------------------------------------------------------
 template <int Q, int S>
-__global__ __launch_bounds__(BX *BY) void k_moments(Pops<S> P, const uint8_t *__restrict__ mask,
+__global__ __launch_bounds__(BX *BY) void k_moments(Pops<Q, S> P, const uint32_t *__restrict__ nbm,
                                                     float2 *__restrict__ M, Geom G, int odd) {
   int x, y, z;
   long long c;
   if (!cell_of_thread(G, x, y, z, c)) return;
-  if (mask[c] != CELL_FLUID) return;
+  if (nbm[c] & NB_SELF_SOLID) return;
   int nb[Q];
   neighbours<Q>(G, x, y, z, nb);
   float df[Q], g[Q];
@@ -77,20 +81,15 @@ __global__ __launch_bounds__(BX *BY) void k_moments(Pops<S> P, const uint8_t *__
   M[c] = make_float2(drho, phi);
 }
 
-// Solid cells next to fluid take the lattice-weighted mean of their fluid
-// neighbours (for rho, phi and Pi alike).  NC = 2: float2 field, NC = 1: float.
-template <int Q, int NC>
-__global__ __launch_bounds__(256) void k_fill(float *__restrict__ X, const int *__restrict__ list, int n,
-                                              const uint8_t *__restrict__ mask, Geom G) {
+// Weighted mean over the fluid neighbours of solid cell s (coordinates x, y,
+// z) of the NC leading floats of a field with stride ST floats per cell.
+template <int Q, int NC, int ST>
+__device__ __forceinline__ void fluid_mean(const float *__restrict__ X, const uint8_t *__restrict__ mask,
+                                           const Geom &G, int x, int y, int z, float *out) {
   using V = VSet<Q>;
-  int k = blockIdx.x * blockDim.x + threadIdx.x;
-  if (k >= n) return;
-  int s = list[k];
-  int x = s % G.ex;
-  int r = s / G.ex;
-  int y = r % G.ey;
-  int z = r / G.ey;
-  float num0 = 0.0f, num1 = 0.0f, den = 0.0f;
+  float num[NC], den = 0.0f;
+#pragma unroll
+  for (int k = 0; k < NC; ++k) num[k] = 0.0f;
 #pragma unroll
   for (int i = 1; i < Q; ++i) {
     int xn = x + V::cx(i), yn = y + V::cy(i), zn = z + V::cz(i);
@@ -99,16 +98,52 @@ __global__ __launch_bounds__(256) void k_fill(float *__restrict__ X, const int *
     if (V::D == 3) {
       if (G.per[2]) zn = wrap(zn, G.ez); else if (zn < 0 || zn >= G.ez) continue;
     }
-    long long n2 = (long long)xn + (long long)G.ex * ((long long)yn + (long long)G.ey * zn);
+    long long n2 = (long long)xn + (long long)G.px * ((long long)yn + (long long)G.ey * zn);
     if (mask[n2] != CELL_FLUID) continue;
     float w = V::w(i);
-    num0 += w * X[NC * n2];
-    if (NC == 2) num1 += w * X[NC * n2 + 1];
+#pragma unroll
+    for (int k = 0; k < NC; ++k) num[k] += w * X[ST * n2 + k];
     den += w;
   }
   float inv = den > 0.0f ? 1.0f / den : 0.0f;
-  X[NC * (long long)s] = num0 * inv;
-  if (NC == 2) X[NC * (long long)s + 1] = num1 * inv;
+#pragma unroll
+  for (int k = 0; k < NC; ++k) out[k] = num[k] * inv;
+}
+
+__device__ __forceinline__ void cell_coords(const Geom &G, int s, int &x, int &y, int &z) {
+  x = s % G.px;
+  int r = s / G.px;
+  y = r % G.ey;
+  z = r / G.ey;
+}
+
+// Solid cells next to fluid take the lattice-weighted mean of their fluid
+// neighbours: rho, phi into M.
+template <int Q>
+__global__ __launch_bounds__(256) void k_fill_m(float2 *__restrict__ M, const int *__restrict__ list, int n,
+                                                const uint8_t *__restrict__ mask, Geom G) {
+  int k = blockIdx.x * blockDim.x + threadIdx.x;
+  if (k >= n) return;
+  int s = list[k], x, y, z;
+  cell_coords(G, s, x, y, z);
+  float v[2];
+  fluid_mean<Q, 2, 2>((const float *)M, mask, G, x, y, z, v);
+  M[s] = make_float2(v[0], v[1]);
+}
+
+// ... and Pi into C (with the filled rho, phi copied from M).
+template <int Q>
+__global__ __launch_bounds__(256) void k_fill_c(float4 *__restrict__ C, const float2 *__restrict__ M,
+                                                const int *__restrict__ list, int n,
+                                                const uint8_t *__restrict__ mask, Geom G) {
+  int k = blockIdx.x * blockDim.x + threadIdx.x;
+  if (k >= n) return;
+  int s = list[k], x, y, z;
+  cell_coords(G, s, x, y, z);
+  float pi;
+  fluid_mean<Q, 1, 4>((const float *)C + 2, mask, G, x, y, z, &pi);
+  float2 m = M[s];
+  C[s] = make_float4(m.x, m.y, pi, 0.0f);
 }
 
 template <int Q>
@@ -128,13 +163,13 @@ __device__ __forceinline__ void laplacians(const float2 *__restrict__ M, const i
 
 template <int Q>
 __global__ __launch_bounds__(BX *BY) void k_potential(const float2 *__restrict__ M,
-                                                      const uint8_t *__restrict__ mask,
-                                                      float2 *__restrict__ MU, float *__restrict__ PI,
+                                                      const uint32_t *__restrict__ nbm,
+                                                      float4 *__restrict__ C, float *__restrict__ MUP,
                                                       Geom G, Phys P) {
   int x, y, z;
   long long c;
   if (!cell_of_thread(G, x, y, z, c)) return;
-  if (mask[c] != CELL_FLUID) return;
+  if (nbm[c] & NB_SELF_SOLID) return;
   int nb[Q];
   neighbours<Q>(G, x, y, z, nb);
   float2 m0 = M[c];
@@ -142,8 +177,8 @@ __global__ __launch_bounds__(BX *BY) void k_potential(const float2 *__restrict__
   laplacians<Q>(M, nb, m0, lr, lp);
   float mr, mp;
   chem_pot(P, m0.x, m0.y, lr, lp, mr, mp);
-  MU[c] = make_float2(mr, mp);
-  PI[c] = (1.0f + m0.x) * mr + m0.y * mp;
+  C[c] = make_float4(m0.x, m0.y, (1.0f + m0.x) * mr + m0.y * mp, mr);
+  MUP[c] = mp;
 }
 
 // Force of eq. (F) in product-rule form:
@@ -151,34 +186,34 @@ __global__ __launch_bounds__(BX *BY) void k_potential(const float2 *__restrict__
 //     = mu_rho grad rho + mu_phi grad phi - grad(rho mu_rho + phi mu_phi),
 // gradients by the lattice stencil (1/cs^2) sum_i w_i c_i X(x + c_i).
 template <int Q>
-__device__ __forceinline__ void force(const float2 *__restrict__ M, const float *__restrict__ PI,
-                                      const int *nb, float2 mu, float F[3]) {
+__device__ __forceinline__ void force(const float4 *__restrict__ C, const int *nb, float mu_rho,
+                                      float mu_phi, float F[3]) {
   using V = VSet<Q>;
   float gr[3] = {0, 0, 0}, gp[3] = {0, 0, 0}, gq[3] = {0, 0, 0};
 #pragma unroll
   for (int i = 1; i < Q; ++i) {
-    float2 m = M[nb[i]];
-    float pi = PI[nb[i]];
+    float4 m = C[nb[i]];
     float w = 3.0f * V::w(i);
-    if (V::cx(i)) { gr[0] += V::cx(i) * w * m.x; gp[0] += V::cx(i) * w * m.y; gq[0] += V::cx(i) * w * pi; }
-    if (V::cy(i)) { gr[1] += V::cy(i) * w * m.x; gp[1] += V::cy(i) * w * m.y; gq[1] += V::cy(i) * w * pi; }
-    if (V::cz(i)) { gr[2] += V::cz(i) * w * m.x; gp[2] += V::cz(i) * w * m.y; gq[2] += V::cz(i) * w * pi; }
+    if (V::cx(i)) { gr[0] += V::cx(i) * w * m.x; gp[0] += V::cx(i) * w * m.y; gq[0] += V::cx(i) * w * m.z; }
+    if (V::cy(i)) { gr[1] += V::cy(i) * w * m.x; gp[1] += V::cy(i) * w * m.y; gq[1] += V::cy(i) * w * m.z; }
+    if (V::cz(i)) { gr[2] += V::cz(i) * w * m.x; gp[2] += V::cz(i) * w * m.y; gq[2] += V::cz(i) * w * m.z; }
   }
 #pragma unroll
-  for (int a = 0; a < 3; ++a) F[a] = mu.x * gr[a] + mu.y * gp[a] - gq[a];
+  for (int a = 0; a < 3; ++a) F[a] = mu_rho * gr[a] + mu_phi * gp[a] - gq[a];
 }
 
 template <int Q, int S>
-__global__ __launch_bounds__(BX *BY) void k_collide(Pops<S> P, const uint8_t *__restrict__ mask,
-                                                    const float2 *__restrict__ M,
-                                                    const float2 *__restrict__ MU,
-                                                    const float *__restrict__ PI, Geom G, Phys ph,
+__global__ __launch_bounds__(BX *BY) void k_collide(Pops<Q, S> P, const uint32_t *__restrict__ nbm,
+                                                    const uint8_t *__restrict__ mask,
+                                                    const float4 *__restrict__ C,
+                                                    const float *__restrict__ MUP, Geom G, Phys ph,
                                                     int odd) {
   using V = VSet<Q>;
   int x, y, z;
   long long c;
   if (!cell_of_thread(G, x, y, z, c)) return;
-  if (mask[c] != CELL_FLUID) return;
+  const uint32_t bits = nbm[c];
+  if (bits & NB_SELF_SOLID) return;
   int nb[Q];
   neighbours<Q>(G, x, y, z, nb);
   float df[Q], g[Q];
@@ -195,70 +230,73 @@ __global__ __launch_bounds__(BX *BY) void k_collide(Pops<S> P, const uint8_t *__
     j[2] += V::cz(i) * df[i];
   }
   float rho = 1.0f + drho;
+  const float mu_rho = C[c].w, mu_phi = MUP[c];
   float F[3];
-  force<Q>(M, PI, nb, MU[c], F);
-  float mu_phi = MU[c].y;
+  force<Q>(C, nb, mu_rho, mu_phi, F);
   float inv_rho = 1.0f / rho;
   float u[3] = {(j[0] + 0.5f * F[0]) * inv_rho, (j[1] + 0.5f * F[1]) * inv_rho,
                 (j[2] + 0.5f * F[2]) * inv_rho};
   float uu = u[0] * u[0] + u[1] * u[1] + u[2] * u[2];
   float uF = u[0] * F[0] + u[1] * F[1] + u[2] * F[2];
 
-  // collision (eqs. bgk, feq, Fi for f; LBEg, geq for g)
-  float fs[Q], gs[Q];
+  // collision (eqs. bgk, feq, Fi for f; LBEg, geq for g) and streaming with
+  // moving halfway bounce-back (AA in place)
   float geq_rest = 0.0f;
+  float gs0 = 0.0f;
 #pragma unroll
   for (int i = 0; i < Q; ++i) {
     float cu = V::cx(i) * u[0] + V::cy(i) * u[1] + V::cz(i) * u[2];
     float cF = V::cx(i) * F[0] + V::cy(i) * F[1] + V::cz(i) * F[2];
     float wi = V::w(i);
     float poly = 3.0f * cu + 4.5f * cu * cu - 1.5f * uu;
-    float dfeq = wi * (drho + rho * poly);                       // f_i^eq - w_i
+    float dfeq = wi * (drho + rho * poly);                         // f_i^eq - w_i
     float src = ph.guo * wi * (3.0f * (cF - uF) + 9.0f * cu * cF);  // Guo term
-    fs[i] = df[i] + ph.om_f * (dfeq - df[i]) + src;
+    float fs = df[i] + ph.om_f * (dfeq - df[i]) + src;
+    float gs;
     if (i > 0) {
       float geq = wi * (ph.gam3 * mu_phi + phi * poly);
       geq_rest += geq;
-      gs[i] = g[i] + ph.om_g * (geq - g[i]);
-    }
-  }
-  gs[0] = g[0] + ph.om_g * ((phi - geq_rest) - g[0]);
-
-  // streaming with moving halfway bounce-back (AA in place)
-#pragma unroll
-  for (int i = 0; i < Q; ++i) {
-    long long n = nb[i];
-    uint8_t code = i == 0 ? CELL_FLUID : mask[n];
-    if (code == CELL_FLUID) {
-      if (!odd) { P.stf(opp(i), c, fs[i]); P.stg(opp(i), c, gs[i]); }
-      else { P.stf(i, n, fs[i]); P.stg(i, n, gs[i]); }
+      gs = g[i] + ph.om_g * (geq - g[i]);
     } else {
+      gs = 0.0f;  // g_0 needs the complement of all other equilibria; stored below
+    }
+    if (i == 0) {
+      P.stf(0, c, fs);
+      continue;
+    }
+    if (!((bits >> i) & 1u)) {
+      if (!odd) { P.stf(opp(i), c, fs); P.stg(opp(i), c, gs); }
+      else { P.stf(i, nb[i], fs); P.stg(i, nb[i], gs); }
+    } else {
+      long long n = nb[i];
       int xs = wrap(x + V::cx(i), G.ex), ys = wrap(y + V::cy(i), G.ey);
       int zs = V::D == 3 ? wrap(z + V::cz(i), G.ez) : z;
       float uw[3];
-      body_velocity<V>(G, ph, code, x, y, z, xs, ys, zs, i, uw);
+      body_velocity<V>(G, ph, mask[n], x, y, z, xs, ys, zs, i, uw);
       float cw = V::cx(i) * uw[0] + V::cy(i) * uw[1] + V::cz(i) * uw[2];
-      float k = 6.0f * V::w(i) * cw;  // 2 w_i (c_i . u_w) / cs^2
-      float fb = fs[i] - k * rho, gb = gs[i] - k * phi;
+      float k = 6.0f * wi * cw;  // 2 w_i (c_i . u_w) / cs^2
+      float fb = fs - k * rho, gb = gs - k * phi;
       // f_opp(i)(x, t+1): read next step from slot (x + c_i, i) after an
       // even step, from slot (x, opp(i)) after an odd step
       if (!odd) { P.stf(i, n, fb); P.stg(i, n, gb); }
       else { P.stf(opp(i), c, fb); P.stg(opp(i), c, gb); }
     }
   }
+  gs0 = g[0] + ph.om_g * ((phi - geq_rest) - g[0]);
+  P.stg(0, c, gs0);
 }
 
 // Initialisation at equilibrium (Sec. 2.3).  M holds (rho0 - 1, phi0) with
 // solid cells filled; U0 holds u0.  Writes the parity-0 layout.
 template <int Q, int S>
-__global__ __launch_bounds__(BX *BY) void k_init(Pops<S> P, const uint8_t *__restrict__ mask,
+__global__ __launch_bounds__(BX *BY) void k_init(Pops<Q, S> P, const uint32_t *__restrict__ nbm,
                                                  const float2 *__restrict__ M,
                                                  const float4 *__restrict__ U0, Geom G, Phys ph) {
   using V = VSet<Q>;
   int x, y, z;
   long long c;
   if (!cell_of_thread(G, x, y, z, c)) return;
-  if (mask[c] != CELL_FLUID) return;
+  if (nbm[c] & NB_SELF_SOLID) return;
   int nb[Q];
   neighbours<Q>(G, x, y, z, nb);
   float2 m0 = M[c];
@@ -284,19 +322,18 @@ __global__ __launch_bounds__(BX *BY) void k_init(Pops<S> P, const uint8_t *__res
   P.stg(0, c, phi - rest);
 }
 
-// Observables (u with F/2, bulk pressure) at the current time; M, MU, PI
-// must be current.  OUT[c] = (ux, uy, uz, P).
+// Observables (u with F/2, bulk pressure) at the current time; M, C, MUP must
+// be current.  OUT[c] = (ux, uy, uz, P).
 template <int Q, int S>
-__global__ __launch_bounds__(BX *BY) void k_observe(Pops<S> P, const uint8_t *__restrict__ mask,
-                                                    const float2 *__restrict__ M,
-                                                    const float2 *__restrict__ MU,
-                                                    const float *__restrict__ PI,
+__global__ __launch_bounds__(BX *BY) void k_observe(Pops<Q, S> P, const uint32_t *__restrict__ nbm,
+                                                    const float4 *__restrict__ C,
+                                                    const float *__restrict__ MUP,
                                                     float4 *__restrict__ OUT, Geom G, Phys ph, int odd) {
   using V = VSet<Q>;
   int x, y, z;
   long long c;
   if (!cell_of_thread(G, x, y, z, c)) return;
-  if (mask[c] != CELL_FLUID) {
+  if (nbm[c] & NB_SELF_SOLID) {
     OUT[c] = make_float4(0, 0, 0, 0);
     return;
   }
@@ -311,26 +348,26 @@ __global__ __launch_bounds__(BX *BY) void k_observe(Pops<S> P, const uint8_t *__
     j[1] += V::cy(i) * df[i];
     j[2] += V::cz(i) * df[i];
   }
-  float2 m0 = M[c];
-  float2 mu = MU[c];
+  float4 m0 = C[c];
+  float mu_phi = MUP[c];
   float F[3];
-  force<Q>(M, PI, nb, mu, F);
+  force<Q>(C, nb, m0.w, mu_phi, F);
   float rho = 1.0f + m0.x;
   float inv = 1.0f / rho;
-  float pres = rho / 3.0f + rho * mu.x + m0.y * mu.y - psi_bulk(ph, rho, m0.y);
+  float pres = rho / 3.0f + rho * m0.w + m0.y * mu_phi - psi_bulk(ph, rho, m0.y);
   OUT[c] = make_float4((j[0] + 0.5f * F[0]) * inv, (j[1] + 0.5f * F[1]) * inv,
                        (j[2] + 0.5f * F[2]) * inv, pres);
 }
 
 // Unshifted populations in the natural layout, [2q][ncell] floats.
 template <int Q, int S>
-__global__ __launch_bounds__(BX *BY) void k_read_pops(Pops<S> P, const uint8_t *__restrict__ mask,
+__global__ __launch_bounds__(BX *BY) void k_read_pops(Pops<Q, S> P, const uint32_t *__restrict__ nbm,
                                                       float *__restrict__ out, Geom G, int odd) {
   using V = VSet<Q>;
   int x, y, z;
   long long c;
   if (!cell_of_thread(G, x, y, z, c)) return;
-  if (mask[c] != CELL_FLUID) {
+  if (nbm[c] & NB_SELF_SOLID) {
     for (int i = 0; i < 2 * Q; ++i) out[i * G.ncell + c] = 0.0f;
     return;
   }
@@ -356,15 +393,15 @@ __device__ __forceinline__ void kahan(float &s, float &comp, float v) {
   s = t;
 }
 
-__global__ __launch_bounds__(256) void k_reduce(const float2 *__restrict__ M, const float4 *__restrict__ OUT,
-                                                const uint8_t *__restrict__ mask, long long ncell,
+__global__ __launch_bounds__(256) void k_reduce(const float4 *__restrict__ C, const float4 *__restrict__ OUT,
+                                                const uint32_t *__restrict__ nbm, long long ncell,
                                                 double *__restrict__ part) {
   float s[6] = {0, 0, 0, 0, 0, 0}, e[6] = {0, 0, 0, 0, 0, 0};
   unsigned bad = 0, nfl = 0;
   for (long long c = (long long)blockIdx.x * blockDim.x + threadIdx.x; c < ncell;
        c += (long long)gridDim.x * blockDim.x) {
-    if (mask[c] != CELL_FLUID) continue;
-    float2 m = M[c];
+    if (nbm[c] & NB_SELF_SOLID) continue;
+    float4 m = C[c];
     float4 o = OUT[c];
     float rho = 1.0f + m.x;
     float v[6] = {m.x, m.y, fabsf(m.y), rho * o.x, rho * o.y, rho * o.z};
@@ -394,58 +431,44 @@ __global__ __launch_bounds__(256) void k_reduce(const float2 *__restrict__ M, co
 // ---------------------------------------------------------------------------
 static dim3 cell_grid(const Geom &G) { return dim3((G.ex + BX - 1) / BX, (G.ey + BY - 1) / BY, G.ez); }
 static dim3 cell_block() { return dim3(BX, BY, 1); }
+static int fill_blocks(int n) { return (n + 255) / 256; }
 
+// The kernels of one step in order; ev (if not null) receives an event
+// before each launch and one after the last.
 template <int Q, int S>
-static void step_impl(const LaunchArgs &a, int odd) {
-  Pops<S> P = make_pops<S>(a);
+static void step_seq(const LaunchArgs &a, int odd, hipEvent_t *ev, bool collide) {
+  Pops<Q, S> P = make_pops<Q, S>(a);
   dim3 gr = cell_grid(a.G), bl = cell_block();
-  k_moments<Q, S><<<gr, bl, 0, a.stream>>>(P, a.mask, a.M, a.G, odd);
-  if (a.n_fill) k_fill<Q, 2><<<(a.n_fill + 255) / 256, 256, 0, a.stream>>>((float *)a.M, a.fill_list, a.n_fill, a.mask, a.G);
-  k_potential<Q><<<gr, bl, 0, a.stream>>>(a.M, a.mask, a.MU, a.PI, a.G, a.ph);
-  if (a.n_fill) k_fill<Q, 1><<<(a.n_fill + 255) / 256, 256, 0, a.stream>>>(a.PI, a.fill_list, a.n_fill, a.mask, a.G);
-  k_collide<Q, S><<<gr, bl, 0, a.stream>>>(P, a.mask, a.M, a.MU, a.PI, a.G, a.ph, odd);
+  int k = 0;
+  auto mark = [&]() { if (ev) (void)hipEventRecord(ev[k++], a.stream); };
+  mark();
+  k_moments<Q, S><<<gr, bl, 0, a.stream>>>(P, a.nbm, a.M, a.G, odd);
+  mark();
+  if (a.n_fill) k_fill_m<Q><<<fill_blocks(a.n_fill), 256, 0, a.stream>>>(a.M, a.fill_list, a.n_fill, a.mask, a.G);
+  mark();
+  k_potential<Q><<<gr, bl, 0, a.stream>>>(a.M, a.nbm, a.C, a.MUP, a.G, a.ph);
+  mark();
+  if (a.n_fill) k_fill_c<Q><<<fill_blocks(a.n_fill), 256, 0, a.stream>>>(a.C, a.M, a.fill_list, a.n_fill, a.mask, a.G);
+  mark();
+  if (collide) k_collide<Q, S><<<gr, bl, 0, a.stream>>>(P, a.nbm, a.mask, a.C, a.MUP, a.G, a.ph, odd);
+  else k_observe<Q, S><<<gr, bl, 0, a.stream>>>(P, a.nbm, a.C, a.MUP, a.AUX, a.G, a.ph, odd);
+  mark();
 }
 
-// The same five launches as step_impl, each bracketed by events on the
-// stream (ev[k] before launch k, ev[5] after the last).
-template <int Q, int S>
-static void step_events_impl(const LaunchArgs &a, int odd, hipEvent_t *ev) {
-  Pops<S> P = make_pops<S>(a);
-  dim3 gr = cell_grid(a.G), bl = cell_block();
-  (void)hipEventRecord(ev[0], a.stream);
-  k_moments<Q, S><<<gr, bl, 0, a.stream>>>(P, a.mask, a.M, a.G, odd);
-  (void)hipEventRecord(ev[1], a.stream);
-  if (a.n_fill) k_fill<Q, 2><<<(a.n_fill + 255) / 256, 256, 0, a.stream>>>((float *)a.M, a.fill_list, a.n_fill, a.mask, a.G);
-  (void)hipEventRecord(ev[2], a.stream);
-  k_potential<Q><<<gr, bl, 0, a.stream>>>(a.M, a.mask, a.MU, a.PI, a.G, a.ph);
-  (void)hipEventRecord(ev[3], a.stream);
-  if (a.n_fill) k_fill<Q, 1><<<(a.n_fill + 255) / 256, 256, 0, a.stream>>>(a.PI, a.fill_list, a.n_fill, a.mask, a.G);
-  (void)hipEventRecord(ev[4], a.stream);
-  k_collide<Q, S><<<gr, bl, 0, a.stream>>>(P, a.mask, a.M, a.MU, a.PI, a.G, a.ph, odd);
-  (void)hipEventRecord(ev[5], a.stream);
-}
-
-template <int Q, int S>
-static void observe_impl(const LaunchArgs &a, int odd) {
-  Pops<S> P = make_pops<S>(a);
-  dim3 gr = cell_grid(a.G), bl = cell_block();
-  k_moments<Q, S><<<gr, bl, 0, a.stream>>>(P, a.mask, a.M, a.G, odd);
-  if (a.n_fill) k_fill<Q, 2><<<(a.n_fill + 255) / 256, 256, 0, a.stream>>>((float *)a.M, a.fill_list, a.n_fill, a.mask, a.G);
-  k_potential<Q><<<gr, bl, 0, a.stream>>>(a.M, a.mask, a.MU, a.PI, a.G, a.ph);
-  if (a.n_fill) k_fill<Q, 1><<<(a.n_fill + 255) / 256, 256, 0, a.stream>>>(a.PI, a.fill_list, a.n_fill, a.mask, a.G);
-  k_observe<Q, S><<<gr, bl, 0, a.stream>>>(P, a.mask, a.M, a.MU, a.PI, a.AUX, a.G, a.ph, odd);
-}
+template <int Q, int S> static void step_impl(const LaunchArgs &a, int odd) { step_seq<Q, S>(a, odd, nullptr, true); }
+template <int Q, int S> static void step_events_impl(const LaunchArgs &a, int odd, hipEvent_t *ev) { step_seq<Q, S>(a, odd, ev, true); }
+template <int Q, int S> static void observe_impl(const LaunchArgs &a, int odd) { step_seq<Q, S>(a, odd, nullptr, false); }
 
 template <int Q, int S>
 static void init_impl(const LaunchArgs &a) {
-  Pops<S> P = make_pops<S>(a);
-  if (a.n_fill) k_fill<Q, 2><<<(a.n_fill + 255) / 256, 256, 0, a.stream>>>((float *)a.M, a.fill_list, a.n_fill, a.mask, a.G);
-  k_init<Q, S><<<cell_grid(a.G), cell_block(), 0, a.stream>>>(P, a.mask, a.M, a.AUX, a.G, a.ph);
+  Pops<Q, S> P = make_pops<Q, S>(a);
+  if (a.n_fill) k_fill_m<Q><<<fill_blocks(a.n_fill), 256, 0, a.stream>>>(a.M, a.fill_list, a.n_fill, a.mask, a.G);
+  k_init<Q, S><<<cell_grid(a.G), cell_block(), 0, a.stream>>>(P, a.nbm, a.M, a.AUX, a.G, a.ph);
 }
 
 template <int Q, int S>
 static void read_pops_impl(const LaunchArgs &a, int odd, float *out) {
-  k_read_pops<Q, S><<<cell_grid(a.G), cell_block(), 0, a.stream>>>(make_pops<S>(a), a.mask, out, a.G, odd);
+  k_read_pops<Q, S><<<cell_grid(a.G), cell_block(), 0, a.stream>>>(make_pops<Q, S>(a), a.nbm, out, a.G, odd);
 }
 
 #define FRE_DISPATCH(fn, ...)                                   \
@@ -460,7 +483,7 @@ void launch_step(const LaunchArgs &a, int odd) { FRE_DISPATCH(step_impl, a, odd)
 void launch_step_events(const LaunchArgs &a, int odd, hipEvent_t *ev) { FRE_DISPATCH(step_events_impl, a, odd, ev); }
 int step_kernel_count() { return 5; }
 const char *step_kernel_name(int k) {
-  static const char *names[5] = {"k_moments", "k_fill_moments", "k_potential", "k_fill_pi", "k_collide"};
+  static const char *names[5] = {"k_moments", "k_fill_m", "k_potential", "k_fill_c", "k_collide"};
   return (k >= 0 && k < 5) ? names[k] : nullptr;
 }
 void launch_observe(const LaunchArgs &a, int odd) { FRE_DISPATCH(observe_impl, a, odd); }
@@ -469,7 +492,7 @@ void launch_read_pops(const LaunchArgs &a, int odd, float *out) { FRE_DISPATCH(r
 
 int reduce_blocks() { return 1024; }
 void launch_reduce(const LaunchArgs &a, double *part) {
-  k_reduce<<<reduce_blocks(), 256, 0, a.stream>>>(a.M, a.AUX, a.mask, a.G.ncell, part);
+  k_reduce<<<reduce_blocks(), 256, 0, a.stream>>>(a.C, a.AUX, a.nbm, a.G.ncell, part);
 }
 
 }  // namespace frelbm

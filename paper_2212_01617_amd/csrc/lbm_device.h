@@ -60,17 +60,23 @@ __host__ __device__ constexpr int opp(int i) { return i == 0 ? 0 : ((i & 1) ? i 
 
 // ---------------------------------------------------------------------------
 // Geometry of one lattice in device memory.  The storage grid is the fluid
-// domain plus one ghost layer at both ends of every wall axis; a cell index is
-// x + ex*(y + ey*z) and population i of cell c lives at i*np + c.
+// domain plus one ghost layer at both ends of every wall axis.  Rows are
+// padded to a pitch px (a multiple of 64) so that every 64-cell block of the
+// population layout is one aligned row segment: cell index c = x + px*(y +
+// ey*z); cells with x >= ex are padding and never touched by the method.
 // ---------------------------------------------------------------------------
-enum : uint8_t { CELL_FLUID = 0, CELL_SOLID = 1, CELL_ROLLER0 = 2, CELL_GHOST = 8 };
+enum : uint8_t { CELL_FLUID = 0, CELL_SOLID = 1, CELL_ROLLER0 = 2, CELL_GHOST = 8, CELL_PAD = 9 };
+
+// Bit 31 of a cell's neighbour word: the cell itself is not fluid.  Bit i
+// (1 <= i < q): the neighbour along c_i is not fluid (bounce-back link).
+constexpr uint32_t NB_SELF_SOLID = 0x80000000u;
 
 struct Geom {
   int ex, ey, ez;   // storage grid
+  int px;           // row pitch (multiple of 64)
   int per[3];       // 1 if the axis is periodic
   int off[3];       // ghost offset (1 on wall axes)
-  long long np;     // stride between direction planes (elements)
-  long long ncell;  // ex*ey*ez
+  long long ncell;  // px*ey*ez
 };
 
 struct Phys {
@@ -95,35 +101,40 @@ __device__ __forceinline__ int nb_fluid(const Geom &G, int x, int y, int z, int 
   int xn = wrap(x + V::cx(i), G.ex);
   int yn = wrap(y + V::cy(i), G.ey);
   int zn = V::D == 3 ? wrap(z + V::cz(i), G.ez) : z;
-  return xn + G.ex * (yn + G.ey * zn);
+  return xn + G.px * (yn + G.ey * zn);
 }
 
 // ---------------------------------------------------------------------------
-// Population storage.  S = 0: FP32 for f and g.  S = 1: f as half, g_0 as
-// float, g_1.. as half (round to nearest even).
+// Population storage: blocks of 64 consecutive cells, each block holding all
+// directions of one population contiguously ([block][direction][64]), so a
+// wavefront streams one contiguous 256-byte (FP32) segment per direction.
+// S = 0: FP32 for f and g.  S = 1: f and g_1.. as half (round to nearest
+// even), g_0 as float in a plane of its own.
 // ---------------------------------------------------------------------------
-template <int S> struct Pops;
+__device__ __forceinline__ long long blk_index(int planes, int i, long long c) {
+  return ((c >> 6) * planes + i) * 64 + (c & 63);
+}
 
-template <> struct Pops<0> {
+template <int Q, int S> struct Pops;
+
+template <int Q> struct Pops<Q, 0> {
   float *f, *g;
-  long long np;
-  __device__ __forceinline__ float ldf(int i, long long c) const { return f[i * np + c]; }
-  __device__ __forceinline__ float ldg(int i, long long c) const { return g[i * np + c]; }
-  __device__ __forceinline__ void stf(int i, long long c, float v) const { f[i * np + c] = v; }
-  __device__ __forceinline__ void stg(int i, long long c, float v) const { g[i * np + c] = v; }
+  __device__ __forceinline__ float ldf(int i, long long c) const { return f[blk_index(Q, i, c)]; }
+  __device__ __forceinline__ float ldg(int i, long long c) const { return g[blk_index(Q, i, c)]; }
+  __device__ __forceinline__ void stf(int i, long long c, float v) const { f[blk_index(Q, i, c)] = v; }
+  __device__ __forceinline__ void stg(int i, long long c, float v) const { g[blk_index(Q, i, c)] = v; }
 };
 
-template <> struct Pops<1> {
-  __half *f, *g;  // g holds directions 1..q-1 at (i-1)*np
+template <int Q> struct Pops<Q, 1> {
+  __half *f, *g;  // g holds directions 1..q-1
   float *g0;
-  long long np;
-  __device__ __forceinline__ float ldf(int i, long long c) const { return __half2float(f[i * np + c]); }
+  __device__ __forceinline__ float ldf(int i, long long c) const { return __half2float(f[blk_index(Q, i, c)]); }
   __device__ __forceinline__ float ldg(int i, long long c) const {
-    return i == 0 ? g0[c] : __half2float(g[(i - 1) * np + c]);
+    return i == 0 ? g0[c] : __half2float(g[blk_index(Q - 1, i - 1, c)]);
   }
-  __device__ __forceinline__ void stf(int i, long long c, float v) const { f[i * np + c] = __float2half_rn(v); }
+  __device__ __forceinline__ void stf(int i, long long c, float v) const { f[blk_index(Q, i, c)] = __float2half_rn(v); }
   __device__ __forceinline__ void stg(int i, long long c, float v) const {
-    if (i == 0) g0[c] = v; else g[(i - 1) * np + c] = __float2half_rn(v);
+    if (i == 0) g0[c] = v; else g[blk_index(Q - 1, i - 1, c)] = __float2half_rn(v);
   }
 };
 
