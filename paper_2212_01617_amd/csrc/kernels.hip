@@ -35,10 +35,32 @@ __device__ __forceinline__ bool cell_of_thread(const Geom &G, int &x, int &y, in
   return true;
 }
 
+// Neighbour addressing of one cell: the wrapped x, row and plane offsets for
+// steps -1, 0, +1 along each axis; neighbour i is at ox[cx+1] + oy[cy+1] +
+// oz[cz+1].  Fluid cells never sit on the storage boundary of a wall axis
+// (the ghost layer is there), so only periodic axes wrap.
+struct Nbr {
+  int ox[3], oy[3], oz[3];
+  __device__ __forceinline__ Nbr(const Geom &G, int x, int y, int z) {
+    ox[0] = wrap(x - 1, G.ex); ox[1] = x; ox[2] = wrap(x + 1, G.ex);
+    oy[0] = G.px * wrap(y - 1, G.ey); oy[1] = G.px * y; oy[2] = G.px * wrap(y + 1, G.ey);
+    const int pl = G.px * G.ey;
+    oz[0] = pl * wrap(z - 1, G.ez); oz[1] = pl * z; oz[2] = pl * wrap(z + 1, G.ez);
+  }
+  template <class V> __device__ __forceinline__ int at(int i) const {
+    return ox[V::cx(i) + 1] + oy[V::cy(i) + 1] + oz[V::cz(i) + 1];
+  }
+  // the cell x - c_i
+  template <class V> __device__ __forceinline__ int back(int i) const {
+    return ox[1 - V::cx(i)] + oy[1 - V::cy(i)] + oz[1 - V::cz(i)];
+  }
+};
+
 // Load the q populations of fluid cell c at time parity `odd` (AA pattern).
 template <int Q, int S>
-__device__ __forceinline__ void load_pops(const Pops<Q, S> &P, const int *nb, long long c, int odd,
+__device__ __forceinline__ void load_pops(const Pops<Q, S> &P, const Nbr &N, long long c, int odd,
                                           float *df, float *g) {
+  using V = VSet<Q>;
 #pragma unroll
   for (int i = 0; i < Q; ++i) {
     if (!odd) {
@@ -46,32 +68,24 @@ __device__ __forceinline__ void load_pops(const Pops<Q, S> &P, const int *nb, lo
       g[i] = P.ldg(i, c);
     } else {
       // f_i(x) = f_i*(x - c_i), written by x - c_i into its slot opp(i)
-      long long s = i == 0 ? c : nb[opp(i)];
+      long long s = i == 0 ? c : N.template back<V>(i);
       df[i] = P.ldf(opp(i), s);
       g[i] = P.ldg(opp(i), s);
     }
   }
 }
 
-template <int Q>
-__device__ __forceinline__ void neighbours(const Geom &G, int x, int y, int z, int *nb) {
-  using V = VSet<Q>;
-#pragma unroll
-  for (int i = 0; i < Q; ++i) nb[i] = nb_fluid<V>(G, x, y, z, i);
-}
-
 // ---------------------------------------------------------------------------
-template <int Q, int S>
+template <int Q, int S, int ODD>
 __global__ __launch_bounds__(BX *BY) void k_moments(Pops<Q, S> P, const uint32_t *__restrict__ nbm,
-                                                    float2 *__restrict__ M, Geom G, int odd) {
+                                                    float2 *__restrict__ M, Geom G) {
   int x, y, z;
   long long c;
   if (!cell_of_thread(G, x, y, z, c)) return;
   if (nbm[c] & NB_SELF_SOLID) return;
-  int nb[Q];
-  neighbours<Q>(G, x, y, z, nb);
+  const Nbr N(G, x, y, z);
   float df[Q], g[Q];
-  load_pops<Q, S>(P, nb, c, odd, df, g);
+  load_pops<Q, S>(P, N, c, ODD, df, g);
   float drho = 0.0f, phi = 0.0f;
 #pragma unroll
   for (int i = 0; i < Q; ++i) {
@@ -147,13 +161,13 @@ __global__ __launch_bounds__(256) void k_fill_c(float4 *__restrict__ C, const fl
 }
 
 template <int Q>
-__device__ __forceinline__ void laplacians(const float2 *__restrict__ M, const int *nb, float2 m0,
+__device__ __forceinline__ void laplacians(const float2 *__restrict__ M, const Nbr &N, float2 m0,
                                            float &lr, float &lp) {
   using V = VSet<Q>;
   float ar = 0.0f, ap = 0.0f;
 #pragma unroll
   for (int i = 1; i < Q; ++i) {
-    float2 m = M[nb[i]];
+    float2 m = M[N.template at<V>(i)];
     ar += V::w(i) * (m.x - m0.x);
     ap += V::w(i) * (m.y - m0.y);
   }
@@ -170,11 +184,10 @@ __global__ __launch_bounds__(BX *BY) void k_potential(const float2 *__restrict__
   long long c;
   if (!cell_of_thread(G, x, y, z, c)) return;
   if (nbm[c] & NB_SELF_SOLID) return;
-  int nb[Q];
-  neighbours<Q>(G, x, y, z, nb);
+  const Nbr N(G, x, y, z);
   float2 m0 = M[c];
   float lr, lp;
-  laplacians<Q>(M, nb, m0, lr, lp);
+  laplacians<Q>(M, N, m0, lr, lp);
   float mr, mp;
   chem_pot(P, m0.x, m0.y, lr, lp, mr, mp);
   C[c] = make_float4(m0.x, m0.y, (1.0f + m0.x) * mr + m0.y * mp, mr);
@@ -186,13 +199,13 @@ __global__ __launch_bounds__(BX *BY) void k_potential(const float2 *__restrict__
 //     = mu_rho grad rho + mu_phi grad phi - grad(rho mu_rho + phi mu_phi),
 // gradients by the lattice stencil (1/cs^2) sum_i w_i c_i X(x + c_i).
 template <int Q>
-__device__ __forceinline__ void force(const float4 *__restrict__ C, const int *nb, float mu_rho,
+__device__ __forceinline__ void force(const float4 *__restrict__ C, const Nbr &N, float mu_rho,
                                       float mu_phi, float F[3]) {
   using V = VSet<Q>;
   float gr[3] = {0, 0, 0}, gp[3] = {0, 0, 0}, gq[3] = {0, 0, 0};
 #pragma unroll
   for (int i = 1; i < Q; ++i) {
-    float4 m = C[nb[i]];
+    float4 m = C[N.template at<V>(i)];
     float w = 3.0f * V::w(i);
     if (V::cx(i)) { gr[0] += V::cx(i) * w * m.x; gp[0] += V::cx(i) * w * m.y; gq[0] += V::cx(i) * w * m.z; }
     if (V::cy(i)) { gr[1] += V::cy(i) * w * m.x; gp[1] += V::cy(i) * w * m.y; gq[1] += V::cy(i) * w * m.z; }
@@ -202,24 +215,20 @@ __device__ __forceinline__ void force(const float4 *__restrict__ C, const int *n
   for (int a = 0; a < 3; ++a) F[a] = mu_rho * gr[a] + mu_phi * gp[a] - gq[a];
 }
 
-template <int Q, int S>
-__global__ __launch_bounds__(BX *BY) void k_collide(Pops<Q, S> P, const uint32_t *__restrict__ nbm,
-                                                    const uint8_t *__restrict__ mask,
-                                                    const float4 *__restrict__ C,
-                                                    const float *__restrict__ MUP, Geom G, Phys ph,
-                                                    int odd) {
+// Collision of one fluid cell and streaming of its populations (AA pattern
+// of parity ODD): every population goes to the slot it streams to.  For a
+// link into a solid cell that slot is never read; bounce_back() then moves
+// the population to the slot the cell reads it from next step.
+template <int Q, int S, int ODD>
+__device__ __forceinline__ void collide_cell(const Pops<Q, S> &P, const Nbr &N, long long c,
+                                             const float4 *__restrict__ C, const float *__restrict__ MUP,
+                                             const Phys &ph, float &rho_out, float &phi_out) {
   using V = VSet<Q>;
-  int x, y, z;
-  long long c;
-  if (!cell_of_thread(G, x, y, z, c)) return;
-  const uint32_t bits = nbm[c];
-  if (bits & NB_SELF_SOLID) return;
-  int nb[Q];
-  neighbours<Q>(G, x, y, z, nb);
+  const float mu_rho = C[c].w, mu_phi = MUP[c];
+  float F[3];
+  force<Q>(C, N, mu_rho, mu_phi, F);
   float df[Q], g[Q];
-  load_pops<Q, S>(P, nb, c, odd, df, g);
-
-  // zeroth and first moments (df_i = f_i - w_i; sum w_i = 1, sum w_i c_i = 0)
+  load_pops<Q, S>(P, N, c, ODD, df, g);
   float drho = 0.0f, phi = 0.0f, j[3] = {0, 0, 0};
 #pragma unroll
   for (int i = 0; i < Q; ++i) {
@@ -229,61 +238,85 @@ __global__ __launch_bounds__(BX *BY) void k_collide(Pops<Q, S> P, const uint32_t
     j[1] += V::cy(i) * df[i];
     j[2] += V::cz(i) * df[i];
   }
-  float rho = 1.0f + drho;
-  const float mu_rho = C[c].w, mu_phi = MUP[c];
-  float F[3];
-  force<Q>(C, nb, mu_rho, mu_phi, F);
-  float inv_rho = 1.0f / rho;
-  float u[3] = {(j[0] + 0.5f * F[0]) * inv_rho, (j[1] + 0.5f * F[1]) * inv_rho,
-                (j[2] + 0.5f * F[2]) * inv_rho};
-  float uu = u[0] * u[0] + u[1] * u[1] + u[2] * u[2];
-  float uF = u[0] * F[0] + u[1] * F[1] + u[2] * F[2];
-
-  // collision (eqs. bgk, feq, Fi for f; LBEg, geq for g) and streaming with
-  // moving halfway bounce-back (AA in place)
+  const float rho = 1.0f + drho;
+  const float inv_rho = 1.0f / rho;
+  const float u[3] = {(j[0] + 0.5f * F[0]) * inv_rho, (j[1] + 0.5f * F[1]) * inv_rho,
+                      (j[2] + 0.5f * F[2]) * inv_rho};
+  const float uu = u[0] * u[0] + u[1] * u[1] + u[2] * u[2];
+  const float uF = u[0] * F[0] + u[1] * F[1] + u[2] * F[2];
   float geq_rest = 0.0f;
-  float gs0 = 0.0f;
 #pragma unroll
   for (int i = 0; i < Q; ++i) {
-    float cu = V::cx(i) * u[0] + V::cy(i) * u[1] + V::cz(i) * u[2];
-    float cF = V::cx(i) * F[0] + V::cy(i) * F[1] + V::cz(i) * F[2];
-    float wi = V::w(i);
-    float poly = 3.0f * cu + 4.5f * cu * cu - 1.5f * uu;
-    float dfeq = wi * (drho + rho * poly);                         // f_i^eq - w_i
-    float src = ph.guo * wi * (3.0f * (cF - uF) + 9.0f * cu * cF);  // Guo term
-    float fs = df[i] + ph.om_f * (dfeq - df[i]) + src;
-    float gs;
-    if (i > 0) {
-      float geq = wi * (ph.gam3 * mu_phi + phi * poly);
-      geq_rest += geq;
-      gs = g[i] + ph.om_g * (geq - g[i]);
-    } else {
-      gs = 0.0f;  // g_0 needs the complement of all other equilibria; stored below
-    }
+    const float cu = V::cx(i) * u[0] + V::cy(i) * u[1] + V::cz(i) * u[2];
+    const float cF = V::cx(i) * F[0] + V::cy(i) * F[1] + V::cz(i) * F[2];
+    const float wi = V::w(i);
+    const float poly = 3.0f * cu + 4.5f * cu * cu - 1.5f * uu;
+    const float dfeq = wi * (drho + rho * poly);                         // f_i^eq - w_i
+    const float src = ph.guo * wi * (3.0f * (cF - uF) + 9.0f * cu * cF);  // Guo term
+    const float fs = P.round(df[i] + ph.om_f * (dfeq - df[i]) + src);
     if (i == 0) {
       P.stf(0, c, fs);
       continue;
     }
-    if (!((bits >> i) & 1u)) {
-      if (!odd) { P.stf(opp(i), c, fs); P.stg(opp(i), c, gs); }
-      else { P.stf(i, nb[i], fs); P.stg(i, nb[i], gs); }
-    } else {
-      long long n = nb[i];
-      int xs = wrap(x + V::cx(i), G.ex), ys = wrap(y + V::cy(i), G.ey);
-      int zs = V::D == 3 ? wrap(z + V::cz(i), G.ez) : z;
-      float uw[3];
-      body_velocity<V>(G, ph, mask[n], x, y, z, xs, ys, zs, i, uw);
-      float cw = V::cx(i) * uw[0] + V::cy(i) * uw[1] + V::cz(i) * uw[2];
-      float k = 6.0f * wi * cw;  // 2 w_i (c_i . u_w) / cs^2
-      float fb = fs - k * rho, gb = gs - k * phi;
-      // f_opp(i)(x, t+1): read next step from slot (x + c_i, i) after an
-      // even step, from slot (x, opp(i)) after an odd step
-      if (!odd) { P.stf(i, n, fb); P.stg(i, n, gb); }
-      else { P.stf(opp(i), c, fb); P.stg(opp(i), c, gb); }
-    }
+    const float geq = wi * (ph.gam3 * mu_phi + phi * poly);
+    geq_rest += geq;
+    const float gs = P.round(g[i] + ph.om_g * (geq - g[i]));
+    // streamed: slot (x, opp(i)) after an even step, (x + c_i, i) after an odd one
+    if (!ODD) { P.stf(opp(i), c, fs); P.stg(opp(i), c, gs); }
+    else { const long long n = N.template at<V>(i); P.stf(i, n, fs); P.stg(i, n, gs); }
   }
-  gs0 = g[0] + ph.om_g * ((phi - geq_rest) - g[0]);
-  P.stg(0, c, gs0);
+  const float g0s = g[0] + ph.om_g * ((phi - geq_rest) - g[0]);  // g_0 is stored in FP32
+  P.stg(0, c, g0s);
+  rho_out = rho;
+  phi_out = phi;
+}
+
+// Moving halfway bounce-back on the links of cell c into solid cells:
+//   f_opp(i)(x, t+1) = f*_i(x) - 2 w_i rho (c_i . u_w) / cs^2   (same for g with phi)
+// f*_i is read back from the slot collide_cell() wrote it to and the result
+// goes to the slot the cell reads direction opp(i) from next step: (x + c_i,
+// i) after an even step, (x, opp(i)) after an odd one.  Only cells next to
+// a solid take this path; keeping it after the branch-free main loop (rather
+// than a branch per direction inside it) holds the register count down.
+template <int Q, int S, int ODD>
+__device__ __forceinline__ void bounce_back(const Pops<Q, S> &P, const Nbr &N, long long c, uint32_t bits,
+                                         const uint8_t *__restrict__ mask, const Geom &G, const Phys &ph,
+                                         int x, int y, int z, float rho, float phi) {
+  using V = VSet<Q>;
+#pragma unroll
+  for (int i = 1; i < Q; ++i) {
+    if (!((bits >> i) & 1u)) continue;
+    const long long n = N.template at<V>(i);
+    const int sp = ODD ? i : opp(i);
+    const long long sc = ODD ? n : c;
+    const float fs = P.ldf(sp, sc), gs = P.ldg(sp, sc);
+    const int xs = wrap(x + V::cx(i), G.ex), ys = wrap(y + V::cy(i), G.ey);
+    const int zs = V::D == 3 ? wrap(z + V::cz(i), G.ez) : z;
+    float uw[3];
+    body_velocity<V>(G, ph, mask[n], x, y, z, xs, ys, zs, i, uw);
+    const float k = 6.0f * V::w(i) * (V::cx(i) * uw[0] + V::cy(i) * uw[1] + V::cz(i) * uw[2]);
+    const float fb = P.round(fs - k * rho), gb = P.round(gs - k * phi);
+    const int bp = ODD ? opp(i) : i;
+    const long long bc = ODD ? c : n;
+    P.stf(bp, bc, fb);
+    P.stg(bp, bc, gb);
+  }
+}
+
+template <int Q, int S, int ODD>
+__global__ __launch_bounds__(BX *BY) void k_collide(Pops<Q, S> P, const uint32_t *__restrict__ nbm,
+                                                    const uint8_t *__restrict__ mask,
+                                                    const float4 *__restrict__ C,
+                                                    const float *__restrict__ MUP, Geom G, Phys ph) {
+  int x, y, z;
+  long long c;
+  if (!cell_of_thread(G, x, y, z, c)) return;
+  const uint32_t bits = nbm[c];
+  if (bits & NB_SELF_SOLID) return;
+  const Nbr N(G, x, y, z);
+  float rho, phi;
+  collide_cell<Q, S, ODD>(P, N, c, C, MUP, ph, rho, phi);
+  if (bits != 0u) bounce_back<Q, S, ODD>(P, N, c, bits, mask, G, ph, x, y, z, rho, phi);
 }
 
 // Initialisation at equilibrium (Sec. 2.3).  M holds (rho0 - 1, phi0) with
@@ -297,11 +330,10 @@ __global__ __launch_bounds__(BX *BY) void k_init(Pops<Q, S> P, const uint32_t *_
   long long c;
   if (!cell_of_thread(G, x, y, z, c)) return;
   if (nbm[c] & NB_SELF_SOLID) return;
-  int nb[Q];
-  neighbours<Q>(G, x, y, z, nb);
+  const Nbr N(G, x, y, z);
   float2 m0 = M[c];
   float lr, lp, mr, mp;
-  laplacians<Q>(M, nb, m0, lr, lp);
+  laplacians<Q>(M, N, m0, lr, lp);
   chem_pot(ph, m0.x, m0.y, lr, lp, mr, mp);
   float4 u4 = U0[c];
   float u[3] = {u4.x, u4.y, u4.z};
@@ -337,10 +369,9 @@ __global__ __launch_bounds__(BX *BY) void k_observe(Pops<Q, S> P, const uint32_t
     OUT[c] = make_float4(0, 0, 0, 0);
     return;
   }
-  int nb[Q];
-  neighbours<Q>(G, x, y, z, nb);
+  const Nbr N(G, x, y, z);
   float df[Q], g[Q];
-  load_pops<Q, S>(P, nb, c, odd, df, g);
+  load_pops<Q, S>(P, N, c, odd, df, g);
   float j[3] = {0, 0, 0};
 #pragma unroll
   for (int i = 0; i < Q; ++i) {
@@ -351,7 +382,7 @@ __global__ __launch_bounds__(BX *BY) void k_observe(Pops<Q, S> P, const uint32_t
   float4 m0 = C[c];
   float mu_phi = MUP[c];
   float F[3];
-  force<Q>(C, nb, m0.w, mu_phi, F);
+  force<Q>(C, N, m0.w, mu_phi, F);
   float rho = 1.0f + m0.x;
   float inv = 1.0f / rho;
   float pres = rho / 3.0f + rho * m0.w + m0.y * mu_phi - psi_bulk(ph, rho, m0.y);
@@ -371,10 +402,9 @@ __global__ __launch_bounds__(BX *BY) void k_read_pops(Pops<Q, S> P, const uint32
     for (int i = 0; i < 2 * Q; ++i) out[i * G.ncell + c] = 0.0f;
     return;
   }
-  int nb[Q];
-  neighbours<Q>(G, x, y, z, nb);
+  const Nbr N(G, x, y, z);
   float df[Q], g[Q];
-  load_pops<Q, S>(P, nb, c, odd, df, g);
+  load_pops<Q, S>(P, N, c, odd, df, g);
 #pragma unroll
   for (int i = 0; i < Q; ++i) {
     out[i * G.ncell + c] = df[i] + V::w(i);
@@ -433,31 +463,52 @@ static dim3 cell_grid(const Geom &G) { return dim3((G.ex + BX - 1) / BX, (G.ey +
 static dim3 cell_block() { return dim3(BX, BY, 1); }
 static int fill_blocks(int n) { return (n + 255) / 256; }
 
-// The kernels of one step in order; ev (if not null) receives an event
-// before each launch and one after the last.
+// Coupling fields of the current state: solid fills of rho, phi, then
+// mu_rho, mu_phi, Pi, then the solid fill of Pi.
 template <int Q, int S>
-static void step_seq(const LaunchArgs &a, int odd, hipEvent_t *ev, bool collide) {
-  Pops<Q, S> P = make_pops<Q, S>(a);
+static void couple_seq(const LaunchArgs &a, hipEvent_t *ev, int &k) {
   dim3 gr = cell_grid(a.G), bl = cell_block();
-  int k = 0;
   auto mark = [&]() { if (ev) (void)hipEventRecord(ev[k++], a.stream); };
-  mark();
-  k_moments<Q, S><<<gr, bl, 0, a.stream>>>(P, a.nbm, a.M, a.G, odd);
-  mark();
   if (a.n_fill) k_fill_m<Q><<<fill_blocks(a.n_fill), 256, 0, a.stream>>>(a.M, a.fill_list, a.n_fill, a.mask, a.G);
   mark();
   k_potential<Q><<<gr, bl, 0, a.stream>>>(a.M, a.nbm, a.C, a.MUP, a.G, a.ph);
   mark();
   if (a.n_fill) k_fill_c<Q><<<fill_blocks(a.n_fill), 256, 0, a.stream>>>(a.C, a.M, a.fill_list, a.n_fill, a.mask, a.G);
   mark();
-  if (collide) k_collide<Q, S><<<gr, bl, 0, a.stream>>>(P, a.nbm, a.mask, a.C, a.MUP, a.G, a.ph, odd);
-  else k_observe<Q, S><<<gr, bl, 0, a.stream>>>(P, a.nbm, a.C, a.MUP, a.AUX, a.G, a.ph, odd);
-  mark();
 }
 
-template <int Q, int S> static void step_impl(const LaunchArgs &a, int odd) { step_seq<Q, S>(a, odd, nullptr, true); }
-template <int Q, int S> static void step_events_impl(const LaunchArgs &a, int odd, hipEvent_t *ev) { step_seq<Q, S>(a, odd, ev, true); }
-template <int Q, int S> static void observe_impl(const LaunchArgs &a, int odd) { step_seq<Q, S>(a, odd, nullptr, false); }
+template <int Q, int S>
+static void moments_launch(const LaunchArgs &a, int odd) {
+  if (odd) k_moments<Q, S, 1><<<cell_grid(a.G), cell_block(), 0, a.stream>>>(make_pops<Q, S>(a), a.nbm, a.M, a.G);
+  else k_moments<Q, S, 0><<<cell_grid(a.G), cell_block(), 0, a.stream>>>(make_pops<Q, S>(a), a.nbm, a.M, a.G);
+}
+
+// One step: moments, coupling fields, collide + stream.  ev (if not null)
+// receives an event before the first launch and after each.
+template <int Q, int S>
+static void step_seq(const LaunchArgs &a, int odd, hipEvent_t *ev) {
+  Pops<Q, S> P = make_pops<Q, S>(a);
+  int k = 0;
+  if (ev) (void)hipEventRecord(ev[k++], a.stream);
+  moments_launch<Q, S>(a, odd);
+  if (ev) (void)hipEventRecord(ev[k++], a.stream);
+  couple_seq<Q, S>(a, ev, k);
+  if (odd) k_collide<Q, S, 1><<<cell_grid(a.G), cell_block(), 0, a.stream>>>(P, a.nbm, a.mask, a.C, a.MUP, a.G, a.ph);
+  else k_collide<Q, S, 0><<<cell_grid(a.G), cell_block(), 0, a.stream>>>(P, a.nbm, a.mask, a.C, a.MUP, a.G, a.ph);
+  if (ev) (void)hipEventRecord(ev[k++], a.stream);
+}
+
+template <int Q, int S> static void step_impl(const LaunchArgs &a, int odd) { step_seq<Q, S>(a, odd, nullptr); }
+template <int Q, int S> static void step_events_impl(const LaunchArgs &a, int odd, hipEvent_t *ev) { step_seq<Q, S>(a, odd, ev); }
+
+
+template <int Q, int S>
+static void observe_impl(const LaunchArgs &a, int odd) {
+  int k = 0;
+  moments_launch<Q, S>(a, odd);
+  couple_seq<Q, S>(a, nullptr, k);
+  k_observe<Q, S><<<cell_grid(a.G), cell_block(), 0, a.stream>>>(make_pops<Q, S>(a), a.nbm, a.C, a.MUP, a.AUX, a.G, a.ph, odd);
+}
 
 template <int Q, int S>
 static void init_impl(const LaunchArgs &a) {

@@ -119,6 +119,8 @@ template <int Q, int S> struct Pops;
 
 template <int Q> struct Pops<Q, 0> {
   float *f, *g;
+  // the value a store keeps (identity for FP32)
+  __device__ __forceinline__ float round(float v) const { return v; }
   __device__ __forceinline__ float ldf(int i, long long c) const { return f[blk_index(Q, i, c)]; }
   __device__ __forceinline__ float ldg(int i, long long c) const { return g[blk_index(Q, i, c)]; }
   __device__ __forceinline__ void stf(int i, long long c, float v) const { f[blk_index(Q, i, c)] = v; }
@@ -128,6 +130,8 @@ template <int Q> struct Pops<Q, 0> {
 template <int Q> struct Pops<Q, 1> {
   __half *f, *g;  // g holds directions 1..q-1
   float *g0;
+  // the value a half store keeps (g_0 is stored in FP32 and not rounded)
+  __device__ __forceinline__ float round(float v) const { return __half2float(__float2half_rn(v)); }
   __device__ __forceinline__ float ldf(int i, long long c) const { return __half2float(f[blk_index(Q, i, c)]); }
   __device__ __forceinline__ float ldg(int i, long long c) const {
     return i == 0 ? g0[c] : __half2float(g[blk_index(Q - 1, i - 1, c)]);
