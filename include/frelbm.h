@@ -176,8 +176,52 @@ fre_status fre_profile_step(fre_lattice *L, int64_t n, double *kernel_ms,
                             int32_t max_kernels, int32_t *n_kernels);
 const char *fre_kernel_name(int32_t k);
 
-/* Release the handle (accepts NULL).  Never frees caller memory. */
+/* Release the handle (accepts NULL).  Never frees caller memory.  A batch
+ * member is removed from its batch first. */
 void fre_lattice_destroy(fre_lattice *L);
+
+/* ---------------------------------------------------------------------------
+ * Batches: many lattices of different sizes, velocity sets and storage
+ * precisions advanced together.  Each step runs, per (velocity set, storage)
+ * class present, one persistent launch per stage of the step over a
+ * device-side list of (lattice, block) work items; the list and its length
+ * live in device memory, so lattices join and leave without recapturing the
+ * batch's HIP graph.  A lattice advanced inside a batch takes exactly the
+ * arithmetic it takes alone (bitwise the same populations).
+ * ------------------------------------------------------------------------- */
+
+/* Device bytes of a batch's tables for max_slots lattices, max_work cell
+ * work items and max_fill solid-boundary items in total (see
+ * fre_lattice_batch_needs).  No device work. */
+fre_status fre_batch_footprint(int32_t max_slots, int64_t max_work, int64_t max_fill, size_t *bytes);
+
+/* Work items a lattice adds to a batch (cell blocks, solid-boundary cells). */
+fre_status fre_lattice_batch_needs(const fre_lattice *L, int64_t *n_work, int64_t *n_fill);
+
+/* Create a batch in the caller's device buffer (>= fre_batch_footprint,
+ * 256-byte aligned); its steps run on hip_stream.  Freed with
+ * fre_batch_destroy, which never frees caller memory. */
+fre_status fre_batch_create(void *device_buf, size_t bytes, void *hip_stream, int32_t max_slots,
+                            int64_t max_work, int64_t max_fill, fre_batch **out);
+
+/* Add a lattice (not in another batch, not failed); *slot receives its slot.
+ * All members share the AA parity: a lattice one step out of phase is first
+ * advanced one step on its own.  FRE_ENOMEM when the slots or work lists
+ * are full.  While a member, the lattice is stepped only through the batch;
+ * reads, reductions and checkpoints of it wait for the batch's stream. */
+fre_status fre_batch_add(fre_batch *B, fre_lattice *L, int32_t *slot);
+
+/* Remove the lattice in `slot` (waits for the batch's stream). */
+fre_status fre_batch_remove(fre_batch *B, int32_t slot);
+
+/* Advance every member n >= 0 steps, asynchronously on the batch's stream.
+ * FRE_ESTATE if a member has failed. */
+fre_status fre_batch_step(fre_batch *B, int64_t n);
+
+/* Number of members and the common AA parity. */
+fre_status fre_batch_info(const fre_batch *B, int32_t *members, int32_t *parity);
+
+void fre_batch_destroy(fre_batch *B);
 
 /* Thread-local message of the last failing call on this thread. */
 const char *fre_last_error(void);

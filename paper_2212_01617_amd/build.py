@@ -15,7 +15,10 @@ LIB = os.path.join(HERE, "libfrelbm.so")
 SOURCES = ["kernels.hip", "api.hip"]
 
 # -packed-fp32-ops: keep the compiler from emitting packed FP32 instructions.
-HIPFLAGS = ["--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC",
+# -ffp-contract=on: fuse a*b+c only where one source expression says so, so
+# every kernel that inlines the same per-cell code (single lattice, batch)
+# rounds identically.
+HIPFLAGS = ["--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC", "-ffp-contract=on",
             "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
             "-Wall", "-Wno-unused-function"]
 

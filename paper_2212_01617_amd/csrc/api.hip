@@ -9,6 +9,7 @@
 // into a HIP graph and replayed.
 #include <hip/hip_runtime.h>
 
+#include <climits>
 #include <cmath>
 #include <cstdarg>
 #include <cstdio>
@@ -65,8 +66,15 @@ fre_status validate(const fre_params *p) {
     if (p->bc[a] != FRE_PERIODIC && p->bc[a] != FRE_WALL) return fail(FRE_EINVAL, "bc[%d]=%d", a, p->bc[a]);
   if (p->kind == FRE_D2Q9 && (p->nz != 1 || p->bc[2] != FRE_PERIODIC))
     return fail(FRE_EINVAL, "D2Q9 needs nz = 1 and a periodic z axis");
-  double cells = (double)(p->nx + 2) * (p->ny + 2) * (p->nz + 2);
-  if (cells > 2.0e9) return fail(FRE_EINVAL, "lattice too large for 32-bit cell indices");
+  {
+    // population arrays are addressed with 32-bit byte offsets
+    const int q = p->kind == FRE_D2Q9 ? 9 : 19;
+    const double px = std::ceil((p->nx + (p->bc[0] == FRE_WALL ? 2.0 : 0.0)) / 64.0) * 64.0;
+    const double cells = px * (p->ny + (p->bc[1] == FRE_WALL ? 2.0 : 0.0)) * (p->nz + (p->bc[2] == FRE_WALL ? 2.0 : 0.0));
+    const double bytes = cells * q * (p->storage == FRE_FP32 ? 4.0 : 2.0);
+    if (bytes >= 4294967296.0 || cells >= 1073741824.0)
+      return fail(FRE_EINVAL, "lattice too large: a population array would exceed 4 GiB (%.0f cells)", cells);
+  }
   if (!(p->tau_f > 0.5) || !(p->tau_g > 0.5)) return fail(FRE_EINVAL, "tau_f, tau_g must exceed 1/2");
   if (!(p->M > 0.0) || !std::isfinite(p->M)) return fail(FRE_EINVAL, "mobility M must be > 0");
   if (p->use_paper_form) {
@@ -110,7 +118,9 @@ Plan make_plan(const fre_params *p) {
     P.o_g = take((size_t)P.q * P.ncell * 4);
     P.o_g0 = 0;
   } else {
-    P.o_g = take((size_t)(P.q - 1) * P.ncell * 2);
+    // plane 0 of the half array is unused (g_0 lives in an FP32 plane), so
+    // f and g share every block offset
+    P.o_g = take((size_t)P.q * P.ncell * 2);
     P.o_g0 = take((size_t)P.ncell * 4);
   }
   P.o_mask = take((size_t)P.ncell);
@@ -166,6 +176,28 @@ struct fre_lattice {
   std::vector<int> fill_host;
   hipGraphExec_t graph;  // two steps starting at even parity
   bool graph_ok;
+  fre_batch *batch;      // non-null while the lattice is a batch member
+};
+
+struct fre_batch {
+  uint8_t *base;
+  size_t bytes;
+  hipStream_t stream;
+  int max_slots, cap_work, cap_fill;
+  Inst *d_inst;
+  int4 *d_work;
+  int2 *d_fill;
+  int *d_range;  // [4 classes][cells start, n, fills start, n]
+  std::vector<fre_lattice *> slot;
+  std::vector<Inst> h_inst;
+  std::vector<int4> h_work;
+  std::vector<int2> h_fill;
+  std::vector<int> h_range;
+  int parity;         // common AA parity of the members
+  unsigned classes;   // bit c: class c has members
+  hipGraphExec_t graph;
+  bool graph_ok;
+  int grid_cells, grid_fill;
 };
 
 namespace {
@@ -173,6 +205,13 @@ namespace {
 void reset_graph(fre_lattice *L) {
   if (L->graph_ok) (void)hipGraphExecDestroy(L->graph);
   L->graph_ok = false;
+}
+
+// A batch member's state is advanced on the batch's stream: wait for it
+// before touching the lattice on its own stream.
+fre_status sync_batch(fre_lattice *L) {
+  if (L && L->batch) HIP_TRY(hipStreamSynchronize(L->batch->stream));
+  return FRE_OK;
 }
 
 long long ext_index(const Plan &P, int x, int y, int z) {
@@ -353,6 +392,7 @@ fre_status fre_set_params(fre_lattice *L, const fre_params *p) {
   if (!L) return fail(FRE_EINVAL, "lattice is NULL");
   fre_status s = validate(p);
   if (s != FRE_OK) return s;
+  if (L->batch) return fail(FRE_ESTATE, "lattice is a batch member: remove it before changing parameters");
   const fre_params &o = L->p;
   if (p->kind != o.kind || p->nx != o.nx || p->ny != o.ny || p->nz != o.nz || p->storage != o.storage ||
       p->bc[0] != o.bc[0] || p->bc[1] != o.bc[1] || p->bc[2] != o.bc[2] || p->n_rollers != o.n_rollers)
@@ -367,6 +407,7 @@ fre_status fre_step(fre_lattice *L, int64_t n) {
   if (!L) return fail(FRE_EINVAL, "lattice is NULL");
   if (n < 0) return fail(FRE_EINVAL, "negative step count");
   if (L->state) return fail(FRE_ESTATE, "lattice is in the failed state");
+  if (L->batch) return fail(FRE_ESTATE, "lattice is a batch member: step the batch");
   hipStream_t st = L->a.stream;
   auto one = [&]() -> fre_status {
     launch_step(L->a, (int)(L->t & 1));
@@ -408,6 +449,7 @@ fre_status fre_step(fre_lattice *L, int64_t n) {
 
 fre_status fre_read_moments(fre_lattice *L, uint32_t field_mask, double *host_out, size_t n_doubles) {
   if (!L || !host_out) return fail(FRE_EINVAL, "NULL argument");
+  if (fre_status bs = sync_batch(L)) return bs;
   if (field_mask == 0 || (field_mask & ~63u)) return fail(FRE_EINVAL, "bad field mask 0x%x", field_mask);
   size_t need = 0;
   const long long N = L->n_user;
@@ -457,6 +499,7 @@ fre_status fre_read_moments(fre_lattice *L, uint32_t field_mask, double *host_ou
 
 fre_status fre_read_populations(fre_lattice *L, double *f_out, double *g_out, size_t n_doubles_each) {
   if (!L || !f_out || !g_out) return fail(FRE_EINVAL, "NULL argument");
+  if (fre_status bs = sync_batch(L)) return bs;
   const Plan &P = L->plan;
   const long long N = L->n_user;
   if (n_doubles_each < (size_t)P.q * N) return fail(FRE_EINVAL, "outputs need q*N doubles each");
@@ -485,6 +528,7 @@ fre_status fre_read_populations(fre_lattice *L, double *f_out, double *g_out, si
 
 fre_status fre_reduce(fre_lattice *L, double out[8]) {
   if (!L || !out) return fail(FRE_EINVAL, "NULL argument");
+  if (fre_status bs = sync_batch(L)) return bs;
   fre_status s = observe(L);
   if (s != FRE_OK) return s;
   double *part = (double *)(L->base + L->plan.o_part);
@@ -529,6 +573,7 @@ fre_status fre_state_bytes(const fre_lattice *L, size_t *bytes) {
 }
 
 fre_status fre_save(fre_lattice *L, void *host, size_t bytes) {
+  if (fre_status bs = sync_batch(L)) return bs;
   size_t need;
   fre_status s = fre_state_bytes(L, &need);
   if (s != FRE_OK) return s;
@@ -548,6 +593,7 @@ fre_status fre_save(fre_lattice *L, void *host, size_t bytes) {
 
 fre_status fre_load(fre_lattice *L, const void *host, size_t bytes) {
   if (!L || !host || bytes < sizeof(CkptHeader)) return fail(FRE_EINVAL, "bad checkpoint buffer");
+  if (L->batch) return fail(FRE_ESTATE, "lattice is a batch member: remove it before loading");
   CkptHeader h;
   memcpy(&h, host, sizeof h);
   if (memcmp(h.magic, "FRELBM01", 8) != 0 || h.version != 1) return fail(FRE_EINVAL, "not a checkpoint");
@@ -570,6 +616,7 @@ fre_status fre_profile_step(fre_lattice *L, int64_t n, double *kernel_ms, int32_
   if (L->state) return fail(FRE_ESTATE, "lattice is in the failed state");
   const int K = step_kernel_count();
   if (max_kernels < K) return fail(FRE_EINVAL, "kernel_ms needs %d entries", K);
+  if (L->batch) return fail(FRE_ESTATE, "lattice is a batch member: profile it alone");
   std::vector<hipEvent_t> ev((size_t)(K + 1) * n);
   for (auto &e : ev) HIP_TRY(hipEventCreate(&e));
   for (int k = 0; k < K; ++k) kernel_ms[k] = 0.0;
@@ -600,8 +647,282 @@ const char *fre_kernel_name(int32_t k) { return step_kernel_name(k); }
 
 void fre_lattice_destroy(fre_lattice *L) {
   if (!L) return;
+  if (L->batch) {
+    fre_batch *B = L->batch;
+    for (size_t k = 0; k < B->slot.size(); ++k)
+      if (B->slot[k] == L) fre_batch_remove(B, (int32_t)k);
+  }
   reset_graph(L);
   delete L;
+}
+
+// ---------------------------------------------------------------------------
+// Batches
+// ---------------------------------------------------------------------------
+namespace {
+
+struct BatchPlan {
+  size_t o_inst, o_work, o_fill, o_range, total;
+};
+
+BatchPlan batch_plan(int max_slots, int64_t max_work, int64_t max_fill) {
+  BatchPlan P{};
+  size_t o = 0;
+  auto take = [&](size_t b) { size_t at = o; o = align_up(o + b, kAlign); return at; };
+  P.o_inst = take((size_t)max_slots * sizeof(Inst));
+  P.o_work = take((size_t)max_work * sizeof(int4));
+  P.o_fill = take((size_t)max_fill * sizeof(int2));
+  P.o_range = take(16 * sizeof(int));
+  P.total = o;
+  return P;
+}
+
+void lattice_needs(const fre_lattice *L, int64_t *n_work, int64_t *n_fill) {
+  const Geom &G = L->a.G;
+  *n_work = (int64_t)((G.ex + 63) / 64) * ((G.ey + 3) / 4) * G.ez;
+  *n_fill = (int64_t)L->fill_host.size();
+}
+
+long long rel(const void *p, const void *base) { return (long long)((uintptr_t)p - (uintptr_t)base); }
+
+Inst inst_of(const fre_lattice *L, const void *base) {
+  Inst I{};
+  I.G = L->a.G;
+  I.ph = L->a.ph;
+  I.f = rel(L->a.f, base);
+  I.g = rel(L->a.g, base);
+  I.g0 = L->a.g0 ? rel(L->a.g0, base) : 0;
+  I.mask = rel(L->a.mask, base);
+  I.nbm = rel(L->a.nbm, base);
+  I.M = rel(L->a.M, base);
+  I.C = rel(L->a.C, base);
+  I.MUP = rel(L->a.MUP, base);
+  I.fill = rel(L->a.fill_list, base);
+  I.n_fill = L->a.n_fill;
+  return I;
+}
+
+void batch_reset_graph(fre_batch *B) {
+  if (B->graph_ok) (void)hipGraphExecDestroy(B->graph);
+  B->graph_ok = false;
+}
+
+// Rebuild and upload the instance table and the work lists, grouped by
+// class; the ranges tell each class's persistent kernels what to walk.
+fre_status batch_rebuild(fre_batch *B) {
+  HIP_TRY(hipStreamSynchronize(B->stream));
+  B->h_inst.assign(B->slot.size(), Inst{});
+  B->h_work.clear();
+  B->h_fill.clear();
+  B->h_range.assign(16, 0);
+  unsigned classes = 0;
+  for (int cls = 0; cls < 4; ++cls) {
+    B->h_range[4 * cls + 0] = (int)B->h_work.size();
+    B->h_range[4 * cls + 2] = (int)B->h_fill.size();
+    for (size_t k = 0; k < B->slot.size(); ++k) {
+      fre_lattice *L = B->slot[k];
+      if (!L || batch_class(L->a.q, L->a.storage) != cls) continue;
+      classes |= 1u << cls;
+      B->h_inst[k] = inst_of(L, B->base);
+      const Geom &G = L->a.G;
+      for (int z = 0; z < G.ez; ++z)
+        for (int by = 0; by < (G.ey + 3) / 4; ++by)
+          for (int bx = 0; bx < (G.ex + 63) / 64; ++bx) B->h_work.push_back(make_int4((int)k, bx, by, z));
+      for (int s : L->fill_host) B->h_fill.push_back(make_int2((int)k, s));
+    }
+    B->h_range[4 * cls + 1] = (int)B->h_work.size() - B->h_range[4 * cls + 0];
+    B->h_range[4 * cls + 3] = (int)B->h_fill.size() - B->h_range[4 * cls + 2];
+  }
+  if ((int64_t)B->h_work.size() > B->cap_work || (int64_t)B->h_fill.size() > B->cap_fill)
+    return fail(FRE_ENOMEM, "batch work lists exceed their capacity (%zu/%d cells, %zu/%d fills)",
+                B->h_work.size(), B->cap_work, B->h_fill.size(), B->cap_fill);
+  if (!B->h_inst.empty())
+    HIP_TRY(hipMemcpyAsync(B->d_inst, B->h_inst.data(), B->h_inst.size() * sizeof(Inst), hipMemcpyHostToDevice, B->stream));
+  if (!B->h_work.empty())
+    HIP_TRY(hipMemcpyAsync(B->d_work, B->h_work.data(), B->h_work.size() * sizeof(int4), hipMemcpyHostToDevice, B->stream));
+  if (!B->h_fill.empty())
+    HIP_TRY(hipMemcpyAsync(B->d_fill, B->h_fill.data(), B->h_fill.size() * sizeof(int2), hipMemcpyHostToDevice, B->stream));
+  HIP_TRY(hipMemcpyAsync(B->d_range, B->h_range.data(), 16 * sizeof(int), hipMemcpyHostToDevice, B->stream));
+  HIP_TRY(hipStreamSynchronize(B->stream));
+  if (classes != B->classes) batch_reset_graph(B);  // the graph launches one sequence per class
+  B->classes = classes;
+  return FRE_OK;
+}
+
+BatchArgs batch_args(const fre_batch *B) {
+  BatchArgs b;
+  b.base = (char *)B->base;
+  b.inst = B->d_inst;
+  b.work = B->d_work;
+  b.fill = B->d_fill;
+  b.range = B->d_range;
+  b.grid_cells = B->grid_cells;
+  b.grid_fill = B->grid_fill;
+  b.stream = B->stream;
+  return b;
+}
+
+void batch_launch_step(const fre_batch *B, int odd) {
+  const BatchArgs b = batch_args(B);
+  for (int cls = 0; cls < 4; ++cls)
+    if (B->classes & (1u << cls)) launch_batch_step(b, cls, odd);
+}
+
+}  // namespace
+
+fre_status fre_batch_footprint(int32_t max_slots, int64_t max_work, int64_t max_fill, size_t *bytes) {
+  if (max_slots < 1 || max_work < 1 || max_fill < 0 || !bytes) return fail(FRE_EINVAL, "bad batch capacities");
+  if (max_work > INT32_MAX || max_fill > INT32_MAX) return fail(FRE_EINVAL, "batch capacities exceed 2^31");
+  *bytes = batch_plan(max_slots, max_work, max_fill).total;
+  return FRE_OK;
+}
+
+fre_status fre_lattice_batch_needs(const fre_lattice *L, int64_t *n_work, int64_t *n_fill) {
+  if (!L || !n_work || !n_fill) return fail(FRE_EINVAL, "NULL argument");
+  lattice_needs(L, n_work, n_fill);
+  return FRE_OK;
+}
+
+fre_status fre_batch_create(void *device_buf, size_t bytes, void *hip_stream, int32_t max_slots,
+                            int64_t max_work, int64_t max_fill, fre_batch **out) {
+  if (!out) return fail(FRE_EINVAL, "out is NULL");
+  *out = nullptr;
+  size_t need;
+  fre_status s = fre_batch_footprint(max_slots, max_work, max_fill, &need);
+  if (s != FRE_OK) return s;
+  if (!device_buf || (uintptr_t)device_buf % kAlign) return fail(FRE_EINVAL, "device_buf must be 256-byte aligned");
+  if (bytes < need) return fail(FRE_ENOMEM, "batch buffer of %zu bytes < %zu", bytes, need);
+  const BatchPlan P = batch_plan(max_slots, max_work, max_fill);
+  fre_batch *B = new fre_batch();
+  B->base = (uint8_t *)device_buf;
+  B->bytes = bytes;
+  B->stream = (hipStream_t)hip_stream;
+  B->max_slots = max_slots;
+  B->cap_work = (int)max_work;
+  B->cap_fill = (int)max_fill;
+  B->d_inst = (Inst *)(B->base + P.o_inst);
+  B->d_work = (int4 *)(B->base + P.o_work);
+  B->d_fill = (int2 *)(B->base + P.o_fill);
+  B->d_range = (int *)(B->base + P.o_range);
+  B->slot.assign(max_slots, nullptr);
+  B->parity = 0;
+  B->classes = 0;
+  B->graph_ok = false;
+  int dev = 0, ncu = 256;
+  if (hipGetDevice(&dev) == hipSuccess) {
+    int v = 0;
+    if (hipDeviceGetAttribute(&v, hipDeviceAttributeMultiprocessorCount, dev) == hipSuccess && v > 0) ncu = v;
+  }
+  B->grid_cells = ncu * 8;
+  B->grid_fill = ncu * 2;
+  s = batch_rebuild(B);
+  if (s != FRE_OK) { delete B; return s; }
+  *out = B;
+  return FRE_OK;
+}
+
+fre_status fre_batch_add(fre_batch *B, fre_lattice *L, int32_t *slot) {
+  if (!B || !L || !slot) return fail(FRE_EINVAL, "NULL argument");
+  if (L->batch) return fail(FRE_EINVAL, "lattice is already a batch member");
+  if (L->state) return fail(FRE_ESTATE, "lattice is in the failed state");
+  int free_slot = -1, members = 0;
+  for (int k = 0; k < B->max_slots; ++k) {
+    if (B->slot[k]) ++members;
+    else if (free_slot < 0) free_slot = k;
+  }
+  if (free_slot < 0) return fail(FRE_ENOMEM, "batch is full (%d slots)", B->max_slots);
+  // all members share the AA parity; a lattice one step out of phase takes
+  // one step on its own first (the same arithmetic as inside the batch)
+  if (members == 0) {
+    B->parity = (int)(L->t & 1);
+    batch_reset_graph(B);
+  } else if ((int)(L->t & 1) != B->parity) {
+    fre_status s = fre_step(L, 1);
+    if (s != FRE_OK) return s;
+  }
+  HIP_TRY(hipStreamSynchronize(L->a.stream));
+  B->slot[free_slot] = L;
+  L->batch = B;
+  fre_status s = batch_rebuild(B);
+  if (s != FRE_OK) {
+    B->slot[free_slot] = nullptr;
+    L->batch = nullptr;
+    (void)batch_rebuild(B);
+    return s;
+  }
+  *slot = free_slot;
+  return FRE_OK;
+}
+
+fre_status fre_batch_remove(fre_batch *B, int32_t slot) {
+  if (!B || slot < 0 || slot >= B->max_slots || !B->slot[slot]) return fail(FRE_EINVAL, "no lattice in that slot");
+  fre_lattice *L = B->slot[slot];
+  HIP_TRY(hipStreamSynchronize(B->stream));
+  B->slot[slot] = nullptr;
+  L->batch = nullptr;
+  return batch_rebuild(B);
+}
+
+fre_status fre_batch_step(fre_batch *B, int64_t n) {
+  if (!B) return fail(FRE_EINVAL, "batch is NULL");
+  if (n < 0) return fail(FRE_EINVAL, "negative step count");
+  if (!B->classes || n == 0) return FRE_OK;
+  for (fre_lattice *L : B->slot)
+    if (L && L->state) return fail(FRE_ESTATE, "a member lattice is in the failed state");
+  hipStream_t st = B->stream;
+  int64_t done = 0;
+  auto one = [&]() -> fre_status {
+    batch_launch_step(B, B->parity);
+    HIP_TRY(hipGetLastError());
+    B->parity ^= 1;
+    ++done;
+    return FRE_OK;
+  };
+  fre_status s = FRE_OK;
+  if (st == nullptr || n < 4) {
+    for (int64_t k = 0; k < n && s == FRE_OK; ++k) s = one();
+  } else {
+    if (B->parity) { s = one(); --n; }
+    if (s == FRE_OK && !B->graph_ok) {
+      hipGraph_t g;
+      HIP_TRY(hipStreamBeginCapture(st, hipStreamCaptureModeThreadLocal));
+      batch_launch_step(B, 0);
+      batch_launch_step(B, 1);
+      hipError_t e = hipStreamEndCapture(st, &g);
+      if (e != hipSuccess) return fail(FRE_EDEVICE, "batch graph capture failed: %s", hipGetErrorString(e));
+      e = hipGraphInstantiate(&B->graph, g, nullptr, nullptr, 0);
+      (void)hipGraphDestroy(g);
+      if (e != hipSuccess) return fail(FRE_EDEVICE, "batch graph instantiate failed: %s", hipGetErrorString(e));
+      B->graph_ok = true;
+    }
+    for (int64_t k = 0; s == FRE_OK && k + 1 < n; k += 2) {
+      hipError_t e = hipGraphLaunch(B->graph, st);
+      if (e != hipSuccess) s = fail(FRE_EDEVICE, "batch graph launch failed: %s", hipGetErrorString(e));
+      else done += 2;
+    }
+    if (s == FRE_OK && (n & 1)) s = one();
+  }
+  for (fre_lattice *L : B->slot)
+    if (L) L->t += done;
+  return s;
+}
+
+fre_status fre_batch_info(const fre_batch *B, int32_t *members, int32_t *parity) {
+  if (!B) return fail(FRE_EINVAL, "batch is NULL");
+  int m = 0;
+  for (fre_lattice *L : B->slot) m += L != nullptr;
+  if (members) *members = m;
+  if (parity) *parity = B->parity;
+  return FRE_OK;
+}
+
+void fre_batch_destroy(fre_batch *B) {
+  if (!B) return;
+  (void)hipStreamSynchronize(B->stream);
+  for (fre_lattice *L : B->slot)
+    if (L) L->batch = nullptr;
+  batch_reset_graph(B);
+  delete B;
 }
 
 }  // extern "C"

@@ -34,6 +34,54 @@ template <> inline Pops<19, 0> make_pops<19, 0>(const LaunchArgs &a) { return Po
 template <> inline Pops<9, 1> make_pops<9, 1>(const LaunchArgs &a) { return Pops<9, 1>{(__half *)a.f, (__half *)a.g, a.g0}; }
 template <> inline Pops<19, 1> make_pops<19, 1>(const LaunchArgs &a) { return Pops<19, 1>{(__half *)a.f, (__half *)a.g, a.g0}; }
 
+// Device view of one lattice for the kernels of one (velocity set, storage)
+// class.
+template <int Q, int S> struct LatView {
+  Pops<Q, S> P;
+  const uint32_t *nbm;
+  const uint8_t *mask;
+  float2 *M;
+  float4 *C;
+  float *MUP;
+  Geom G;
+  Phys ph;
+  const int *fill;
+  int n_fill;
+};
+
+// One slot of a batch, as stored in device memory.  Arrays are given as
+// byte offsets from the batch's base pointer (a kernel argument), so the
+// kernels address them as global memory, as they do kernel-argument pointers.
+struct Inst {
+  Geom G;
+  Phys ph;
+  long long f, g, g0, mask, nbm, M, C, MUP, fill;
+  int n_fill;
+};
+
+template <int Q, int S>
+__host__ __device__ inline Pops<Q, S> pops_of(void *f, void *g, float *g0);
+template <> __host__ __device__ inline Pops<9, 0> pops_of<9, 0>(void *f, void *g, float *) { return Pops<9, 0>{(float *)f, (float *)g}; }
+template <> __host__ __device__ inline Pops<19, 0> pops_of<19, 0>(void *f, void *g, float *) { return Pops<19, 0>{(float *)f, (float *)g}; }
+template <> __host__ __device__ inline Pops<9, 1> pops_of<9, 1>(void *f, void *g, float *g0) { return Pops<9, 1>{(__half *)f, (__half *)g, g0}; }
+template <> __host__ __device__ inline Pops<19, 1> pops_of<19, 1>(void *f, void *g, float *g0) { return Pops<19, 1>{(__half *)f, (__half *)g, g0}; }
+
+// Device tables of a batch.  range[4*cls + 0..1]: start and length of the
+// class's cell work items; range[4*cls + 2..3]: the same for fill items.
+struct BatchArgs {
+  char *base;  // origin of the Inst offsets
+  const Inst *inst;
+  const int4 *work;
+  const int2 *fill;
+  const int *range;
+  int grid_cells, grid_fill;
+  hipStream_t stream;
+};
+
+// class index of a (velocity set, storage) pair
+inline int batch_class(int q, int storage) { return (q == 19 ? 2 : 0) + storage; }
+
+void launch_batch_step(const BatchArgs &b, int cls, int odd);
 void launch_step(const LaunchArgs &a, int odd);
 void launch_step_events(const LaunchArgs &a, int odd, hipEvent_t *ev);
 int step_kernel_count();

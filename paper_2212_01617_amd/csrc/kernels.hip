@@ -76,23 +76,26 @@ __device__ __forceinline__ void load_pops(const Pops<Q, S> &P, const Nbr &N, lon
 }
 
 // ---------------------------------------------------------------------------
+// ---------------------------------------------------------------------------
+// Stages of one step, per cell (or per solid boundary cell for the fills).
+// The single-lattice kernels and the batched persistent kernels below both
+// call these, so a lattice advanced alone or inside a batch takes exactly
+// the same arithmetic.
+// ---------------------------------------------------------------------------
 template <int Q, int S, int ODD>
-__global__ __launch_bounds__(BX *BY) void k_moments(Pops<Q, S> P, const uint32_t *__restrict__ nbm,
-                                                    float2 *__restrict__ M, Geom G) {
-  int x, y, z;
-  long long c;
-  if (!cell_of_thread(G, x, y, z, c)) return;
-  if (nbm[c] & NB_SELF_SOLID) return;
-  const Nbr N(G, x, y, z);
+__device__ __forceinline__ void stage_moments(const LatView<Q, S> &L, int x, int y, int z) {
+  const long long c = (long long)x + (long long)L.G.px * ((long long)y + (long long)L.G.ey * z);
+  if (L.nbm[c] & NB_SELF_SOLID) return;
+  const Nbr N(L.G, x, y, z);
   float df[Q], g[Q];
-  load_pops<Q, S>(P, N, c, ODD, df, g);
+  load_pops<Q, S>(L.P, N, c, ODD, df, g);
   float drho = 0.0f, phi = 0.0f;
 #pragma unroll
   for (int i = 0; i < Q; ++i) {
     drho += df[i];
     phi += g[i];
   }
-  M[c] = make_float2(drho, phi);
+  L.M[c] = make_float2(drho, phi);
 }
 
 // Weighted mean over the fluid neighbours of solid cell s (coordinates x, y,
@@ -132,32 +135,25 @@ __device__ __forceinline__ void cell_coords(const Geom &G, int s, int &x, int &y
 }
 
 // Solid cells next to fluid take the lattice-weighted mean of their fluid
-// neighbours: rho, phi into M.
-template <int Q>
-__global__ __launch_bounds__(256) void k_fill_m(float2 *__restrict__ M, const int *__restrict__ list, int n,
-                                                const uint8_t *__restrict__ mask, Geom G) {
-  int k = blockIdx.x * blockDim.x + threadIdx.x;
-  if (k >= n) return;
-  int s = list[k], x, y, z;
-  cell_coords(G, s, x, y, z);
+// neighbours: rho, phi into M ...
+template <int Q, int S>
+__device__ __forceinline__ void stage_fill_m(const LatView<Q, S> &L, int s) {
+  int x, y, z;
+  cell_coords(L.G, s, x, y, z);
   float v[2];
-  fluid_mean<Q, 2, 2>((const float *)M, mask, G, x, y, z, v);
-  M[s] = make_float2(v[0], v[1]);
+  fluid_mean<Q, 2, 2>((const float *)L.M, L.mask, L.G, x, y, z, v);
+  L.M[s] = make_float2(v[0], v[1]);
 }
 
 // ... and Pi into C (with the filled rho, phi copied from M).
-template <int Q>
-__global__ __launch_bounds__(256) void k_fill_c(float4 *__restrict__ C, const float2 *__restrict__ M,
-                                                const int *__restrict__ list, int n,
-                                                const uint8_t *__restrict__ mask, Geom G) {
-  int k = blockIdx.x * blockDim.x + threadIdx.x;
-  if (k >= n) return;
-  int s = list[k], x, y, z;
-  cell_coords(G, s, x, y, z);
+template <int Q, int S>
+__device__ __forceinline__ void stage_fill_c(const LatView<Q, S> &L, int s) {
+  int x, y, z;
+  cell_coords(L.G, s, x, y, z);
   float pi;
-  fluid_mean<Q, 1, 4>((const float *)C + 2, mask, G, x, y, z, &pi);
-  float2 m = M[s];
-  C[s] = make_float4(m.x, m.y, pi, 0.0f);
+  fluid_mean<Q, 1, 4>((const float *)L.C + 2, L.mask, L.G, x, y, z, &pi);
+  const float2 m = L.M[s];
+  L.C[s] = make_float4(m.x, m.y, pi, 0.0f);
 }
 
 template <int Q>
@@ -175,23 +171,18 @@ __device__ __forceinline__ void laplacians(const float2 *__restrict__ M, const N
   lp = 6.0f * ap;
 }
 
-template <int Q>
-__global__ __launch_bounds__(BX *BY) void k_potential(const float2 *__restrict__ M,
-                                                      const uint32_t *__restrict__ nbm,
-                                                      float4 *__restrict__ C, float *__restrict__ MUP,
-                                                      Geom G, Phys P) {
-  int x, y, z;
-  long long c;
-  if (!cell_of_thread(G, x, y, z, c)) return;
-  if (nbm[c] & NB_SELF_SOLID) return;
-  const Nbr N(G, x, y, z);
-  float2 m0 = M[c];
+template <int Q, int S>
+__device__ __forceinline__ void stage_potential(const LatView<Q, S> &L, int x, int y, int z) {
+  const long long c = (long long)x + (long long)L.G.px * ((long long)y + (long long)L.G.ey * z);
+  if (L.nbm[c] & NB_SELF_SOLID) return;
+  const Nbr N(L.G, x, y, z);
+  const float2 m0 = L.M[c];
   float lr, lp;
-  laplacians<Q>(M, N, m0, lr, lp);
+  laplacians<Q>(L.M, N, m0, lr, lp);
   float mr, mp;
-  chem_pot(P, m0.x, m0.y, lr, lp, mr, mp);
-  C[c] = make_float4(m0.x, m0.y, (1.0f + m0.x) * mr + m0.y * mp, mr);
-  MUP[c] = mp;
+  chem_pot(L.ph, m0.x, m0.y, lr, lp, mr, mp);
+  L.C[c] = make_float4(m0.x, m0.y, (1.0f + m0.x) * mr + m0.y * mp, mr);
+  L.MUP[c] = mp;
 }
 
 // Force of eq. (F) in product-rule form:
@@ -304,19 +295,84 @@ __device__ __forceinline__ void bounce_back(const Pops<Q, S> &P, const Nbr &N, l
 }
 
 template <int Q, int S, int ODD>
-__global__ __launch_bounds__(BX *BY) void k_collide(Pops<Q, S> P, const uint32_t *__restrict__ nbm,
-                                                    const uint8_t *__restrict__ mask,
-                                                    const float4 *__restrict__ C,
-                                                    const float *__restrict__ MUP, Geom G, Phys ph) {
+__device__ __forceinline__ void stage_collide(const LatView<Q, S> &L, int x, int y, int z) {
+  const long long c = (long long)x + (long long)L.G.px * ((long long)y + (long long)L.G.ey * z);
+  const uint32_t bits = L.nbm[c];
+  if (bits & NB_SELF_SOLID) return;
+  const Nbr N(L.G, x, y, z);
+  float rho, phi;
+  collide_cell<Q, S, ODD>(L.P, N, c, L.C, L.MUP, L.ph, rho, phi);
+  if (bits != 0u) bounce_back<Q, S, ODD>(L.P, N, c, bits, L.mask, L.G, L.ph, x, y, z, rho, phi);
+}
+
+// ---------------------------------------------------------------------------
+// Kernels over one lattice: one thread per storage cell (64 x 4 blocks), one
+// thread per solid boundary cell for the fills.
+// ---------------------------------------------------------------------------
+enum Stage { ST_MOMENTS = 0, ST_POTENTIAL = 1, ST_COLLIDE = 2 };
+
+template <int Q, int S, int STAGE, int ODD>
+__device__ __forceinline__ void run_stage(const LatView<Q, S> &L, int x, int y, int z) {
+  if (STAGE == ST_MOMENTS) stage_moments<Q, S, ODD>(L, x, y, z);
+  else if (STAGE == ST_POTENTIAL) stage_potential<Q, S>(L, x, y, z);
+  else stage_collide<Q, S, ODD>(L, x, y, z);
+}
+
+template <int Q, int S, int STAGE, int ODD>
+__global__ __launch_bounds__(BX *BY) void k_cells(LatView<Q, S> L) {
   int x, y, z;
   long long c;
-  if (!cell_of_thread(G, x, y, z, c)) return;
-  const uint32_t bits = nbm[c];
-  if (bits & NB_SELF_SOLID) return;
-  const Nbr N(G, x, y, z);
-  float rho, phi;
-  collide_cell<Q, S, ODD>(P, N, c, C, MUP, ph, rho, phi);
-  if (bits != 0u) bounce_back<Q, S, ODD>(P, N, c, bits, mask, G, ph, x, y, z, rho, phi);
+  if (!cell_of_thread(L.G, x, y, z, c)) return;
+  run_stage<Q, S, STAGE, ODD>(L, x, y, z);
+}
+
+template <int Q, int S, int PI>
+__global__ __launch_bounds__(256) void k_fill(LatView<Q, S> L) {
+  const int k = blockIdx.x * blockDim.x + threadIdx.x;
+  if (k >= L.n_fill) return;
+  if (PI) stage_fill_c<Q, S>(L, L.fill[k]);
+  else stage_fill_m<Q, S>(L, L.fill[k]);
+}
+
+// ---------------------------------------------------------------------------
+// Batched persistent kernels: a fixed grid walks a device-side work list of
+// (slot, block-x, block-y, z) items (or (slot, cell) fill items) for the
+// lattices of one (velocity set, storage) class.  The list and its length
+// live in device memory, so a captured graph stays valid while lattices join
+// and leave the batch.
+// ---------------------------------------------------------------------------
+template <int Q, int S>
+__device__ __forceinline__ LatView<Q, S> view_of(char *base, const Inst &I) {
+  LatView<Q, S> L;
+  L.P = pops_of<Q, S>(base + I.f, base + I.g, (float *)(base + I.g0));
+  L.nbm = (const uint32_t *)(base + I.nbm); L.mask = (const uint8_t *)(base + I.mask);
+  L.M = (float2 *)(base + I.M); L.C = (float4 *)(base + I.C); L.MUP = (float *)(base + I.MUP);
+  L.G = I.G; L.ph = I.ph; L.fill = (const int *)(base + I.fill); L.n_fill = I.n_fill;
+  return L;
+}
+
+template <int Q, int S, int STAGE, int ODD>
+__global__ __launch_bounds__(BX *BY) void k_batch_cells(char *base, const Inst *__restrict__ inst, const int4 *__restrict__ work,
+                                                        const int *__restrict__ range) {
+  const int start = range[0], n = range[1];
+  for (int w = blockIdx.x; w < n; w += gridDim.x) {
+    const int4 it = work[start + w];
+    const LatView<Q, S> L = view_of<Q, S>(base, inst[it.x]);
+    const int x = it.y * BX + threadIdx.x, y = it.z * BY + threadIdx.y, z = it.w;
+    if (x < L.G.ex && y < L.G.ey) run_stage<Q, S, STAGE, ODD>(L, x, y, z);
+  }
+}
+
+template <int Q, int S, int PI>
+__global__ __launch_bounds__(256) void k_batch_fill(char *base, const Inst *__restrict__ inst, const int2 *__restrict__ work,
+                                                    const int *__restrict__ range) {
+  const int start = range[0], n = range[1];
+  for (int k = blockIdx.x * blockDim.x + threadIdx.x; k < n; k += gridDim.x * blockDim.x) {
+    const int2 it = work[start + k];
+    const LatView<Q, S> L = view_of<Q, S>(base, inst[it.x]);
+    if (PI) stage_fill_c<Q, S>(L, it.y);
+    else stage_fill_m<Q, S>(L, it.y);
+  }
 }
 
 // Initialisation at equilibrium (Sec. 2.3).  M holds (rho0 - 1, phi0) with
@@ -463,38 +519,53 @@ static dim3 cell_grid(const Geom &G) { return dim3((G.ex + BX - 1) / BX, (G.ey +
 static dim3 cell_block() { return dim3(BX, BY, 1); }
 static int fill_blocks(int n) { return (n + 255) / 256; }
 
+template <int Q, int S>
+static LatView<Q, S> view_of_args(const LaunchArgs &a) {
+  LatView<Q, S> L;
+  L.P = make_pops<Q, S>(a);
+  L.nbm = a.nbm; L.mask = a.mask; L.M = a.M; L.C = a.C; L.MUP = a.MUP;
+  L.G = a.G; L.ph = a.ph; L.fill = a.fill_list; L.n_fill = a.n_fill;
+  return L;
+}
+
+template <int Q, int S, int STAGE>
+static void cells_launch(const LaunchArgs &a, int odd) {
+  const LatView<Q, S> L = view_of_args<Q, S>(a);
+  if (odd) k_cells<Q, S, STAGE, 1><<<cell_grid(a.G), cell_block(), 0, a.stream>>>(L);
+  else k_cells<Q, S, STAGE, 0><<<cell_grid(a.G), cell_block(), 0, a.stream>>>(L);
+}
+
+template <int Q, int S, int PI>
+static void fill_launch(const LaunchArgs &a) {
+  if (a.n_fill) k_fill<Q, S, PI><<<fill_blocks(a.n_fill), 256, 0, a.stream>>>(view_of_args<Q, S>(a));
+}
+
+template <int Q, int S>
+static void moments_launch(const LaunchArgs &a, int odd) { cells_launch<Q, S, ST_MOMENTS>(a, odd); }
+
 // Coupling fields of the current state: solid fills of rho, phi, then
 // mu_rho, mu_phi, Pi, then the solid fill of Pi.
 template <int Q, int S>
 static void couple_seq(const LaunchArgs &a, hipEvent_t *ev, int &k) {
-  dim3 gr = cell_grid(a.G), bl = cell_block();
   auto mark = [&]() { if (ev) (void)hipEventRecord(ev[k++], a.stream); };
-  if (a.n_fill) k_fill_m<Q><<<fill_blocks(a.n_fill), 256, 0, a.stream>>>(a.M, a.fill_list, a.n_fill, a.mask, a.G);
+  fill_launch<Q, S, 0>(a);
   mark();
-  k_potential<Q><<<gr, bl, 0, a.stream>>>(a.M, a.nbm, a.C, a.MUP, a.G, a.ph);
+  cells_launch<Q, S, ST_POTENTIAL>(a, 0);
   mark();
-  if (a.n_fill) k_fill_c<Q><<<fill_blocks(a.n_fill), 256, 0, a.stream>>>(a.C, a.M, a.fill_list, a.n_fill, a.mask, a.G);
+  fill_launch<Q, S, 1>(a);
   mark();
-}
-
-template <int Q, int S>
-static void moments_launch(const LaunchArgs &a, int odd) {
-  if (odd) k_moments<Q, S, 1><<<cell_grid(a.G), cell_block(), 0, a.stream>>>(make_pops<Q, S>(a), a.nbm, a.M, a.G);
-  else k_moments<Q, S, 0><<<cell_grid(a.G), cell_block(), 0, a.stream>>>(make_pops<Q, S>(a), a.nbm, a.M, a.G);
 }
 
 // One step: moments, coupling fields, collide + stream.  ev (if not null)
 // receives an event before the first launch and after each.
 template <int Q, int S>
 static void step_seq(const LaunchArgs &a, int odd, hipEvent_t *ev) {
-  Pops<Q, S> P = make_pops<Q, S>(a);
   int k = 0;
   if (ev) (void)hipEventRecord(ev[k++], a.stream);
   moments_launch<Q, S>(a, odd);
   if (ev) (void)hipEventRecord(ev[k++], a.stream);
   couple_seq<Q, S>(a, ev, k);
-  if (odd) k_collide<Q, S, 1><<<cell_grid(a.G), cell_block(), 0, a.stream>>>(P, a.nbm, a.mask, a.C, a.MUP, a.G, a.ph);
-  else k_collide<Q, S, 0><<<cell_grid(a.G), cell_block(), 0, a.stream>>>(P, a.nbm, a.mask, a.C, a.MUP, a.G, a.ph);
+  cells_launch<Q, S, ST_COLLIDE>(a, odd);
   if (ev) (void)hipEventRecord(ev[k++], a.stream);
 }
 
@@ -513,7 +584,7 @@ static void observe_impl(const LaunchArgs &a, int odd) {
 template <int Q, int S>
 static void init_impl(const LaunchArgs &a) {
   Pops<Q, S> P = make_pops<Q, S>(a);
-  if (a.n_fill) k_fill_m<Q><<<fill_blocks(a.n_fill), 256, 0, a.stream>>>(a.M, a.fill_list, a.n_fill, a.mask, a.G);
+  fill_launch<Q, S, 0>(a);
   k_init<Q, S><<<cell_grid(a.G), cell_block(), 0, a.stream>>>(P, a.nbm, a.M, a.AUX, a.G, a.ph);
 }
 
@@ -540,6 +611,31 @@ const char *step_kernel_name(int k) {
 void launch_observe(const LaunchArgs &a, int odd) { FRE_DISPATCH(observe_impl, a, odd); }
 void launch_init(const LaunchArgs &a) { FRE_DISPATCH(init_impl, a); }
 void launch_read_pops(const LaunchArgs &a, int odd, float *out) { FRE_DISPATCH(read_pops_impl, a, odd, out); }
+
+// One batched step of one class: the same five stages over every lattice of
+// the class listed in the work lists (ranges: cells [start, n], fills
+// [start, n]).
+template <int Q, int S>
+static void batch_step_impl(const BatchArgs &b, int cls, int odd) {
+  const int *rc = b.range + 4 * cls, *rf = rc + 2;
+  const dim3 bl = cell_block();
+  if (odd) k_batch_cells<Q, S, ST_MOMENTS, 1><<<b.grid_cells, bl, 0, b.stream>>>(b.base, b.inst, b.work, rc);
+  else k_batch_cells<Q, S, ST_MOMENTS, 0><<<b.grid_cells, bl, 0, b.stream>>>(b.base, b.inst, b.work, rc);
+  k_batch_fill<Q, S, 0><<<b.grid_fill, 256, 0, b.stream>>>(b.base, b.inst, b.fill, rf);
+  k_batch_cells<Q, S, ST_POTENTIAL, 0><<<b.grid_cells, bl, 0, b.stream>>>(b.base, b.inst, b.work, rc);
+  k_batch_fill<Q, S, 1><<<b.grid_fill, 256, 0, b.stream>>>(b.base, b.inst, b.fill, rf);
+  if (odd) k_batch_cells<Q, S, ST_COLLIDE, 1><<<b.grid_cells, bl, 0, b.stream>>>(b.base, b.inst, b.work, rc);
+  else k_batch_cells<Q, S, ST_COLLIDE, 0><<<b.grid_cells, bl, 0, b.stream>>>(b.base, b.inst, b.work, rc);
+}
+
+void launch_batch_step(const BatchArgs &b, int cls, int odd) {
+  switch (cls) {
+    case 0: batch_step_impl<9, 0>(b, cls, odd); break;
+    case 1: batch_step_impl<9, 1>(b, cls, odd); break;
+    case 2: batch_step_impl<19, 0>(b, cls, odd); break;
+    default: batch_step_impl<19, 1>(b, cls, odd); break;
+  }
+}
 
 int reduce_blocks() { return 1024; }
 void launch_reduce(const LaunchArgs &a, double *part) {

@@ -109,10 +109,25 @@ __device__ __forceinline__ int nb_fluid(const Geom &G, int x, int y, int z, int 
 // directions of one population contiguously ([block][direction][64]), so a
 // wavefront streams one contiguous 256-byte (FP32) segment per direction.
 // S = 0: FP32 for f and g.  S = 1: f and g_1.. as half (round to nearest
-// even), g_0 as float in a plane of its own.
+// even), g_0 as float in a plane of its own; the half g array keeps the same
+// q-direction block shape as f (its plane 0 unused) so both share offsets.
 // ---------------------------------------------------------------------------
-__device__ __forceinline__ long long blk_index(int planes, int i, long long c) {
-  return ((c >> 6) * planes + i) * 64 + (c & 63);
+// Byte offset of population i of cell c in an array of `planes` directions
+// of elements of ES bytes.  Offsets are 32-bit (every population array is
+// kept under 4 GiB), so the compiler can address with a scalar base plus a
+// 32-bit vector offset.
+template <int ES>
+__device__ __forceinline__ uint32_t blk_offset(int planes, int i, long long c) {
+  const uint32_t cc = (uint32_t)c;
+  return (((cc >> 6) * (uint32_t)planes + (uint32_t)i) * 64u + (cc & 63u)) * (uint32_t)ES;
+}
+template <class T>
+__device__ __forceinline__ T ld_at(const T *base, uint32_t off) {
+  return *(const T *)((const char *)base + off);
+}
+template <class T>
+__device__ __forceinline__ void st_at(T *base, uint32_t off, T v) {
+  *(T *)((char *)base + off) = v;
 }
 
 template <int Q, int S> struct Pops;
@@ -121,24 +136,24 @@ template <int Q> struct Pops<Q, 0> {
   float *f, *g;
   // the value a store keeps (identity for FP32)
   __device__ __forceinline__ float round(float v) const { return v; }
-  __device__ __forceinline__ float ldf(int i, long long c) const { return f[blk_index(Q, i, c)]; }
-  __device__ __forceinline__ float ldg(int i, long long c) const { return g[blk_index(Q, i, c)]; }
-  __device__ __forceinline__ void stf(int i, long long c, float v) const { f[blk_index(Q, i, c)] = v; }
-  __device__ __forceinline__ void stg(int i, long long c, float v) const { g[blk_index(Q, i, c)] = v; }
+  __device__ __forceinline__ float ldf(int i, long long c) const { return ld_at(f, blk_offset<4>(Q, i, c)); }
+  __device__ __forceinline__ float ldg(int i, long long c) const { return ld_at(g, blk_offset<4>(Q, i, c)); }
+  __device__ __forceinline__ void stf(int i, long long c, float v) const { st_at(f, blk_offset<4>(Q, i, c), v); }
+  __device__ __forceinline__ void stg(int i, long long c, float v) const { st_at(g, blk_offset<4>(Q, i, c), v); }
 };
 
 template <int Q> struct Pops<Q, 1> {
-  __half *f, *g;  // g holds directions 1..q-1
-  float *g0;
+  __half *f, *g;  // g: q planes like f, plane 0 unused
+  float *g0;      // g_0
   // the value a half store keeps (g_0 is stored in FP32 and not rounded)
   __device__ __forceinline__ float round(float v) const { return __half2float(__float2half_rn(v)); }
-  __device__ __forceinline__ float ldf(int i, long long c) const { return __half2float(f[blk_index(Q, i, c)]); }
+  __device__ __forceinline__ float ldf(int i, long long c) const { return __half2float(ld_at(f, blk_offset<2>(Q, i, c))); }
   __device__ __forceinline__ float ldg(int i, long long c) const {
-    return i == 0 ? g0[c] : __half2float(g[blk_index(Q - 1, i - 1, c)]);
+    return i == 0 ? ld_at(g0, (uint32_t)c * 4u) : __half2float(ld_at(g, blk_offset<2>(Q, i, c)));
   }
-  __device__ __forceinline__ void stf(int i, long long c, float v) const { f[blk_index(Q, i, c)] = __float2half_rn(v); }
+  __device__ __forceinline__ void stf(int i, long long c, float v) const { st_at(f, blk_offset<2>(Q, i, c), __float2half_rn(v)); }
   __device__ __forceinline__ void stg(int i, long long c, float v) const {
-    if (i == 0) g0[c] = v; else g[blk_index(Q - 1, i - 1, c)] = __float2half_rn(v);
+    if (i == 0) st_at(g0, (uint32_t)c * 4u, v); else st_at(g, blk_offset<2>(Q, i, c), __float2half_rn(v));
   }
 };
 
@@ -175,6 +190,8 @@ template <class V>
 __device__ __forceinline__ void body_velocity(const Geom &G, const Phys &P, uint8_t code, int x,
                                               int y, int z, int xs, int ys, int zs, int i,
                                               float uw[3]) {
+  // Phys is read with compile-time indices only (selects instead of a
+  // run-time array index), so a copy of it can live in registers.
   uw[0] = uw[1] = uw[2] = 0.0f;
   if (code == CELL_GHOST) {
     const int sc[3] = {xs, ys, zs};
@@ -185,9 +202,8 @@ __device__ __forceinline__ void body_velocity(const Geom &G, const Phys &P, uint
       if (G.per[a]) continue;
       int side = sc[a] == 0 ? 0 : (sc[a] == ext[a] - 1 ? 1 : -1);
       if (side < 0) continue;
-      uw[0] += P.wall_u[a][side][0];
-      uw[1] += P.wall_u[a][side][1];
-      uw[2] += P.wall_u[a][side][2];
+#pragma unroll
+      for (int k = 0; k < 3; ++k) uw[k] += side ? P.wall_u[a][1][k] : P.wall_u[a][0][k];
       ++n;
     }
     if (n > 1) {
@@ -196,14 +212,18 @@ __device__ __forceinline__ void body_velocity(const Geom &G, const Phys &P, uint
     }
     return;
   }
-  int r = (int)code - CELL_ROLLER0;
+  const int r = (int)code - CELL_ROLLER0;
   if (r < 0 || r >= P.n_rollers) return;
-  float d0 = (float)(x - G.off[0]) + 0.5f * V::cx(i) - P.rc[r][0];
-  float d1 = (float)(y - G.off[1]) + 0.5f * V::cy(i) - P.rc[r][1];
-  float d2 = (float)(z - G.off[2]) + 0.5f * V::cz(i) - P.rc[r][2];
-  float om = P.rom[r];
-  if (P.rax[r] == 0) { uw[1] = -om * d2; uw[2] = om * d1; }
-  else if (P.rax[r] == 1) { uw[0] = om * d2; uw[2] = -om * d0; }
+  float rc0 = 0.0f, rc1 = 0.0f, rc2 = 0.0f, om = 0.0f;
+  int ax = 2;
+#pragma unroll
+  for (int k = 0; k < 4; ++k)
+    if (k == r) { rc0 = P.rc[k][0]; rc1 = P.rc[k][1]; rc2 = P.rc[k][2]; om = P.rom[k]; ax = P.rax[k]; }
+  float d0 = (float)(x - G.off[0]) + 0.5f * V::cx(i) - rc0;
+  float d1 = (float)(y - G.off[1]) + 0.5f * V::cy(i) - rc1;
+  float d2 = (float)(z - G.off[2]) + 0.5f * V::cz(i) - rc2;
+  if (ax == 0) { uw[1] = -om * d2; uw[2] = om * d1; }
+  else if (ax == 1) { uw[0] = om * d2; uw[2] = -om * d0; }
   else { uw[0] = -om * d1; uw[1] = om * d0; }
 }
 

@@ -70,6 +70,15 @@ _SIGS = [
                                      C.POINTER(C.c_int32)]),
     ("fre_kernel_name", C.c_char_p, [C.c_int32]),
     ("fre_lattice_destroy", None, [C.c_void_p]),
+    ("fre_batch_footprint", C.c_int32, [C.c_int32, C.c_int64, C.c_int64, C.POINTER(C.c_size_t)]),
+    ("fre_lattice_batch_needs", C.c_int32, [C.c_void_p, C.POINTER(C.c_int64), C.POINTER(C.c_int64)]),
+    ("fre_batch_create", C.c_int32, [C.c_void_p, C.c_size_t, C.c_void_p, C.c_int32, C.c_int64, C.c_int64,
+                                     C.POINTER(C.c_void_p)]),
+    ("fre_batch_add", C.c_int32, [C.c_void_p, C.c_void_p, C.POINTER(C.c_int32)]),
+    ("fre_batch_remove", C.c_int32, [C.c_void_p, C.c_int32]),
+    ("fre_batch_step", C.c_int32, [C.c_void_p, C.c_int64]),
+    ("fre_batch_info", C.c_int32, [C.c_void_p, C.POINTER(C.c_int32), C.POINTER(C.c_int32)]),
+    ("fre_batch_destroy", None, [C.c_void_p]),
     ("fre_last_error", C.c_char_p, []),
 ]
 
@@ -240,3 +249,55 @@ class Lattice:
     def load(self, blob: bytes):
         buf = np.frombuffer(blob, np.uint8).copy()
         _check(lib().fre_load(self._h, _ptr(buf), buf.size))
+
+
+class Batch:
+    """A batch of lattices advanced together (continuous batching): device
+    tables in a torch-allocated buffer, steps on a torch stream."""
+
+    def __init__(self, max_slots: int, max_work: int, max_fill: int, device="cuda:0", stream=None):
+        import torch  # device memory and streams only
+        n = C.c_size_t()
+        _check(lib().fre_batch_footprint(max_slots, max_work, max_fill, C.byref(n)))
+        self.buf = torch.empty(n.value + 256, dtype=torch.uint8, device=device)
+        base = self.buf.data_ptr() + ((-self.buf.data_ptr()) % 256)
+        self.stream = stream if stream is not None else torch.cuda.Stream(device)
+        h = C.c_void_p()
+        _check(lib().fre_batch_create(C.c_void_p(base), n.value, C.c_void_p(self.stream.cuda_stream),
+                                      max_slots, max_work, max_fill, C.byref(h)))
+        self._h = h
+        self.members = {}
+
+    @staticmethod
+    def needs(lat: "Lattice"):
+        w, f = C.c_int64(), C.c_int64()
+        _check(lib().fre_lattice_batch_needs(lat.handle, C.byref(w), C.byref(f)))
+        return w.value, f.value
+
+    def add(self, lat: "Lattice") -> int:
+        s = C.c_int32()
+        _check(lib().fre_batch_add(self._h, lat.handle, C.byref(s)))
+        self.members[s.value] = lat
+        return s.value
+
+    def remove(self, slot: int):
+        _check(lib().fre_batch_remove(self._h, int(slot)))
+        self.members.pop(slot, None)
+
+    def step(self, n: int = 1):
+        _check(lib().fre_batch_step(self._h, int(n)))
+        return self
+
+    def info(self):
+        m, p = C.c_int32(), C.c_int32()
+        _check(lib().fre_batch_info(self._h, C.byref(m), C.byref(p)))
+        return m.value, p.value
+
+    def close(self):
+        if getattr(self, "_h", None):
+            lib().fre_batch_destroy(self._h)
+            self._h = None
+            self.members = {}
+
+    def __del__(self):
+        self.close()

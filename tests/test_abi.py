@@ -31,8 +31,7 @@ def test_every_declared_symbol_is_exported(lib):
     for n in names:
         assert hasattr(lib, n), n
     bound = {s[0] for s in F._SIGS}
-    assert set(names) <= bound | {"fre_batch_create", "fre_batch_add", "fre_batch_remove",
-                                  "fre_batch_step", "fre_batch_destroy", "fre_batch_info"}
+    assert set(names) <= bound
 
 
 def _ok_params(**kw):

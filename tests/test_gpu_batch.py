@@ -1,0 +1,134 @@
+"""Batched stepping (continuous batching) on the GPU.
+
+A lattice advanced inside a batch -- mixed velocity sets, storage precisions
+and sizes, members joining and leaving while others run -- must hold exactly
+the populations it holds when advanced alone (bitwise), and the batch's
+graph replay must equal step-by-step launches.
+"""
+import numpy as np
+import pytest
+import torch
+
+from paper_2212_01617_amd import frelbm as F
+from paper_2212_01617_amd import synth
+
+from _pair import case_inputs, ensure_gpu_lib, log
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module", autouse=True)
+def _lib():
+    assert torch.cuda.is_available(), "GPU tests need a GPU"
+    ensure_gpu_lib()
+
+
+def _specs():
+    """Four lattices of different classes, shapes and boundaries."""
+    out = []
+    wu = np.zeros((3, 2, 3)); wu[2, 0, 0] = -0.01; wu[2, 1, 0] = 0.01
+    phi0, _, u0 = case_inputs(1, (40, 20, 12), radius=5, xi=1.5, u_amp=0.005, seed=1)
+    out.append((F.make_params(1, (40, 20, 12), bc=(0, 0, 1), wall_u=wu, A=0.04, kappa=0.09), phi0, u0, None))
+    phi0, _, _ = case_inputs(0, (70, 33, 1), radius=8, xi=1.5, seed=2)
+    out.append((F.make_params(0, (70, 33, 1), storage=1, A=0.04, kappa=0.09), phi0, None, None))
+    n = 48
+    cs, signs = synth.four_roller_geometry(n, n, 6.0, nz=5)
+    mask = synth.roller_mask((5, n, n), cs, 6.0)
+    rollers = [(c, s * 0.01 / 6.0, 2, 6.0) for c, s in zip(cs, signs)]
+    phi0, _, _ = case_inputs(1, (n, n, 5), radius=6, xi=2.0, seed=3, center=(23.5, 23.5, 2.0))
+    out.append((F.make_params(1, (n, n, 5), storage=1, rollers=rollers, A=3.07e-3, kappa=1.23e-2,
+                              tau_g=1.15, M=5.26), phi0, None, mask))
+    wu2 = np.zeros((3, 2, 3)); wu2[1, 0, 0] = -0.008; wu2[1, 1, 0] = 0.008
+    phi0, _, u0 = case_inputs(0, (130, 24, 1), radius=6, xi=2.0, shear=(0.016 / 24, 1), seed=4)
+    out.append((F.make_params(0, (130, 24, 1), bc=(0, 1, 0), wall_u=wu2, A=1.84e-3, kappa=7.36e-3,
+                              M=5.26), phi0, u0, None))
+    return out
+
+
+def _make(spec, stream=None):
+    p, phi0, u0, mask = spec
+    return F.Lattice(p, phi0, None, u0, mask, stream=stream)
+
+
+def _solo(spec, steps):
+    L = _make(spec)
+    L.step(steps)
+    return L.populations()
+
+
+def _capacity(lats):
+    w = f = 0
+    for L in lats:
+        a, b = F.Batch.needs(L)
+        w += a
+        f += b
+    return w, f
+
+
+def test_batch_equals_solo_bitwise_with_joins_and_leaves():
+    specs = _specs()
+    lats = [_make(s) for s in specs]
+    w, f = _capacity(lats)
+    B = F.Batch(max_slots=6, max_work=w, max_fill=f)
+    # members join at different times: 0 and 1 now, 2 after 5 steps (out of
+    # phase, so it takes one step alone first), 3 after 9 steps
+    s0, s1 = B.add(lats[0]), B.add(lats[1])
+    B.step(5)
+    s2 = B.add(lats[2])
+    B.step(4)
+    s3 = B.add(lats[3])
+    B.step(7)          # graph replay (non-default stream, n >= 4)
+    B.remove(s1)       # lattice 1 leaves; the others go on
+    B.step(3)
+    # lattices 2 and 3 joined at odd batch parity with t = 0: each took one
+    # solo step first
+    steps = {0: 19, 1: 16, 2: 1 + 14, 3: 1 + 10}
+    for k, L in enumerate(lats):
+        t, state = L.info()
+        assert state == 0
+        assert t == steps[k], (k, t)
+        fa, ga = L.populations()
+        fb, gb = _solo(specs[k], t)
+        same = np.array_equal(fa, fb) and np.array_equal(ga, gb)
+        log(f"[batch] lattice {k}: t={t} bitwise equal to solo: {same}")
+        assert same, k
+    assert B.info()[0] == 3
+
+
+def test_batch_graph_equals_direct_steps():
+    specs = _specs()[:2]
+    a = [_make(s) for s in specs]
+    b = [_make(s) for s in specs]
+    w, f = _capacity(a)
+    Ba = F.Batch(max_slots=2, max_work=w, max_fill=f)          # graph replay
+    for L in a:
+        Ba.add(L)
+    Bb = F.Batch(max_slots=2, max_work=w, max_fill=f)
+    for L in b:
+        Bb.add(L)
+    Ba.step(9)
+    for _ in range(9):
+        Bb.step(1)                                            # one launch sequence per step
+    for La, Lb in zip(a, b):
+        fa, ga = La.populations()
+        fb, gb = Lb.populations()
+        assert np.array_equal(fa, fb) and np.array_equal(ga, gb)
+
+
+def test_batch_capacity_and_state_errors():
+    specs = _specs()
+    L0, L1 = _make(specs[0]), _make(specs[1])
+    w, f = F.Batch.needs(L0)
+    B = F.Batch(max_slots=1, max_work=w, max_fill=f)
+    B.add(L0)
+    with pytest.raises(F.FreError) as ei:
+        B.add(L1)                   # no free slot
+    assert ei.value.status == F.FRE_ENOMEM
+    with pytest.raises(F.FreError) as ei:
+        L0.step(1)                  # members step only through the batch
+    assert ei.value.status == F.FRE_ESTATE
+    B2 = F.Batch(max_slots=2, max_work=1, max_fill=1)
+    with pytest.raises(F.FreError) as ei:
+        B2.add(L1)                  # work list too small
+    assert ei.value.status == F.FRE_ENOMEM
+    assert B2.info()[0] == 0
