@@ -6,10 +6,17 @@ kappa=A xi^2, M=5.26 from Pe=0.43, tau_f=1, tau_g=1.74 for Cahn-Hilliard
 stability), FP32 population storage; synthetic seeded
 inputs, already resident in HBM when timing starts.  A step is one full
 time step of the method (all kernels).  Prints one JSON line.
+
+Modes for profiling (each prints its own JSON line):
+  --kernels-only N   N individually launched steps of the FP32 workload
+                     (for rocprofv3 kernel traces and counter runs)
+  --copy-probe       a plain device-to-device copy of known size, the
+                     reference for scaling the FETCH_SIZE / WRITE_SIZE counters
 """
 from __future__ import annotations
 
 import argparse
+import hashlib
 import json
 import math
 import os
@@ -22,6 +29,37 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 PEAK_HBM_GBS = 8000.0
+KERNEL_SOURCES = ("paper_2212_01617_amd/csrc/kernels.hip", "paper_2212_01617_amd/csrc/lbm_device.h",
+                  "paper_2212_01617_amd/csrc/kernels.h")
+TRAFFIC_FILE = "profiles/traffic_k_collide_d3q19_fp32_256x128x128.txt"
+
+
+def kernel_source_hash() -> str:
+    h = hashlib.sha256()
+    for f in KERNEL_SOURCES:
+        with open(os.path.join(ROOT, f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
+def measured_traffic():
+    """HBM bytes per launch of k_collide from the committed counter summary,
+    or None when the kernel sources changed since the counters were taken."""
+    path = os.path.join(ROOT, TRAFFIC_FILE)
+    if not os.path.exists(path):
+        return None
+    kv = {}
+    with open(path) as fh:
+        for line in fh:
+            if "=" in line and not line.startswith("#"):
+                k, v = line.split("=", 1)
+                kv[k.strip()] = v.strip()
+    if kv.get("source_hash") != kernel_source_hash():
+        return None
+    try:
+        return float(kv["hbm_bytes_per_launch"])
+    except (KeyError, ValueError):
+        return None
 
 
 def workload(storage: int):
@@ -66,7 +104,7 @@ def time_steps(L, steps, warmup, reps):
     return float(np.median(times)), times
 
 
-def cpu_baseline(p_gpu, phi0, u0, meta, steps=20):
+def cpu_baseline(p_gpu, phi0, u0, meta, steps=60):
     from oracle import oracle as O
     nx, ny, nz = meta["shape"]
     po = O.make_params(1, (nx, ny, nz), bc=(0, 0, 1), wall_u=meta["wall_u"], **meta["phys"])
@@ -89,6 +127,9 @@ def main():
     ap.add_argument("--reps", type=int, default=5)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-fp16", action="store_true")
+    ap.add_argument("--serve", type=int, default=24, help="requests in the serving leg (0: skip)")
+    ap.add_argument("--kernels-only", type=int, default=0)
+    ap.add_argument("--copy-probe", action="store_true")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py runs on one GPU only: this build has no multi-GPU path "
@@ -101,6 +142,17 @@ def main():
         build.build()
     torch.cuda.init()
     stream = torch.cuda.Stream()
+    if args.copy_probe:
+        copy_probe()
+        return
+    if args.kernels_only:
+        p, phi0, u0, meta = workload(0)
+        L = F.Lattice(p, phi0, None, u0, stream=stream)
+        prof = L.profile(args.kernels_only)
+        torch.cuda.synchronize()
+        print(json.dumps({"mode": "kernels-only", "steps": args.kernels_only,
+                          "kernels_ms": {k: round(v, 5) for k, v in prof.items()}}), flush=True)
+        return
 
     res = {}
     for storage in ((0,) if args.no_fp16 else (0, 1)):
@@ -136,7 +188,8 @@ def main():
         "config": {"workload": "D3Q19 shear droplet 256x128x128, walls in z, R=25, xi=2, Ca=0.1, Re=1, FP32 storage",
                    "storage": "fp32", "fluid_cells": n, "bytes_per_lu": b},
         "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": PEAK_HBM_GBS, "unit": "GB/s",
-                     "frac": round(achieved / PEAK_HBM_GBS, 4), "traffic": None,
+                     "frac": round(achieved / PEAK_HBM_GBS, 4), "traffic": measured_traffic(),
+                     "traffic_unit": "bytes per launch",
                      "kernel": dom, "kernel_ms": round(dom_ms, 5),
                      "step_frac": round(mlups * 1e6 * b / 1e9 / PEAK_HBM_GBS, 4)},
         "kernels_ms": {k: round(v, 5) for k, v in r["prof"].items()},
@@ -148,9 +201,54 @@ def main():
         out["fp16_store"] = {"value": round(m16, 1), "unit": "MLUPS", "ms_per_step": round(r16["ms"], 5),
                              "bytes_per_lu": b16, "step_frac": round(m16 * 1e6 * b16 / 1e9 / PEAK_HBM_GBS, 4),
                              "kernels_ms": {k: round(v, 5) for k, v in r16["prof"].items()}}
+    for v in res.values():
+        v["L"].close()
+    res.clear()
+    if args.serve:
+        out["serving"] = serving(args.serve)
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(r["p"], r["phi0"], r["u0"], r["meta"])
     print(json.dumps(out), flush=True)
+
+
+def serving(n_requests: int) -> dict:
+    """Continuous batching of a mixed droplet request stream (Poisson
+    arrivals at 20/s; D2Q9 N in 64..256 and D3Q19 N in 48..96, shear and
+    four-roller, FP32 and FP16, Ca in [0.05, 0.4], Re in [0.1, 1]; R = 0.2 N,
+    xi = 2) under a 16 GiB budget; caps of 10 strain units or 20000 steps."""
+    from paper_2212_01617_amd import serve
+    rs = serve.make_requests(n_requests, rate=20.0, seed=0, d2_sizes=tuple(range(64, 257, 16)),
+                             d3_sizes=tuple(range(48, 97, 16)))
+    budget = 16 << 30
+    eng = serve.GpuEngine(budget_bytes=budget, max_members=32)
+    srv = serve.Server(eng, budget, max_members=32, chunk=200, strain_cap=10.0, step_cap=20_000)
+    rep = srv.run(rs)
+    s = rep.summary()
+    s = {k: (round(v, 4) if isinstance(v, float) else v) for k, v in s.items()}
+    s["workload"] = (f"{n_requests} requests, Poisson 20/s, D2Q9 N 64-256 / D3Q19 N 48-96, shear/rollers, "
+                     "FP32/FP16, caps 10 strain units or 20000 steps, 16 GiB budget")
+    eng.batch.close()
+    return s
+
+
+def copy_probe(nbytes: int = 1 << 30, reps: int = 5) -> None:
+    """A plain device copy of nbytes, repeated: reading the FETCH_SIZE and
+    WRITE_SIZE counters of these launches against nbytes gives the scale of
+    the counters for the kernels of the step."""
+    import torch
+    src = torch.empty(nbytes, dtype=torch.uint8, device="cuda")
+    src.fill_(1)
+    dst = torch.empty_like(src)
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(reps):
+        dst.copy_(src)
+    e1.record()
+    torch.cuda.synchronize()
+    ms = e0.elapsed_time(e1) / reps
+    print(json.dumps({"mode": "copy-probe", "bytes_read": nbytes, "bytes_written": nbytes, "reps": reps,
+                      "ms": round(ms, 4), "GBps": round(2 * nbytes / ms / 1e6, 1)}), flush=True)
 
 
 if __name__ == "__main__":

@@ -35,6 +35,33 @@ __device__ __forceinline__ bool cell_of_thread(const Geom &G, int &x, int &y, in
   return true;
 }
 
+// XCD-aware tile order for a 1D grid of nb blocks.  Workgroups are handed to
+// the 8 XCDs round-robin (block b runs on XCD b % 8) and each XCD has its own
+// L2.  With the plain order, the tiles left and right of a tile run on other
+// XCDs, and the partial cache lines that an x-shifted access (odd-parity
+// streaming, the stencils) reads across the tile edge are fetched from HBM
+// once per XCD.  Here consecutive runs of `ch` tiles (one grid row in x) go
+// to one XCD, while the 8 XCDs still work on neighbouring rows at any time.
+constexpr int NXCD = 8;
+__device__ __forceinline__ int xcd_tile(int b, int nb, int ch) {
+  const int full = nb / (NXCD * ch) * (NXCD * ch);
+  if (b >= full) return b;
+  const int k = b % NXCD, j = b / NXCD;
+  return ((j / ch) * NXCD + k) * ch + j % ch;
+}
+
+__device__ __forceinline__ bool cell_of_tile(const Geom &G, int &x, int &y, int &z, long long &c) {
+  const int gx = (G.ex + BX - 1) / BX, gy = (G.ey + BY - 1) / BY;
+  const int t = xcd_tile((int)blockIdx.x, (int)gridDim.x, gx);
+  const int bx = t % gx, r = t / gx;
+  x = bx * BX + threadIdx.x;
+  y = (r % gy) * BY + threadIdx.y;
+  z = r / gy;
+  if (x >= G.ex || y >= G.ey) return false;
+  c = (long long)x + (long long)G.px * ((long long)y + (long long)G.ey * z);
+  return true;
+}
+
 // Neighbour addressing of one cell: the wrapped x, row and plane offsets for
 // steps -1, 0, +1 along each axis; neighbour i is at ox[cx+1] + oy[cy+1] +
 // oz[cz+1].  Fluid cells never sit on the storage boundary of a wall axis
@@ -322,7 +349,7 @@ template <int Q, int S, int STAGE, int ODD>
 __global__ __launch_bounds__(BX *BY) void k_cells(LatView<Q, S> L) {
   int x, y, z;
   long long c;
-  if (!cell_of_thread(L.G, x, y, z, c)) return;
+  if (!cell_of_tile(L.G, x, y, z, c)) return;
   run_stage<Q, S, STAGE, ODD>(L, x, y, z);
 }
 
@@ -517,6 +544,9 @@ __global__ __launch_bounds__(256) void k_reduce(const float4 *__restrict__ C, co
 // ---------------------------------------------------------------------------
 static dim3 cell_grid(const Geom &G) { return dim3((G.ex + BX - 1) / BX, (G.ey + BY - 1) / BY, G.ez); }
 static dim3 cell_block() { return dim3(BX, BY, 1); }
+static dim3 tile_grid(const Geom &G) {
+  return dim3((unsigned)(((G.ex + BX - 1) / BX) * ((G.ey + BY - 1) / BY) * G.ez));
+}
 static int fill_blocks(int n) { return (n + 255) / 256; }
 
 template <int Q, int S>
@@ -531,8 +561,8 @@ static LatView<Q, S> view_of_args(const LaunchArgs &a) {
 template <int Q, int S, int STAGE>
 static void cells_launch(const LaunchArgs &a, int odd) {
   const LatView<Q, S> L = view_of_args<Q, S>(a);
-  if (odd) k_cells<Q, S, STAGE, 1><<<cell_grid(a.G), cell_block(), 0, a.stream>>>(L);
-  else k_cells<Q, S, STAGE, 0><<<cell_grid(a.G), cell_block(), 0, a.stream>>>(L);
+  if (odd) k_cells<Q, S, STAGE, 1><<<tile_grid(a.G), cell_block(), 0, a.stream>>>(L);
+  else k_cells<Q, S, STAGE, 0><<<tile_grid(a.G), cell_block(), 0, a.stream>>>(L);
 }
 
 template <int Q, int S, int PI>

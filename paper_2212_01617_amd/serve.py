@@ -1,0 +1,346 @@
+"""Continuous-batching server for many droplet runs on one GPU.
+
+Requests (a droplet in shear between moving walls, or in the extensional
+flow of four rollers; D2Q9 or D3Q19; FP32 or FP16 storage) arrive as a
+Poisson process.  They are admitted in arrival order when their device
+footprint fits the memory budget and a batch slot is free, advanced
+together by one batched step (``frelbm.Batch``), sampled for the Taylor
+deformation D every 0.1 strain units, and retired when D is steady, the
+droplet has broken up, or a cap is reached (diagnostics.SteadyTracker,
+diagnostics.broken_up).  The report gives p50/p99 time-to-steady (arrival
+to retirement, host clock, read-back included) and the aggregate lattice
+update rate.
+
+The scheduler is independent of the GPU: an engine object supplies
+footprints, admission, stepping and sampling, so the scheduling logic can
+be exercised on the host with a synthetic engine.
+"""
+from __future__ import annotations
+
+import math
+import time
+from collections import deque
+from dataclasses import dataclass, field
+
+import numpy as np
+
+from . import diagnostics as Dg
+from . import synth
+
+SAMPLE_STRAIN = 0.1
+
+
+class InvalidRequest(ValueError):
+    """The library refuses the request's parameters."""
+
+
+@dataclass
+class Request:
+    rid: int
+    arrival: float      # seconds after the start of the run
+    kind: int           # 0 D2Q9, 1 D3Q19
+    n: int              # lattice size parameter N
+    flow: str           # "shear" or "rollers"
+    storage: int        # 0 FP32, 1 FP16
+    Ca: float
+    Re: float
+    xi: float = 2.0
+
+    @property
+    def radius(self) -> float:
+        return 0.2 * self.n
+
+    @property
+    def shape(self) -> tuple:
+        """(nx, ny, nz) of the lattice."""
+        n = self.n
+        if self.kind == 0:
+            return (2 * n, n, 1) if self.flow == "shear" else (n, n, 1)
+        return (2 * n, n, n) if self.flow == "shear" else (n, n, max(n // 2, 8))
+
+    @property
+    def cells(self) -> int:
+        nx, ny, nz = self.shape
+        return nx * ny * nz
+
+
+def make_requests(n: int = 256, rate: float = 20.0, seed: int = 0,
+                  d2_sizes=tuple(range(64, 513, 16)), d3_sizes=tuple(range(48, 161, 16)),
+                  Ca=(0.05, 0.4), Re=(0.1, 1.0), xi: float = 2.0) -> list[Request]:
+    """The mixed request stream: exponential inter-arrival gaps at ``rate``
+    per second; half D2Q9, half D3Q19 (sizes drawn from the given lists);
+    half shear, half four-roller; half FP32, half FP16; Ca and Re uniform.
+    Every draw is a SplitMix64 uniform of (seed, request, field)."""
+    u = synth.uniform(seed, 8 * n).reshape(n, 8)
+    out = []
+    t = 0.0
+    for k in range(n):
+        t += -math.log(1.0 - u[k, 0]) / rate
+        kind = 0 if u[k, 1] < 0.5 else 1
+        sizes = d2_sizes if kind == 0 else d3_sizes
+        size = sizes[min(int(u[k, 2] * len(sizes)), len(sizes) - 1)]
+        flow = "shear" if u[k, 3] < 0.5 else "rollers"
+        storage = 0 if u[k, 4] < 0.5 else 1
+        ca = Ca[0] + (Ca[1] - Ca[0]) * u[k, 5]
+        re = Re[0] + (Re[1] - Re[0]) * u[k, 6]
+        out.append(Request(k, t, kind, int(size), flow, storage, float(ca), float(re), xi))
+    return out
+
+
+@dataclass
+class Outcome:
+    rid: int
+    reason: str           # "steady", "breakup", "cap" or "invalid" (refused parameters)
+    arrival: float
+    admitted: float
+    retired: float
+    steps: int
+    strain: float
+    D: float
+    cells: int
+
+    @property
+    def latency(self) -> float:
+        return self.retired - self.arrival
+
+
+@dataclass
+class Report:
+    outcomes: list
+    wall: float
+    lattice_updates: float
+    peak_bytes: int
+    peak_members: int
+
+    def summary(self) -> dict:
+        lat = np.array([o.latency for o in self.outcomes]) if self.outcomes else np.zeros(1)
+        st = [o for o in self.outcomes if o.reason == "steady"]
+        tts = np.array([o.latency for o in st])
+        return {
+            "requests": len(self.outcomes),
+            "steady": len(st),
+            "breakup": sum(o.reason == "breakup" for o in self.outcomes),
+            "capped": sum(o.reason == "cap" for o in self.outcomes),
+            "invalid": sum(o.reason == "invalid" for o in self.outcomes),
+            "p50_time_to_steady_s": float(np.percentile(tts, 50)) if st else None,
+            "p99_time_to_steady_s": float(np.percentile(tts, 99)) if st else None,
+            "p50_latency_s": float(np.percentile(lat, 50)),
+            "p99_latency_s": float(np.percentile(lat, 99)),
+            "aggregate_mlups": self.lattice_updates / self.wall / 1e6 if self.wall > 0 else 0.0,
+            "wall_s": self.wall,
+            "peak_bytes": self.peak_bytes,
+            "peak_members": self.peak_members,
+        }
+
+
+@dataclass
+class _Member:
+    req: Request
+    handle: object
+    rate: float            # strain per step
+    sample_every: int      # steps between D samples
+    admitted: float
+    t: int = 0
+    next_sample: int = 0
+    tracker: Dg.SteadyTracker = field(default_factory=Dg.SteadyTracker)
+    D: float = 0.0
+
+
+class Server:
+    """Admission, stepping and retirement over an engine.
+
+    engine.footprint(req) -> bytes (raises InvalidRequest for parameters the
+    library refuses, e.g. a wall speed beyond the Mach guard);
+    engine.admit(req) -> (handle, strain per step) or None when the engine
+    cannot take it now; engine.step(n); engine.phi(handle) -> phi field;
+    engine.periodic(req) -> periodic flags (x, y, z); engine.retire(handle)."""
+
+    def __init__(self, engine, budget_bytes: int, max_members: int, chunk: int = 200,
+                 strain_cap: float = 25.0, step_cap: int = 200_000, clock=time.monotonic,
+                 sleep=time.sleep):
+        self.engine = engine
+        self.budget = int(budget_bytes)
+        self.max_members = int(max_members)
+        self.chunk = int(chunk)
+        self.strain_cap = strain_cap
+        self.step_cap = int(step_cap)
+        self.clock = clock
+        self.sleep = sleep
+
+    def _sample(self, m: _Member, now: float):
+        """Sample D (and breakup); return the retirement reason or None."""
+        phi = self.engine.phi(m.handle)
+        req = m.req
+        per = self.engine.periodic(req)
+        if Dg.broken_up(phi, per):
+            return "breakup"
+        plane = "xz" if (req.flow == "shear" and req.kind == 1) else "xy"
+        m.D = Dg.deformation(phi, plane=plane, periodic=per).D
+        strain = m.t * m.rate
+        if m.tracker.add(strain, m.D):
+            return "steady"
+        if strain >= self.strain_cap or m.t >= self.step_cap:
+            return "cap"
+        return None
+
+    def run(self, requests) -> Report:
+        outcomes = []
+        ok = []
+        for r in sorted(requests, key=lambda r: r.arrival):
+            try:
+                need = self.engine.footprint(r)
+            except InvalidRequest:
+                outcomes.append(Outcome(r.rid, "invalid", r.arrival, r.arrival, r.arrival, 0, 0.0, 0.0, r.cells))
+                continue
+            if need > self.budget:
+                raise ValueError(f"request {r.rid} needs more than the whole memory budget")
+            ok.append(r)
+        pending = deque(ok)
+        active: list[_Member] = []
+        used = 0
+        lu = 0.0
+        peak_bytes = peak_members = 0
+        t0 = self.clock()
+        while pending or active:
+            now = self.clock() - t0
+            # admission in arrival order (no overtaking)
+            while pending and pending[0].arrival <= now and len(active) < self.max_members:
+                r = pending[0]
+                need = self.engine.footprint(r)
+                if used + need > self.budget:
+                    break
+                got = self.engine.admit(r)
+                if got is None:
+                    break
+                handle, rate = got
+                pending.popleft()
+                every = max(1, int(round(SAMPLE_STRAIN / rate)))
+                active.append(_Member(r, handle, rate, every, now, next_sample=every))
+                used += need
+            peak_bytes = max(peak_bytes, used)
+            peak_members = max(peak_members, len(active))
+            if not active:
+                if pending:
+                    self.sleep(max(0.0, pending[0].arrival - (self.clock() - t0)))
+                continue
+            # step up to the next sample that falls due, at most one chunk
+            n = min(self.chunk, min(m.next_sample - m.t for m in active))
+            n = max(n, 1)
+            self.engine.step(n)
+            lu += n * sum(m.req.cells for m in active)
+            done = []
+            for m in active:
+                m.t += n
+                if m.t >= m.next_sample:
+                    m.next_sample += m.sample_every
+                    reason = self._sample(m, self.clock() - t0)
+                    if reason:
+                        done.append((m, reason))
+            for m, reason in done:
+                self.engine.retire(m.handle)
+                active.remove(m)
+                used -= self.engine.footprint(m.req)
+                outcomes.append(Outcome(m.req.rid, reason, m.req.arrival, m.admitted, self.clock() - t0,
+                                        m.t, m.t * m.rate, m.D, m.req.cells))
+        wall = self.clock() - t0
+        return Report(outcomes, wall, lu, peak_bytes, peak_members)
+
+
+# ---------------------------------------------------------------------------
+# GPU engine: lattices in one frelbm.Batch
+# ---------------------------------------------------------------------------
+def lattice_inputs(req: Request):
+    """Parameters and initial fields of a request (shear: walls normal to the
+    last axis moving at -+u_w with the linear shear profile; rollers: four
+    cylinders along z, all axes periodic)."""
+    from . import frelbm as F
+    from .params import derive_params
+    nx, ny, nz = req.shape
+    sh = (nz, ny, nx)
+    R = req.radius
+    if req.flow == "shear":
+        wall_axis = 1 if req.kind == 0 else 2
+        H = (ny, nz)[wall_axis - 1]
+        dp = derive_params(Re=req.Re, Ca=req.Ca, radius=R, xi=req.xi, H=H)
+        wu = np.zeros((3, 2, 3))
+        wu[wall_axis, 0, 0] = -dp.wall_u
+        wu[wall_axis, 1, 0] = dp.wall_u
+        bc = [0, 0, 0]
+        bc[wall_axis] = 1
+        phi0 = synth.droplet_phi(sh, R, req.xi, noise=1e-4, seed=req.rid, dims=2 if req.kind == 0 else 3)
+        u0 = synth.shear_velocity(sh, dp.rate, axis_normal=wall_axis)
+        p = F.make_params(req.kind, (nx, ny, nz), storage=req.storage, bc=tuple(bc), wall_u=wu, **dp.phys())
+        return p, phi0, u0, None, dp.rate
+    # four rollers: tip speed eps * d with d the gap from the domain centre to
+    # the roller surface (the stagnation flow u = eps (x, -y) there);
+    # uncalibrated against a single-phase run
+    dp = derive_params(Re=req.Re, Ca=req.Ca, radius=R, xi=req.xi)
+    rr = 0.117 * nx
+    cs, signs = synth.four_roller_geometry(nx, ny, rr, nz=nz)
+    d = math.hypot(nx / 4.0, ny / 4.0) - rr
+    om = dp.rate * d / rr
+    mask = synth.roller_mask(sh, cs, rr)
+    rollers = [(c, s * om, 2, rr) for c, s in zip(cs, signs)]
+    phi0 = synth.droplet_phi(sh, R, req.xi, noise=1e-4, seed=req.rid, dims=2 if req.kind == 0 else 3)
+    p = F.make_params(req.kind, (nx, ny, nz), storage=req.storage, rollers=rollers, **dp.phys())
+    return p, phi0, None, mask, dp.rate
+
+
+class GpuEngine:
+    """Lattices in torch-allocated device buffers, stepped by one Batch."""
+
+    def __init__(self, budget_bytes: int, max_members: int, keep_final: bool = False):
+        from . import frelbm as F
+        self.F = F
+        cap = max(1 << 16, budget_bytes // 2048)
+        self.batch = F.Batch(max_slots=max_members, max_work=cap, max_fill=cap)
+        self.cap = cap
+        self.work = self.fill = 0
+        self.slots = {}
+        self.keep_final = keep_final
+        self.final = {}
+        self._fp = {}
+
+    def footprint(self, req: Request) -> int:
+        if req.rid not in self._fp:
+            p, *_ = lattice_inputs(req)
+            try:
+                self._fp[req.rid] = self.F.footprint(p)
+            except self.F.FreError as e:
+                if e.status != self.F.FRE_EINVAL:
+                    raise
+                raise InvalidRequest(str(e)) from e
+        return self._fp[req.rid]
+
+    def periodic(self, req: Request):
+        if req.flow == "shear":
+            return (True, req.kind != 0, req.kind == 0)
+        return (True, True, True)
+
+    def admit(self, req: Request):
+        p, phi0, u0, mask, rate = lattice_inputs(req)
+        L = self.F.Lattice(p, phi0, None, u0, mask)
+        w, f = self.F.Batch.needs(L)
+        if self.work + w > self.cap or self.fill + f > self.cap:
+            L.close()
+            return None
+        slot = self.batch.add(L)
+        self.work += w
+        self.fill += f
+        self.slots[id(L)] = (slot, w, f, req.rid)
+        return L, rate
+
+    def step(self, n: int):
+        self.batch.step(n)
+
+    def phi(self, L):
+        return L.read(("phi",))["phi"]
+
+    def retire(self, L):
+        slot, w, f, rid = self.slots.pop(id(L))
+        if self.keep_final:
+            self.final[rid] = (L.info()[0], L.populations())
+        self.batch.remove(slot)
+        self.work -= w
+        self.fill -= f
+        L.close()
