@@ -129,6 +129,9 @@ def main():
     ap.add_argument("--no-fp16", action="store_true")
     ap.add_argument("--serve", type=int, default=24, help="requests in the serving leg (0: skip)")
     ap.add_argument("--kernels-only", type=int, default=0)
+    ap.add_argument("--no-tune", action="store_true", help="keep the default launch shapes")
+    ap.add_argument("--shape", default="", help="with --kernels-only: rows,xcd for k_moments, "
+                    "k_potential, k_collide, e.g. 4,1,4,1,4,1 (default shapes if empty)")
     ap.add_argument("--copy-probe", action="store_true")
     args = ap.parse_args()
     if args.gpus != 1:
@@ -148,9 +151,12 @@ def main():
     if args.kernels_only:
         p, phi0, u0, meta = workload(0)
         L = F.Lattice(p, phi0, None, u0, stream=stream)
+        if args.shape:
+            v = [int(t) for t in args.shape.split(",")]
+            L.set_launch_shape({k: (v[2 * i], v[2 * i + 1]) for i, k in enumerate(L.STAGES)})
         prof = L.profile(args.kernels_only)
         torch.cuda.synchronize()
-        print(json.dumps({"mode": "kernels-only", "steps": args.kernels_only,
+        print(json.dumps({"mode": "kernels-only", "steps": args.kernels_only, "launch_shape": L.launch_shape(),
                           "kernels_ms": {k: round(v, 5) for k, v in prof.items()}}), flush=True)
         return
 
@@ -158,12 +164,13 @@ def main():
     for storage in ((0,) if args.no_fp16 else (0, 1)):
         p, phi0, u0, meta = workload(storage)
         L = F.Lattice(p, phi0, None, u0, stream=stream)
+        tuned = L.autotune(10) if not args.no_tune else None
         ms, all_ms = time_steps(L, args.steps, args.warmup, args.reps)
         n_fluid = meta["shape"][0] * meta["shape"][1] * meta["shape"][2]
         prof = L.profile(20)
         ok = L.reduce()
         res[storage] = dict(ms=ms, all_ms=all_ms, n=n_fluid, prof=prof, L=L, meta=meta,
-                            p=p, phi0=phi0, u0=u0, sums=ok)
+                            p=p, phi0=phi0, u0=u0, sums=ok, shape=L.launch_shape())
 
     r = res[0]
     n = r["n"]
@@ -193,6 +200,7 @@ def main():
                      "kernel": dom, "kernel_ms": round(dom_ms, 5),
                      "step_frac": round(mlups * 1e6 * b / 1e9 / PEAK_HBM_GBS, 4)},
         "kernels_ms": {k: round(v, 5) for k, v in r["prof"].items()},
+        "launch_shape": {k: {"rows": v[0], "xcd": v[1]} for k, v in r["shape"].items()},
     }
     if 1 in res:
         r16 = res[1]
@@ -200,7 +208,8 @@ def main():
         b16 = bytes_per_lu(19, 1)
         out["fp16_store"] = {"value": round(m16, 1), "unit": "MLUPS", "ms_per_step": round(r16["ms"], 5),
                              "bytes_per_lu": b16, "step_frac": round(m16 * 1e6 * b16 / 1e9 / PEAK_HBM_GBS, 4),
-                             "kernels_ms": {k: round(v, 5) for k, v in r16["prof"].items()}}
+                             "kernels_ms": {k: round(v, 5) for k, v in r16["prof"].items()},
+                             "launch_shape": {k: {"rows": v[0], "xcd": v[1]} for k, v in r16["shape"].items()}}
     for v in res.values():
         v["L"].close()
     res.clear()

@@ -176,6 +176,25 @@ fre_status fre_profile_step(fre_lattice *L, int64_t n, double *kernel_ms,
                             int32_t max_kernels, int32_t *n_kernels);
 const char *fre_kernel_name(int32_t k);
 
+/* Launch shapes of the three cell kernels of the step (k_moments,
+ * k_potential, k_collide), cfg = {rows, xcd} per kernel in that order:
+ * rows of 64 cells per thread block (1, 2, 4 or 8) and xcd = 1 for the
+ * XCD-aware block order (0: plain order).  A shape decides only which
+ * thread updates which cell, never the arithmetic: results are bitwise the
+ * same under every shape.  Default {4, 1} for all three.  Set syncs the
+ * bound stream; FRE_EINVAL for other values. */
+fre_status fre_set_launch_shape(fre_lattice *L, const int32_t cfg[6]);
+fre_status fre_get_launch_shape(const fre_lattice *L, int32_t cfg[6]);
+
+/* Autotuner: times each of the 8 candidate shapes (rows 1, 2, 4, 8 x xcd
+ * 0, 1) over n (rounded up to even, 2 <= n <= 10000) individually launched
+ * steps per candidate and keeps, for each of the three kernels, the fastest.
+ * The lattice state (populations, step count) is copied to host memory
+ * before and restored after, so tuning leaves the run where it was.
+ * cfg_out (may be NULL) receives the chosen shapes, stage_ms (may be NULL,
+ * 3 entries) their mean kernel times.  Syncs; refuses batch members. */
+fre_status fre_autotune(fre_lattice *L, int64_t n, int32_t cfg_out[6], double stage_ms[3]);
+
 /* Release the handle (accepts NULL).  Never frees caller memory.  A batch
  * member is removed from its batch first. */
 void fre_lattice_destroy(fre_lattice *L);
@@ -195,7 +214,9 @@ void fre_lattice_destroy(fre_lattice *L);
  * fre_lattice_batch_needs).  No device work. */
 fre_status fre_batch_footprint(int32_t max_slots, int64_t max_work, int64_t max_fill, size_t *bytes);
 
-/* Work items a lattice adds to a batch (cell blocks, solid-boundary cells). */
+/* Work items a lattice adds to a batch (cell blocks, solid-boundary cells),
+ * counted at the smallest tile (one row of 64 cells), so that capacities
+ * summed from these numbers hold the members at every launch shape. */
 fre_status fre_lattice_batch_needs(const fre_lattice *L, int64_t *n_work, int64_t *n_fill);
 
 /* Create a batch in the caller's device buffer (>= fre_batch_footprint,
@@ -217,6 +238,22 @@ fre_status fre_batch_remove(fre_batch *B, int32_t slot);
 /* Advance every member n >= 0 steps, asynchronously on the batch's stream.
  * FRE_ESTATE if a member has failed. */
 fre_status fre_batch_step(fre_batch *B, int64_t n);
+
+/* Batch launch shape: rows of 64 cells per work item and block (1, 2, 4 or
+ * 8) and the persistent grid of the cell kernels in blocks per compute unit
+ * (1..32).  Default 4 rows, 8 blocks per CU.  Rebuilds the work lists
+ * (FRE_ENOMEM, shape unchanged, when they exceed the capacity).  Results are
+ * bitwise the same under every shape. */
+fre_status fre_batch_set_launch_shape(fre_batch *B, int32_t rows, int32_t blocks_per_cu);
+fre_status fre_batch_get_launch_shape(const fre_batch *B, int32_t out[2]);
+
+/* Batch autotuner: times the batch step over n (rounded up to even,
+ * 2..10000) directly launched steps for rows 1, 2, 4, 8 x blocks per CU
+ * 2, 4, 8, 16 and keeps the fastest.  Every member's state is copied to host
+ * memory before and restored after.  out (may be NULL) receives {rows,
+ * blocks per CU}, ms_per_step (may be NULL) the best mean step time.  Syncs.
+ * FRE_ESTATE for an empty batch or a failed member. */
+fre_status fre_batch_autotune(fre_batch *B, int64_t n, int32_t out[2], double *ms_per_step);
 
 /* Number of members and the common AA parity. */
 fre_status fre_batch_info(const fre_batch *B, int32_t *members, int32_t *parity);

@@ -189,7 +189,7 @@ class Lattice:
 
     def __del__(self):
         h = getattr(self, "_h", None)
-        if h:
+        if h and lib is not None:  # module globals are gone at interpreter exit
             lib().or_destroy(h)
             self._h = None
 

@@ -195,6 +195,9 @@ struct fre_batch {
   std::vector<int> h_range;
   int parity;         // common AA parity of the members
   unsigned classes;   // bit c: class c has members
+  int rows;           // rows of 64 cells per work item
+  int blocks_per_cu;  // persistent grid of the cell kernels
+  int ncu;
   hipGraphExec_t graph;
   bool graph_ok;
   int grid_cells, grid_fill;
@@ -349,6 +352,7 @@ fre_status fre_lattice_init(const fre_params *p, void *device_buf, size_t bytes,
   s = build_mask(L, solid_mask, mask, nbm);
   if (s != FRE_OK) { delete L; return s; }
   bind_args(L);
+  for (int k = 0; k < N_SHAPES; ++k) L->a.shape[k] = Shape{4, 1};
   L->a.stream = (hipStream_t)hip_stream;
   // initial fields in storage layout
   std::vector<float> M((size_t)P.ncell * 2, 0.0f), U((size_t)P.ncell * 4, 0.0f);
@@ -609,14 +613,14 @@ fre_status fre_load(fre_lattice *L, const void *host, size_t bytes) {
   return FRE_OK;
 }
 
-fre_status fre_profile_step(fre_lattice *L, int64_t n, double *kernel_ms, int32_t max_kernels,
-                            int32_t *n_kernels) {
-  if (!L || !kernel_ms || !n_kernels) return fail(FRE_EINVAL, "NULL argument");
-  if (n < 1) return fail(FRE_EINVAL, "n must be >= 1");
-  if (L->state) return fail(FRE_ESTATE, "lattice is in the failed state");
+}  // extern "C"
+
+namespace {
+
+// Mean duration (ms) of each kernel of the step over n individually launched
+// steps, from HIP events recorded on the lattice's stream around every launch.
+fre_status time_kernels(fre_lattice *L, int64_t n, double *kernel_ms) {
   const int K = step_kernel_count();
-  if (max_kernels < K) return fail(FRE_EINVAL, "kernel_ms needs %d entries", K);
-  if (L->batch) return fail(FRE_ESTATE, "lattice is a batch member: profile it alone");
   std::vector<hipEvent_t> ev((size_t)(K + 1) * n);
   for (auto &e : ev) HIP_TRY(hipEventCreate(&e));
   for (int k = 0; k < K; ++k) kernel_ms[k] = 0.0;
@@ -639,8 +643,105 @@ fre_status fre_profile_step(fre_lattice *L, int64_t n, double *kernel_ms, int32_
         kernel_ms[k] += ms / (double)n;
       }
   for (auto &e : ev) (void)hipEventDestroy(e);
+  return st;
+}
+
+// Population state of a lattice kept on the host while the tuners step it.
+struct HostState {
+  std::vector<uint8_t> pops;
+  int64_t t = 0;
+};
+
+fre_status snapshot(fre_lattice *L, HostState &h) {
+  const size_t nb = pops_bytes(L->plan, L->p.storage);
+  h.pops.resize(nb);
+  h.t = L->t;
+  HIP_TRY(hipMemcpyAsync(h.pops.data(), L->base + L->plan.o_f, nb, hipMemcpyDeviceToHost, L->a.stream));
+  HIP_TRY(hipStreamSynchronize(L->a.stream));
+  return FRE_OK;
+}
+
+fre_status restore(fre_lattice *L, const HostState &h) {
+  HIP_TRY(hipMemcpyAsync(L->base + L->plan.o_f, h.pops.data(), h.pops.size(), hipMemcpyHostToDevice, L->a.stream));
+  HIP_TRY(hipStreamSynchronize(L->a.stream));
+  L->t = h.t;
+  return FRE_OK;
+}
+
+// Stage kernels whose launch shape is tuned, as indices into the kernel list.
+const int kStageKernel[N_SHAPES] = {0, 2, 4};  // k_moments, k_potential, k_collide
+const Shape kCandidates[] = {{1, 0}, {2, 0}, {4, 0}, {8, 0}, {1, 1}, {2, 1}, {4, 1}, {8, 1}};
+
+}  // namespace
+
+extern "C" {
+
+fre_status fre_profile_step(fre_lattice *L, int64_t n, double *kernel_ms, int32_t max_kernels,
+                            int32_t *n_kernels) {
+  if (!L || !kernel_ms || !n_kernels) return fail(FRE_EINVAL, "NULL argument");
+  if (n < 1) return fail(FRE_EINVAL, "n must be >= 1");
+  if (L->state) return fail(FRE_ESTATE, "lattice is in the failed state");
+  const int K = step_kernel_count();
+  if (max_kernels < K) return fail(FRE_EINVAL, "kernel_ms needs %d entries", K);
+  if (L->batch) return fail(FRE_ESTATE, "lattice is a batch member: profile it alone");
+  fre_status st = time_kernels(L, n, kernel_ms);
   *n_kernels = K;
   return st;
+}
+
+fre_status fre_set_launch_shape(fre_lattice *L, const int32_t cfg[6]) {
+  if (!L || !cfg) return fail(FRE_EINVAL, "NULL argument");
+  Shape sh[N_SHAPES];
+  for (int k = 0; k < N_SHAPES; ++k) {
+    sh[k] = Shape{cfg[2 * k], cfg[2 * k + 1]};
+    if (!shape_ok(sh[k])) return fail(FRE_EINVAL, "bad launch shape (%d rows, xcd %d)", sh[k].rows, sh[k].xcd);
+  }
+  if (fre_status bs = sync_batch(L)) return bs;
+  HIP_TRY(hipStreamSynchronize(L->a.stream));
+  for (int k = 0; k < N_SHAPES; ++k) L->a.shape[k] = sh[k];
+  reset_graph(L);
+  return FRE_OK;
+}
+
+fre_status fre_get_launch_shape(const fre_lattice *L, int32_t cfg[6]) {
+  if (!L || !cfg) return fail(FRE_EINVAL, "NULL argument");
+  for (int k = 0; k < N_SHAPES; ++k) {
+    cfg[2 * k] = L->a.shape[k].rows;
+    cfg[2 * k + 1] = L->a.shape[k].xcd;
+  }
+  return FRE_OK;
+}
+
+fre_status fre_autotune(fre_lattice *L, int64_t n, int32_t cfg_out[6], double stage_ms[3]) {
+  if (!L) return fail(FRE_EINVAL, "lattice is NULL");
+  if (n < 2 || n > 10000) return fail(FRE_EINVAL, "n must be in [2, 10000]");
+  if (L->state) return fail(FRE_ESTATE, "lattice is in the failed state");
+  if (L->batch) return fail(FRE_ESTATE, "lattice is a batch member: tune the batch");
+  n += n & 1;  // both parities equally
+  HostState h;
+  fre_status s = snapshot(L, h);
+  if (s != FRE_OK) return s;
+  const Shape saved[N_SHAPES] = {L->a.shape[0], L->a.shape[1], L->a.shape[2]};
+  double best[N_SHAPES] = {1e300, 1e300, 1e300};
+  Shape pick[N_SHAPES] = {saved[0], saved[1], saved[2]};
+  double ms[16];
+  for (const Shape &c : kCandidates) {
+    for (int k = 0; k < N_SHAPES; ++k) L->a.shape[k] = c;
+    s = time_kernels(L, 2, ms);  // warm-up
+    if (s == FRE_OK) s = time_kernels(L, n, ms);
+    if (s != FRE_OK) break;
+    for (int k = 0; k < N_SHAPES; ++k)
+      if (ms[kStageKernel[k]] < best[k]) { best[k] = ms[kStageKernel[k]]; pick[k] = c; }
+  }
+  fre_status r = restore(L, h);
+  for (int k = 0; k < N_SHAPES; ++k) L->a.shape[k] = s == FRE_OK ? pick[k] : saved[k];
+  reset_graph(L);
+  if (s != FRE_OK) return s;
+  if (r != FRE_OK) return r;
+  if (cfg_out) fre_get_launch_shape(L, cfg_out);
+  if (stage_ms)
+    for (int k = 0; k < N_SHAPES; ++k) stage_ms[k] = best[k];
+  return FRE_OK;
 }
 
 const char *fre_kernel_name(int32_t k) { return step_kernel_name(k); }
@@ -677,9 +778,14 @@ BatchPlan batch_plan(int max_slots, int64_t max_work, int64_t max_fill) {
   return P;
 }
 
+int64_t work_items(const Geom &G, int rows) {
+  return (int64_t)((G.ex + 63) / 64) * ((G.ey + rows - 1) / rows) * G.ez;
+}
+
+// Work items at the smallest tile (one row), so a batch sized from these
+// numbers holds its members at every launch shape.
 void lattice_needs(const fre_lattice *L, int64_t *n_work, int64_t *n_fill) {
-  const Geom &G = L->a.G;
-  *n_work = (int64_t)((G.ex + 63) / 64) * ((G.ey + 3) / 4) * G.ez;
+  *n_work = work_items(L->a.G, 1);
   *n_fill = (int64_t)L->fill_host.size();
 }
 
@@ -726,7 +832,7 @@ fre_status batch_rebuild(fre_batch *B) {
       B->h_inst[k] = inst_of(L, B->base);
       const Geom &G = L->a.G;
       for (int z = 0; z < G.ez; ++z)
-        for (int by = 0; by < (G.ey + 3) / 4; ++by)
+        for (int by = 0; by < (G.ey + B->rows - 1) / B->rows; ++by)
           for (int bx = 0; bx < (G.ex + 63) / 64; ++bx) B->h_work.push_back(make_int4((int)k, bx, by, z));
       for (int s : L->fill_host) B->h_fill.push_back(make_int2((int)k, s));
     }
@@ -758,6 +864,7 @@ BatchArgs batch_args(const fre_batch *B) {
   b.range = B->d_range;
   b.grid_cells = B->grid_cells;
   b.grid_fill = B->grid_fill;
+  b.rows = B->rows;
   b.stream = B->stream;
   return b;
 }
@@ -813,7 +920,10 @@ fre_status fre_batch_create(void *device_buf, size_t bytes, void *hip_stream, in
     int v = 0;
     if (hipDeviceGetAttribute(&v, hipDeviceAttributeMultiprocessorCount, dev) == hipSuccess && v > 0) ncu = v;
   }
-  B->grid_cells = ncu * 8;
+  B->ncu = ncu;
+  B->rows = 4;
+  B->blocks_per_cu = 8;
+  B->grid_cells = ncu * B->blocks_per_cu;
   B->grid_fill = ncu * 2;
   s = batch_rebuild(B);
   if (s != FRE_OK) { delete B; return s; }
@@ -905,6 +1015,87 @@ fre_status fre_batch_step(fre_batch *B, int64_t n) {
   for (fre_lattice *L : B->slot)
     if (L) L->t += done;
   return s;
+}
+
+fre_status fre_batch_set_launch_shape(fre_batch *B, int32_t rows, int32_t blocks_per_cu) {
+  if (!B) return fail(FRE_EINVAL, "batch is NULL");
+  if (!shape_ok(Shape{rows, 0}) || blocks_per_cu < 1 || blocks_per_cu > 32)
+    return fail(FRE_EINVAL, "bad batch launch shape (%d rows, %d blocks per CU)", rows, blocks_per_cu);
+  HIP_TRY(hipStreamSynchronize(B->stream));
+  const int old_rows = B->rows, old_bpc = B->blocks_per_cu;
+  B->rows = rows;
+  B->blocks_per_cu = blocks_per_cu;
+  B->grid_cells = B->ncu * blocks_per_cu;
+  batch_reset_graph(B);
+  fre_status s = batch_rebuild(B);
+  if (s != FRE_OK) {
+    B->rows = old_rows;
+    B->blocks_per_cu = old_bpc;
+    B->grid_cells = B->ncu * old_bpc;
+    (void)batch_rebuild(B);
+  }
+  return s;
+}
+
+fre_status fre_batch_get_launch_shape(const fre_batch *B, int32_t out[2]) {
+  if (!B || !out) return fail(FRE_EINVAL, "NULL argument");
+  out[0] = B->rows;
+  out[1] = B->blocks_per_cu;
+  return FRE_OK;
+}
+
+fre_status fre_batch_autotune(fre_batch *B, int64_t n, int32_t out[2], double *ms_per_step) {
+  if (!B) return fail(FRE_EINVAL, "batch is NULL");
+  if (n < 2 || n > 10000) return fail(FRE_EINVAL, "n must be in [2, 10000]");
+  if (!B->classes) return fail(FRE_ESTATE, "batch has no members to tune on");
+  for (fre_lattice *L : B->slot)
+    if (L && L->state) return fail(FRE_ESTATE, "a member lattice is in the failed state");
+  n += n & 1;
+  HIP_TRY(hipStreamSynchronize(B->stream));
+  std::vector<HostState> hs(B->slot.size());
+  for (size_t k = 0; k < B->slot.size(); ++k)
+    if (B->slot[k]) {
+      fre_status s = snapshot(B->slot[k], hs[k]);
+      if (s != FRE_OK) return s;
+    }
+  const int parity0 = B->parity, rows0 = B->rows, bpc0 = B->blocks_per_cu;
+  static const int kRows[] = {1, 2, 4, 8};
+  static const int kBpc[] = {2, 4, 8, 16};
+  double best = 1e300;
+  int best_rows = rows0, best_bpc = bpc0;
+  hipEvent_t e0, e1;
+  HIP_TRY(hipEventCreate(&e0));
+  HIP_TRY(hipEventCreate(&e1));
+  fre_status s = FRE_OK;
+  for (int rows : kRows)
+    for (int bpc : kBpc) {
+      if (fre_batch_set_launch_shape(B, rows, bpc) != FRE_OK) continue;  // lists do not fit
+      int par = B->parity;
+      for (int w = 0; w < 2; ++w, par ^= 1) batch_launch_step(B, par);
+      (void)hipEventRecord(e0, B->stream);
+      for (int64_t k = 0; k < n; ++k, par ^= 1) batch_launch_step(B, par);
+      (void)hipEventRecord(e1, B->stream);
+      hipError_t e = hipStreamSynchronize(B->stream);
+      if (e == hipSuccess) e = hipGetLastError();
+      if (e != hipSuccess) { s = fail(FRE_EDEVICE, "batch tuning step failed: %s", hipGetErrorString(e)); break; }
+      float ms = 0.0f;
+      (void)hipEventElapsedTime(&ms, e0, e1);
+      if (ms / n < best) { best = ms / n; best_rows = rows; best_bpc = bpc; }
+    }
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
+  for (size_t k = 0; k < B->slot.size(); ++k)
+    if (B->slot[k]) {
+      fre_status r = restore(B->slot[k], hs[k]);
+      if (r != FRE_OK && s == FRE_OK) s = r;
+    }
+  B->parity = parity0;
+  fre_status r = fre_batch_set_launch_shape(B, s == FRE_OK ? best_rows : rows0, s == FRE_OK ? best_bpc : bpc0);
+  if (s != FRE_OK) return s;
+  if (r != FRE_OK) return r;
+  if (out) { out[0] = B->rows; out[1] = B->blocks_per_cu; }
+  if (ms_per_step) *ms_per_step = best;
+  return FRE_OK;
 }
 
 fre_status fre_batch_info(const fre_batch *B, int32_t *members, int32_t *parity) {

@@ -8,6 +8,19 @@
 
 namespace frelbm {
 
+// Launch shape of one cell kernel: rows of 64 cells per block (1, 2, 4 or
+// 8) and whether blocks are placed in XCD-aware order.  The shape changes
+// only which thread does which cell, never the arithmetic.
+struct Shape {
+  int rows;
+  int xcd;
+};
+enum { SHAPE_MOMENTS = 0, SHAPE_POTENTIAL = 1, SHAPE_COLLIDE = 2, N_SHAPES = 3 };
+constexpr int MAX_ROWS = 8;
+inline bool shape_ok(const Shape &s) {
+  return (s.rows == 1 || s.rows == 2 || s.rows == 4 || s.rows == 8) && (s.xcd == 0 || s.xcd == 1);
+}
+
 // Everything one launch sequence needs; all pointers are device pointers
 // carved from the caller's buffer.
 struct LaunchArgs {
@@ -25,6 +38,7 @@ struct LaunchArgs {
   float4 *AUX;  // u0 at init; (ux, uy, uz, P) after observe
   int *fill_list;
   int n_fill;
+  Shape shape[N_SHAPES];
   hipStream_t stream;
 };
 
@@ -47,6 +61,7 @@ template <int Q, int S> struct LatView {
   Phys ph;
   const int *fill;
   int n_fill;
+  int xcd;  // XCD-aware block order (single-lattice kernels)
 };
 
 // One slot of a batch, as stored in device memory.  Arrays are given as
@@ -75,6 +90,7 @@ struct BatchArgs {
   const int2 *fill;
   const int *range;
   int grid_cells, grid_fill;
+  int rows;  // rows of 64 cells per work item (and per block)
   hipStream_t stream;
 };
 

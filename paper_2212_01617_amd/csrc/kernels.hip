@@ -50,12 +50,15 @@ __device__ __forceinline__ int xcd_tile(int b, int nb, int ch) {
   return ((j / ch) * NXCD + k) * ch + j % ch;
 }
 
-__device__ __forceinline__ bool cell_of_tile(const Geom &G, int &x, int &y, int &z, long long &c) {
-  const int gx = (G.ex + BX - 1) / BX, gy = (G.ey + BY - 1) / BY;
-  const int t = xcd_tile((int)blockIdx.x, (int)gridDim.x, gx);
+// Cell of this thread in a 1D grid of 64 x blockDim.y tiles (x fastest,
+// then y, then z), in XCD-aware order when `xcd` is set.
+__device__ __forceinline__ bool cell_of_tile(const Geom &G, int xcd, int &x, int &y, int &z, long long &c) {
+  const int rows = (int)blockDim.y;
+  const int gx = (G.ex + BX - 1) / BX, gy = (G.ey + rows - 1) / rows;
+  const int t = xcd ? xcd_tile((int)blockIdx.x, (int)gridDim.x, gx) : (int)blockIdx.x;
   const int bx = t % gx, r = t / gx;
   x = bx * BX + threadIdx.x;
-  y = (r % gy) * BY + threadIdx.y;
+  y = (r % gy) * rows + threadIdx.y;
   z = r / gy;
   if (x >= G.ex || y >= G.ey) return false;
   c = (long long)x + (long long)G.px * ((long long)y + (long long)G.ey * z);
@@ -346,10 +349,10 @@ __device__ __forceinline__ void run_stage(const LatView<Q, S> &L, int x, int y, 
 }
 
 template <int Q, int S, int STAGE, int ODD>
-__global__ __launch_bounds__(BX *BY) void k_cells(LatView<Q, S> L) {
+__global__ __launch_bounds__(BX *MAX_ROWS) void k_cells(LatView<Q, S> L) {
   int x, y, z;
   long long c;
-  if (!cell_of_tile(L.G, x, y, z, c)) return;
+  if (!cell_of_tile(L.G, L.xcd, x, y, z, c)) return;
   run_stage<Q, S, STAGE, ODD>(L, x, y, z);
 }
 
@@ -375,17 +378,18 @@ __device__ __forceinline__ LatView<Q, S> view_of(char *base, const Inst &I) {
   L.nbm = (const uint32_t *)(base + I.nbm); L.mask = (const uint8_t *)(base + I.mask);
   L.M = (float2 *)(base + I.M); L.C = (float4 *)(base + I.C); L.MUP = (float *)(base + I.MUP);
   L.G = I.G; L.ph = I.ph; L.fill = (const int *)(base + I.fill); L.n_fill = I.n_fill;
+  L.xcd = 0;
   return L;
 }
 
 template <int Q, int S, int STAGE, int ODD>
-__global__ __launch_bounds__(BX *BY) void k_batch_cells(char *base, const Inst *__restrict__ inst, const int4 *__restrict__ work,
+__global__ __launch_bounds__(BX *MAX_ROWS) void k_batch_cells(char *base, const Inst *__restrict__ inst, const int4 *__restrict__ work,
                                                         const int *__restrict__ range) {
   const int start = range[0], n = range[1];
   for (int w = blockIdx.x; w < n; w += gridDim.x) {
     const int4 it = work[start + w];
     const LatView<Q, S> L = view_of<Q, S>(base, inst[it.x]);
-    const int x = it.y * BX + threadIdx.x, y = it.z * BY + threadIdx.y, z = it.w;
+    const int x = it.y * BX + threadIdx.x, y = it.z * (int)blockDim.y + threadIdx.y, z = it.w;
     if (x < L.G.ex && y < L.G.ey) run_stage<Q, S, STAGE, ODD>(L, x, y, z);
   }
 }
@@ -544,8 +548,8 @@ __global__ __launch_bounds__(256) void k_reduce(const float4 *__restrict__ C, co
 // ---------------------------------------------------------------------------
 static dim3 cell_grid(const Geom &G) { return dim3((G.ex + BX - 1) / BX, (G.ey + BY - 1) / BY, G.ez); }
 static dim3 cell_block() { return dim3(BX, BY, 1); }
-static dim3 tile_grid(const Geom &G) {
-  return dim3((unsigned)(((G.ex + BX - 1) / BX) * ((G.ey + BY - 1) / BY) * G.ez));
+static dim3 tile_grid(const Geom &G, int rows) {
+  return dim3((unsigned)(((G.ex + BX - 1) / BX) * ((G.ey + rows - 1) / rows) * G.ez));
 }
 static int fill_blocks(int n) { return (n + 255) / 256; }
 
@@ -555,14 +559,20 @@ static LatView<Q, S> view_of_args(const LaunchArgs &a) {
   L.P = make_pops<Q, S>(a);
   L.nbm = a.nbm; L.mask = a.mask; L.M = a.M; L.C = a.C; L.MUP = a.MUP;
   L.G = a.G; L.ph = a.ph; L.fill = a.fill_list; L.n_fill = a.n_fill;
+  L.xcd = 1;
   return L;
 }
 
+// STAGE (ST_MOMENTS, ST_POTENTIAL, ST_COLLIDE) doubles as the index of the
+// stage's launch shape.
 template <int Q, int S, int STAGE>
 static void cells_launch(const LaunchArgs &a, int odd) {
-  const LatView<Q, S> L = view_of_args<Q, S>(a);
-  if (odd) k_cells<Q, S, STAGE, 1><<<tile_grid(a.G), cell_block(), 0, a.stream>>>(L);
-  else k_cells<Q, S, STAGE, 0><<<tile_grid(a.G), cell_block(), 0, a.stream>>>(L);
+  LatView<Q, S> L = view_of_args<Q, S>(a);
+  const Shape sh = a.shape[STAGE];
+  L.xcd = sh.xcd;
+  const dim3 grid = tile_grid(a.G, sh.rows), block(BX, sh.rows, 1);
+  if (odd) k_cells<Q, S, STAGE, 1><<<grid, block, 0, a.stream>>>(L);
+  else k_cells<Q, S, STAGE, 0><<<grid, block, 0, a.stream>>>(L);
 }
 
 template <int Q, int S, int PI>
@@ -648,7 +658,7 @@ void launch_read_pops(const LaunchArgs &a, int odd, float *out) { FRE_DISPATCH(r
 template <int Q, int S>
 static void batch_step_impl(const BatchArgs &b, int cls, int odd) {
   const int *rc = b.range + 4 * cls, *rf = rc + 2;
-  const dim3 bl = cell_block();
+  const dim3 bl(BX, b.rows, 1);
   if (odd) k_batch_cells<Q, S, ST_MOMENTS, 1><<<b.grid_cells, bl, 0, b.stream>>>(b.base, b.inst, b.work, rc);
   else k_batch_cells<Q, S, ST_MOMENTS, 0><<<b.grid_cells, bl, 0, b.stream>>>(b.base, b.inst, b.work, rc);
   k_batch_fill<Q, S, 0><<<b.grid_fill, 256, 0, b.stream>>>(b.base, b.inst, b.fill, rf);

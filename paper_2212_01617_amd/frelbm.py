@@ -69,6 +69,9 @@ _SIGS = [
     ("fre_profile_step", C.c_int32, [C.c_void_p, C.c_int64, C.c_void_p, C.c_int32,
                                      C.POINTER(C.c_int32)]),
     ("fre_kernel_name", C.c_char_p, [C.c_int32]),
+    ("fre_set_launch_shape", C.c_int32, [C.c_void_p, C.c_void_p]),
+    ("fre_get_launch_shape", C.c_int32, [C.c_void_p, C.c_void_p]),
+    ("fre_autotune", C.c_int32, [C.c_void_p, C.c_int64, C.c_void_p, C.c_void_p]),
     ("fre_lattice_destroy", None, [C.c_void_p]),
     ("fre_batch_footprint", C.c_int32, [C.c_int32, C.c_int64, C.c_int64, C.POINTER(C.c_size_t)]),
     ("fre_lattice_batch_needs", C.c_int32, [C.c_void_p, C.POINTER(C.c_int64), C.POINTER(C.c_int64)]),
@@ -78,6 +81,9 @@ _SIGS = [
     ("fre_batch_remove", C.c_int32, [C.c_void_p, C.c_int32]),
     ("fre_batch_step", C.c_int32, [C.c_void_p, C.c_int64]),
     ("fre_batch_info", C.c_int32, [C.c_void_p, C.POINTER(C.c_int32), C.POINTER(C.c_int32)]),
+    ("fre_batch_set_launch_shape", C.c_int32, [C.c_void_p, C.c_int32, C.c_int32]),
+    ("fre_batch_get_launch_shape", C.c_int32, [C.c_void_p, C.c_void_p]),
+    ("fre_batch_autotune", C.c_int32, [C.c_void_p, C.c_int64, C.c_void_p, C.POINTER(C.c_double)]),
     ("fre_batch_destroy", None, [C.c_void_p]),
     ("fre_last_error", C.c_char_p, []),
 ]
@@ -239,6 +245,26 @@ class Lattice:
         _check(lib().fre_profile_step(self._h, int(n), _ptr(ms), 16, C.byref(k)))
         return {lib().fre_kernel_name(i).decode(): float(ms[i]) for i in range(k.value)}
 
+    STAGES = ("k_moments", "k_potential", "k_collide")
+
+    def launch_shape(self) -> dict:
+        """{kernel: (rows, xcd)} for the three cell kernels."""
+        cfg = np.zeros(6, np.int32)
+        _check(lib().fre_get_launch_shape(self._h, _ptr(cfg)))
+        return {k: (int(cfg[2 * i]), int(cfg[2 * i + 1])) for i, k in enumerate(self.STAGES)}
+
+    def set_launch_shape(self, shape: dict):
+        cfg = np.array([v for k in self.STAGES for v in shape[k]], np.int32)
+        _check(lib().fre_set_launch_shape(self._h, _ptr(cfg)))
+
+    def autotune(self, n: int = 10) -> dict:
+        """Pick the fastest launch shape per cell kernel (state is restored);
+        returns {kernel: (rows, xcd, ms)}."""
+        cfg = np.zeros(6, np.int32)
+        ms = np.zeros(3)
+        _check(lib().fre_autotune(self._h, int(n), _ptr(cfg), _ptr(ms)))
+        return {k: (int(cfg[2 * i]), int(cfg[2 * i + 1]), float(ms[i])) for i, k in enumerate(self.STAGES)}
+
     def save(self) -> bytes:
         n = C.c_size_t()
         _check(lib().fre_state_bytes(self._h, C.byref(n)))
@@ -292,6 +318,23 @@ class Batch:
         m, p = C.c_int32(), C.c_int32()
         _check(lib().fre_batch_info(self._h, C.byref(m), C.byref(p)))
         return m.value, p.value
+
+    def launch_shape(self):
+        """(rows per work item, persistent blocks per CU)."""
+        out = np.zeros(2, np.int32)
+        _check(lib().fre_batch_get_launch_shape(self._h, _ptr(out)))
+        return int(out[0]), int(out[1])
+
+    def set_launch_shape(self, rows: int, blocks_per_cu: int):
+        _check(lib().fre_batch_set_launch_shape(self._h, int(rows), int(blocks_per_cu)))
+
+    def autotune(self, n: int = 10):
+        """Pick the fastest (rows, blocks per CU) on the current members
+        (their states are restored); returns (rows, blocks_per_cu, ms/step)."""
+        out = np.zeros(2, np.int32)
+        ms = C.c_double()
+        _check(lib().fre_batch_autotune(self._h, int(n), _ptr(out), C.byref(ms)))
+        return int(out[0]), int(out[1]), ms.value
 
     def close(self):
         if getattr(self, "_h", None):

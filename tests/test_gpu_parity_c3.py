@@ -1,0 +1,114 @@
+"""Parity at the benchmark's shapes.
+
+* The full D3Q19 shear lattice 256x128x128 (walls in z, R=25, xi=2, Ca=0.1,
+  Re=1), FP32 storage, stepped exactly as the benchmark steps it (its own
+  stream, captured two-step graphs), against the FP64 oracle on every cell
+  after 20 steps.
+* A 64x32x32 copy with the same per-cell parameters and shear rate (H=32,
+  R=6.25) after 2000 steps: every field, and the Taylor deformation D
+  computed the same way from both phi fields, within 1%.
+* FP16 storage on the copy: the deviation of phi, u and D is stated.
+"""
+import sys
+import os
+
+import numpy as np
+import pytest
+import torch
+
+from oracle import oracle as O
+from paper_2212_01617_amd import diagnostics as Dg
+from paper_2212_01617_amd import frelbm as F
+from paper_2212_01617_amd import synth
+from paper_2212_01617_amd.params import derive_params
+
+from _pair import ensure_gpu_lib, field_errors, log, pop_errors
+
+sys.path.insert(0, os.path.dirname(os.path.dirname(os.path.abspath(__file__))))
+import bench  # noqa: E402
+
+pytestmark = pytest.mark.gpu
+
+TOL = {"rho": 1e-5, "phi": 1e-5, "u": 1e-5, "mu_rho": 1e-6, "mu_phi": 1e-6, "P": 1e-6}
+
+
+@pytest.fixture(scope="module", autouse=True)
+def _lib():
+    assert torch.cuda.is_available(), "GPU tests need a GPU"
+    ensure_gpu_lib()
+
+
+def _oracle(p_meta, phi0, u0):
+    nx, ny, nz = p_meta["shape"]
+    po = O.make_params(1, (nx, ny, nz), bc=(0, 0, 1), wall_u=p_meta["wall_u"], **p_meta["phys"])
+    return O.Lattice(po, phi0, None, u0)
+
+
+def test_full_size_c3_in_bench_launch_configuration():
+    p, phi0, u0, meta = bench.workload(0)
+    stream = torch.cuda.Stream()
+    gpu = F.Lattice(p, phi0, None, u0, stream=stream)
+    gpu.step(20)
+    ref = _oracle(meta, phi0, u0)
+    ref.step(20)
+    err = field_errors(ref, gpu)
+    pf, pg = pop_errors(ref, gpu)
+    log("[parity] c3_full_20: " + " ".join(f"{k}={v:.2e}" for k, v in err.items()) + f" f={pf:.2e} g={pg:.2e}")
+    for k, v in TOL.items():
+        assert err[k] < v, (k, err[k])
+    assert pf < 1e-5 and pg < 1e-5
+
+
+def _copy_case(storage):
+    dp = derive_params(Re=1.0, Ca=0.1, radius=25.0, xi=2.0, H=128, Pe=0.43)
+    nx, ny, nz = 64, 32, 32
+    uw = dp.rate * nz / 2.0
+    wu = np.zeros((3, 2, 3)); wu[2, 0, 0] = -uw; wu[2, 1, 0] = uw
+    sh = (nz, ny, nx)
+    phi0 = synth.droplet_phi(sh, 6.25, 2.0, noise=1e-4, seed=0)
+    u0 = synth.shear_velocity(sh, dp.rate, axis_normal=2)
+    meta = dict(shape=(nx, ny, nz), wall_u=wu, phys=dp.phys())
+    p = F.make_params(1, (nx, ny, nz), storage=storage, bc=(0, 0, 1), wall_u=wu, **dp.phys())
+    return p, phi0, u0, meta
+
+
+@pytest.fixture(scope="module")
+def copy_oracle():
+    p, phi0, u0, meta = _copy_case(0)
+    ref = _oracle(meta, phi0, u0)
+    ref.step(2000)
+    return ref
+
+
+def _deformation(phi):
+    return Dg.deformation(phi, plane="xz", periodic=(True, True, False)).D
+
+
+def test_c3_copy_2000_steps_fields_and_deformation(copy_oracle):
+    p, phi0, u0, meta = _copy_case(0)
+    gpu = F.Lattice(p, phi0, None, u0, stream=torch.cuda.Stream())
+    gpu.step(2000)
+    err = field_errors(copy_oracle, gpu)
+    d_ref = _deformation(copy_oracle.observe()["phi"])
+    d_gpu = _deformation(gpu.read(("phi",))["phi"])
+    rel = abs(d_gpu - d_ref) / abs(d_ref)
+    log("[parity] c3_copy_2000: " + " ".join(f"{k}={v:.2e}" for k, v in err.items())
+        + f" D_oracle={d_ref:.5f} D_gpu={d_gpu:.5f} rel={rel:.2e}")
+    for k, v in TOL.items():
+        assert err[k] < v, (k, err[k])
+    assert d_ref > 1e-3          # the drop has deformed
+    assert rel < 0.01
+
+
+def test_c3_copy_fp16_storage_error_stated(copy_oracle):
+    p, phi0, u0, meta = _copy_case(1)
+    gpu = F.Lattice(p, phi0, None, u0)
+    gpu.step(2000)
+    err = field_errors(copy_oracle, gpu)
+    d_ref = _deformation(copy_oracle.observe()["phi"])
+    d_gpu = _deformation(gpu.read(("phi",))["phi"])
+    rel = abs(d_gpu - d_ref) / abs(d_ref)
+    log("[parity] c3_copy_fp16_2000: " + " ".join(f"{k}={v:.2e}" for k, v in err.items())
+        + f" D_oracle={d_ref:.5f} D_gpu={d_gpu:.5f} rel={rel:.2e}")
+    # stated error of FP16 storage after 2000 steps
+    assert err["phi"] < 2e-2 and err["u"] < 2e-3 and rel < 0.05
