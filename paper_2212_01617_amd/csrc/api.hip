@@ -259,8 +259,8 @@ fre_status build_mask(fre_lattice *L, const uint8_t *user_mask, std::vector<uint
           nbm[s] = bits;
           continue;
         }
-        bool near = false;
-        for (int i = 1; i < P.q && !near; ++i) {
+        uint32_t fluid = 0;
+        for (int i = 1; i < P.q; ++i) {
           int v[3] = {x + dir(i, 0), y + dir(i, 1), z + dir(i, 2)};
           bool ok = true;
           for (int a = 0; a < 3; ++a) {
@@ -269,9 +269,10 @@ fre_status build_mask(fre_lattice *L, const uint8_t *user_mask, std::vector<uint
           }
           if (!ok) continue;
           long long n = v[0] + (long long)P.px * (v[1] + (long long)P.ext[1] * v[2]);
-          near = mask[n] == CELL_FLUID;
+          if (mask[n] == CELL_FLUID) fluid |= 1u << i;
         }
-        if (near) L->fill_host.push_back((int)s);
+        nbm[s] = NB_SELF_SOLID | fluid;
+        if (fluid) L->fill_host.push_back((int)s);
       }
   return FRE_OK;
 }

@@ -129,30 +129,36 @@ __device__ __forceinline__ void stage_moments(const LatView<Q, S> &L, int x, int
 }
 
 // Weighted mean over the fluid neighbours of solid cell s (coordinates x, y,
-// z) of the NC leading floats of a field with stride ST floats per cell.
+// z) of the NC leading floats of a field with stride ST floats per cell.  Bit
+// i of `fluid_bits` (the solid cell's neighbour word) is set when the
+// neighbour along c_i is fluid; all loads are issued before the sums, which
+// run in direction order.
 template <int Q, int NC, int ST>
-__device__ __forceinline__ void fluid_mean(const float *__restrict__ X, const uint8_t *__restrict__ mask,
-                                           const Geom &G, int x, int y, int z, float *out) {
+__device__ __forceinline__ void fluid_mean(const float *__restrict__ X, uint32_t fluid_bits, const Geom &G,
+                                           int x, int y, int z, float *out) {
   using V = VSet<Q>;
+  float v[Q][NC];
+#pragma unroll
+  for (int i = 1; i < Q; ++i) {
+    if (!((fluid_bits >> i) & 1u)) continue;
+    const int xn = wrap(x + V::cx(i), G.ex), yn = wrap(y + V::cy(i), G.ey);
+    const int zn = V::D == 3 ? wrap(z + V::cz(i), G.ez) : z;
+    const long long n2 = (long long)xn + (long long)G.px * ((long long)yn + (long long)G.ey * zn);
+#pragma unroll
+    for (int k = 0; k < NC; ++k) v[i][k] = X[ST * n2 + k];
+  }
   float num[NC], den = 0.0f;
 #pragma unroll
   for (int k = 0; k < NC; ++k) num[k] = 0.0f;
 #pragma unroll
   for (int i = 1; i < Q; ++i) {
-    int xn = x + V::cx(i), yn = y + V::cy(i), zn = z + V::cz(i);
-    if (G.per[0]) xn = wrap(xn, G.ex); else if (xn < 0 || xn >= G.ex) continue;
-    if (G.per[1]) yn = wrap(yn, G.ey); else if (yn < 0 || yn >= G.ey) continue;
-    if (V::D == 3) {
-      if (G.per[2]) zn = wrap(zn, G.ez); else if (zn < 0 || zn >= G.ez) continue;
-    }
-    long long n2 = (long long)xn + (long long)G.px * ((long long)yn + (long long)G.ey * zn);
-    if (mask[n2] != CELL_FLUID) continue;
-    float w = V::w(i);
+    if (!((fluid_bits >> i) & 1u)) continue;
+    const float w = V::w(i);
 #pragma unroll
-    for (int k = 0; k < NC; ++k) num[k] += w * X[ST * n2 + k];
+    for (int k = 0; k < NC; ++k) num[k] += w * v[i][k];
     den += w;
   }
-  float inv = den > 0.0f ? 1.0f / den : 0.0f;
+  const float inv = den > 0.0f ? 1.0f / den : 0.0f;
 #pragma unroll
   for (int k = 0; k < NC; ++k) out[k] = num[k] * inv;
 }
@@ -171,7 +177,7 @@ __device__ __forceinline__ void stage_fill_m(const LatView<Q, S> &L, int s) {
   int x, y, z;
   cell_coords(L.G, s, x, y, z);
   float v[2];
-  fluid_mean<Q, 2, 2>((const float *)L.M, L.mask, L.G, x, y, z, v);
+  fluid_mean<Q, 2, 2>((const float *)L.M, L.nbm[s], L.G, x, y, z, v);
   L.M[s] = make_float2(v[0], v[1]);
 }
 
@@ -181,7 +187,7 @@ __device__ __forceinline__ void stage_fill_c(const LatView<Q, S> &L, int s) {
   int x, y, z;
   cell_coords(L.G, s, x, y, z);
   float pi;
-  fluid_mean<Q, 1, 4>((const float *)L.C + 2, L.mask, L.G, x, y, z, &pi);
+  fluid_mean<Q, 1, 4>((const float *)L.C + 2, L.nbm[s], L.G, x, y, z, &pi);
   const float2 m = L.M[s];
   L.C[s] = make_float4(m.x, m.y, pi, 0.0f);
 }
