@@ -192,14 +192,15 @@ __device__ __forceinline__ void stage_fill_c(const LatView<Q, S> &L, int s) {
   L.C[s] = make_float4(m.x, m.y, pi, 0.0f);
 }
 
-template <int Q>
-__device__ __forceinline__ void laplacians(const float2 *__restrict__ M, const Nbr &N, float2 m0,
-                                           float &lr, float &lp) {
+// Laplacians of rho and phi at a cell with moments m0; fetch(i) gives the
+// moments of the neighbour along c_i.
+template <int Q, class Fetch>
+__device__ __forceinline__ void laplacians(Fetch fetch, float2 m0, float &lr, float &lp) {
   using V = VSet<Q>;
   float ar = 0.0f, ap = 0.0f;
 #pragma unroll
   for (int i = 1; i < Q; ++i) {
-    float2 m = M[N.template at<V>(i)];
+    const float2 m = fetch(i);
     ar += V::w(i) * (m.x - m0.x);
     ap += V::w(i) * (m.y - m0.y);
   }
@@ -207,18 +208,26 @@ __device__ __forceinline__ void laplacians(const float2 *__restrict__ M, const N
   lp = 6.0f * ap;
 }
 
+// mu_rho, mu_phi and Pi of fluid cell c into C and MUP.
+template <int Q, int S>
+__device__ __forceinline__ void store_potential(const LatView<Q, S> &L, long long c, float2 m0, float lr,
+                                                float lp) {
+  float mr, mp;
+  chem_pot(L.ph, m0.x, m0.y, lr, lp, mr, mp);
+  L.C[c] = make_float4(m0.x, m0.y, (1.0f + m0.x) * mr + m0.y * mp, mr);
+  L.MUP[c] = mp;
+}
+
 template <int Q, int S>
 __device__ __forceinline__ void stage_potential(const LatView<Q, S> &L, int x, int y, int z) {
+  using V = VSet<Q>;
   const long long c = (long long)x + (long long)L.G.px * ((long long)y + (long long)L.G.ey * z);
   if (L.nbm[c] & NB_SELF_SOLID) return;
   const Nbr N(L.G, x, y, z);
   const float2 m0 = L.M[c];
   float lr, lp;
-  laplacians<Q>(L.M, N, m0, lr, lp);
-  float mr, mp;
-  chem_pot(L.ph, m0.x, m0.y, lr, lp, mr, mp);
-  L.C[c] = make_float4(m0.x, m0.y, (1.0f + m0.x) * mr + m0.y * mp, mr);
-  L.MUP[c] = mp;
+  laplacians<Q>([&](int i) { return L.M[N.template at<V>(i)]; }, m0, lr, lp);
+  store_potential<Q, S>(L, c, m0, lr, lp);
 }
 
 // Force of eq. (F) in product-rule form:
@@ -370,6 +379,68 @@ __global__ __launch_bounds__(256) void k_fill(LatView<Q, S> L) {
   else stage_fill_m<Q, S>(L, L.fill[k]);
 }
 
+// Potential of a single lattice with the moments staged through LDS: a block
+// owns a 64 x blockDim.y column of cells over `tz` consecutive planes and
+// keeps three planes of M (with a one-cell halo in x and y) in a ring, so
+// each M value is read from memory about once per block instead of once per
+// neighbour.  Same arithmetic as stage_potential.
+template <int Q, int S>
+__global__ __launch_bounds__(BX *MAX_ROWS) void k_potential_zm(LatView<Q, S> L, int tz) {
+  using V = VSet<Q>;
+  constexpr int HW = BX + 2;
+  __shared__ float2 ring[3][MAX_ROWS + 2][HW];
+  const Geom &G = L.G;
+  const int rows = (int)blockDim.y;
+  const int gx = (G.ex + BX - 1) / BX, gy = (G.ey + rows - 1) / rows;
+  const int t = L.xcd ? xcd_tile((int)blockIdx.x, (int)gridDim.x, gx) : (int)blockIdx.x;
+  const int bx = t % gx, r = t / gx, by = r % gy, ch = r / gy;
+  const int xlo = bx * BX, ylo = by * rows;
+  const int z0 = ch * tz, z1 = min(z0 + tz, G.ez);
+  const int w = min(BX, G.ex - xlo), h = min(rows, G.ey - ylo);  // cells of the tile on the lattice
+  const int tid = threadIdx.y * BX + threadIdx.x, nth = BX * rows;
+  const int hcells = (rows + 2) * HW;
+  // plane zs (wrapped on a periodic axis, skipped outside a wall axis) into
+  // ring slot `slot`; halo columns and rows beyond the tile's cells + 1 are
+  // never read
+  auto load_plane = [&](int zs, int slot) {
+    int zz = zs;
+    if (zz < 0 || zz >= G.ez) zz = G.per[2] ? wrap(zz, G.ez) : -1;
+    for (int k = tid; k < hcells; k += nth) {
+      const int hy = k / HW, hx = k - hy * HW;
+      float2 v = make_float2(0.0f, 0.0f);
+      if (zz >= 0 && hx <= w + 1 && hy <= h + 1) {
+        int xg = xlo - 1 + hx, yg = ylo - 1 + hy;
+        bool ok = true;
+        if (xg < 0 || xg >= G.ex) { if (G.per[0]) xg = wrap(xg, G.ex); else ok = false; }
+        if (yg < 0 || yg >= G.ey) { if (G.per[1]) yg = wrap(yg, G.ey); else ok = false; }
+        if (ok) v = L.M[(long long)xg + (long long)G.px * ((long long)yg + (long long)G.ey * zz)];
+      }
+      ring[slot][hy][hx] = v;
+    }
+  };
+  if (V::D == 3) load_plane(z0 - 1, 0);
+  load_plane(z0, 1);
+  const int tx = threadIdx.x, ty = threadIdx.y;
+  for (int z = z0; z < z1; ++z) {
+    const int sd = (z - z0) % 3, sc = (z - z0 + 1) % 3, su = (z - z0 + 2) % 3;
+    if (V::D == 3) load_plane(z + 1, su);
+    __syncthreads();
+    if (tx < w && ty < h) {
+      const long long c = (long long)(xlo + tx) + (long long)G.px * ((long long)(ylo + ty) + (long long)G.ey * z);
+      if (!(L.nbm[c] & NB_SELF_SOLID)) {
+        const float2 m0 = ring[sc][ty + 1][tx + 1];
+        float lr, lp;
+        laplacians<Q>([&](int i) {
+          const int sl = V::cz(i) < 0 ? sd : (V::cz(i) > 0 ? su : sc);
+          return ring[sl][ty + 1 + V::cy(i)][tx + 1 + V::cx(i)];
+        }, m0, lr, lp);
+        store_potential<Q, S>(L, c, m0, lr, lp);
+      }
+    }
+    __syncthreads();
+  }
+}
+
 // ---------------------------------------------------------------------------
 // Batched persistent kernels: a fixed grid walks a device-side work list of
 // (slot, block-x, block-y, z) items (or (slot, cell) fill items) for the
@@ -426,7 +497,7 @@ __global__ __launch_bounds__(BX *BY) void k_init(Pops<Q, S> P, const uint32_t *_
   const Nbr N(G, x, y, z);
   float2 m0 = M[c];
   float lr, lp, mr, mp;
-  laplacians<Q>(M, N, m0, lr, lp);
+  laplacians<Q>([&](int i) { return M[N.template at<V>(i)]; }, m0, lr, lp);
   chem_pot(ph, m0.x, m0.y, lr, lp, mr, mp);
   float4 u4 = U0[c];
   float u[3] = {u4.x, u4.y, u4.z};
@@ -589,6 +660,21 @@ static void fill_launch(const LaunchArgs &a) {
 template <int Q, int S>
 static void moments_launch(const LaunchArgs &a, int odd) { cells_launch<Q, S, ST_MOMENTS>(a, odd); }
 
+// The z-marching potential: planes per block chosen so that the grid has
+// about 2048 blocks (8 per CU).
+template <int Q, int S>
+static void potential_launch(const LaunchArgs &a) {
+  LatView<Q, S> L = view_of_args<Q, S>(a);
+  const Shape sh = a.shape[SHAPE_POTENTIAL];
+  L.xcd = sh.xcd;
+  const int tiles = ((a.G.ex + BX - 1) / BX) * ((a.G.ey + sh.rows - 1) / sh.rows);
+  int nch = (2048 + tiles - 1) / tiles;
+  nch = nch < 1 ? 1 : (nch > a.G.ez ? a.G.ez : nch);
+  const int tz = (a.G.ez + nch - 1) / nch;
+  nch = (a.G.ez + tz - 1) / tz;
+  k_potential_zm<Q, S><<<dim3((unsigned)(tiles * nch)), dim3(BX, sh.rows, 1), 0, a.stream>>>(L, tz);
+}
+
 // Coupling fields of the current state: solid fills of rho, phi, then
 // mu_rho, mu_phi, Pi, then the solid fill of Pi.
 template <int Q, int S>
@@ -596,7 +682,7 @@ static void couple_seq(const LaunchArgs &a, hipEvent_t *ev, int &k) {
   auto mark = [&]() { if (ev) (void)hipEventRecord(ev[k++], a.stream); };
   fill_launch<Q, S, 0>(a);
   mark();
-  cells_launch<Q, S, ST_POTENTIAL>(a, 0);
+  potential_launch<Q, S>(a);
   mark();
   fill_launch<Q, S, 1>(a);
   mark();
