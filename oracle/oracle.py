@@ -22,15 +22,21 @@ _SRC = os.path.join(_HERE, "frelbm_oracle.c")
 _LIB = os.path.join(_HERE, "libfrelbm_oracle.so")
 
 
+def compile_source(src: str, out: str) -> str:
+    """gcc build of an oracle source file (FP64, no FMA contraction, OpenMP)."""
+    tmp = out + ".tmp"
+    subprocess.check_call([
+        "gcc", "-O2", "-std=c99", "-fPIC", "-shared", "-fopenmp",
+        "-ffp-contract=off", "-fno-fast-math", "-Wall", "-Wextra",
+        "-Wno-unused-parameter", src, "-o", tmp, "-lm"])
+    os.replace(tmp, out)
+    return out
+
+
 def build(force: bool = False) -> str:
-    """Compile the oracle with gcc (FP64, no FMA contraction, OpenMP)."""
+    """Compile the oracle (when the library is missing or older than the source)."""
     if force or not os.path.exists(_LIB) or os.path.getmtime(_LIB) < os.path.getmtime(_SRC):
-        tmp = _LIB + ".tmp"
-        subprocess.check_call([
-            "gcc", "-O2", "-std=c99", "-fPIC", "-shared", "-fopenmp",
-            "-ffp-contract=off", "-fno-fast-math", "-Wall", "-Wextra",
-            "-Wno-unused-parameter", _SRC, "-o", tmp, "-lm"])
-        os.replace(tmp, _LIB)
+        compile_source(_SRC, _LIB)
     return _LIB
 
 
@@ -53,10 +59,12 @@ _lib = None
 
 
 def lib():
+    """The compiled oracle.  FRELBM_ORACLE_LIB names another build of the same
+    source to load instead (the mutation tests plant mistakes in copies)."""
     global _lib
     if _lib is None:
-        build()
-        L = C.CDLL(_LIB)
+        path = os.environ.get("FRELBM_ORACLE_LIB") or build()
+        L = C.CDLL(path)
         dp = C.POINTER(C.c_double)
         L.or_tables.argtypes = [C.c_int, C.POINTER(C.c_int), C.POINTER(C.c_int), dp]
         L.or_feq.argtypes = [C.c_int, C.c_double, dp, dp]
