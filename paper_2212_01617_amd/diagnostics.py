@@ -10,10 +10,15 @@ returned by ``Lattice.read``.
 
 Readings used where the paper leaves the measurement open:
   * Deformation: the second central moments of the phase indicator
-    C = clamp((1 + phi) / 2, 0, 1) about its centroid, restricted to the
-    shear plane; with eigenvalues l1 >= l2 of that 2x2 tensor,
-    D = (sqrt(l1) - sqrt(l2)) / (sqrt(l1) + sqrt(l2)) and theta is the angle
-    of the leading eigenvector to the flow axis.  Exact for ellipses and for
+    C = clamp((phi - phi_out) / (phi_in - phi_out), 0, 1) about its
+    centroid, restricted to the shear plane, where phi_in and phi_out are
+    the medians of phi over the cells with phi > 0 and phi <= 0 (+1 and -1
+    for ideal bulk phases: then C = (1 + phi) / 2).  Referencing the bulk
+    keeps a slightly supersaturated matrix (a drop giving up volume by
+    diffusion) from adding a box-shaped background to the moments.  With
+    eigenvalues l1 >= l2 of that 2x2 tensor, D = (sqrt(l1) - sqrt(l2)) /
+    (sqrt(l1) + sqrt(l2)) and theta is the angle of the leading eigenvector
+    to the flow axis.  Exact for ellipses and for
     ellipsoids with a principal axis normal to the plane.
   * Breakup: connected components of {phi > 0} with face connectivity,
     periodic axes wrapped; components smaller than ``min_cells`` are ignored.
@@ -32,8 +37,16 @@ AXES = {"x": 2, "y": 1, "z": 0}  # array axis of each spatial direction
 
 
 def indicator(phi: np.ndarray) -> np.ndarray:
-    """Phase indicator C = clamp((1 + phi)/2, 0, 1): 1 inside the droplet."""
-    return np.clip(0.5 * (1.0 + np.asarray(phi, dtype=np.float64)), 0.0, 1.0)
+    """Phase indicator, 1 in the droplet's bulk and 0 in the matrix's:
+    C = clamp((phi - phi_out) / (phi_in - phi_out), 0, 1) with phi_in,
+    phi_out the medians of phi over phi > 0 and phi <= 0."""
+    phi = np.asarray(phi, dtype=np.float64)
+    inside = phi > 0.0
+    if not inside.any() or inside.all():
+        return np.clip(0.5 * (1.0 + phi), 0.0, 1.0)
+    hi = float(np.median(phi[inside]))
+    lo = float(np.median(phi[~inside]))
+    return np.clip((phi - lo) / (hi - lo), 0.0, 1.0)
 
 
 def _periodic_centre(w: np.ndarray, axis: int) -> float:
@@ -163,7 +176,8 @@ def laplace_jump(P: np.ndarray, phi: np.ndarray, bulk: float = 0.9) -> float:
 
 
 def droplet_volume(phi: np.ndarray) -> dict:
-    """Droplet volume two ways: cells with phi > 0, and the indicator sum."""
+    """Droplet volume two ways: cells with phi > 0, and the sum of the
+    bulk-referenced indicator."""
     phi = np.asarray(phi)
     return {"cells_phi_pos": int((phi > 0).sum()), "indicator_sum": float(indicator(phi).sum())}
 

@@ -120,6 +120,21 @@ def test_laplace_jump_volume_and_drift():
     assert Dg.laplace_jump(P, phi) == pytest.approx(0.01, abs=1e-15)
     v = Dg.droplet_volume(phi)
     assert v["cells_phi_pos"] == 100 and v["indicator_sum"] == pytest.approx(105.0)
+
+
+def test_indicator_references_the_bulk_phases():
+    # a drop in a matrix that has taken up some of its volume (phi_out > -1)
+    # and with a drop phase below +1: same D and theta as the ideal field
+    ideal = _ellipse((1, 96, 192), (96.0, 48.0, 0.0), 20.0, 12.0, 0.6)
+    shifted = 0.5 * (ideal + 1.0) * (0.93 - (-0.95)) + (-0.95)
+    a = Dg.deformation(ideal, plane="xy")
+    b = Dg.deformation(shifted, plane="xy")
+    assert abs(a.D - b.D) < 1e-9 and abs(a.theta - b.theta) < 1e-9
+    assert abs(a.D - 8.0 / 32.0) < 3e-3
+    # the old (1 + phi)/2 indicator would see the matrix as 2.5% drop phase
+    naive = np.clip(0.5 * (1.0 + shifted), 0.0, 1.0)
+    cen, T = Dg.second_moments(naive)
+    assert T[0, 0] > 1.2 * Dg.second_moments(Dg.indicator(shifted))[1][0, 0]
     dr = Dg.mass_drift([100.0, 2.0, 50.0], [100.001, 2.0005, 50.0])
     assert dr["rho"] == pytest.approx(1e-5) and dr["phi"] == pytest.approx(1e-5)
 

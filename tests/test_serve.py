@@ -137,7 +137,7 @@ def test_scheduler_admits_in_order_within_budget_and_retires_everyone():
             assert o.strain >= 2.0
     s = rep.summary()
     assert s["requests"] == len(rs)
-    assert s["steady"] + s["breakup"] + s["capped"] == len(rs)
+    assert s["steady"] + s["breakup"] + s["capped"] == len(rs) and s["dissolved"] == 0
     assert s["p50_time_to_steady_s"] <= s["p99_time_to_steady_s"]
     assert s["aggregate_mlups"] > 0
 
@@ -159,6 +159,24 @@ def test_request_larger_than_budget_is_rejected_up_front():
     eng = FakeEngine(clock, 10)
     with pytest.raises(ValueError):
         serve.Server(eng, 10, max_members=2, clock=clock, sleep=clock.sleep).run(rs)
+
+
+def test_dissolved_drop_retires():
+    clock = Clock()
+    rs = _requests(4, seed=9)
+
+    class Dissolving(FakeEngine):
+        def phi(self, h):
+            req, t, rate = self.members[h]
+            if req.rid == 1 and t * rate > 1.0:
+                return -0.97 * np.ones((1, 48, 48))   # no phi > 0 left
+            return super().phi(h)
+
+    budget = 4 * max(r.cells for r in rs) * 160
+    eng = Dissolving(clock, budget)
+    rep = serve.Server(eng, budget, max_members=4, chunk=500, clock=clock, sleep=clock.sleep).run(rs)
+    by = {o.rid: o for o in rep.outcomes}
+    assert by[1].reason == "dissolved" and rep.summary()["dissolved"] == 1
 
 
 def test_invalid_requests_are_reported_not_run():
