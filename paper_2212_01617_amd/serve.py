@@ -34,6 +34,10 @@ class InvalidRequest(ValueError):
     """The library refuses the request's parameters."""
 
 
+class RunFailed(RuntimeError):
+    """A served lattice went non-finite (it is retired as failed)."""
+
+
 @dataclass
 class Request:
     rid: int
@@ -90,7 +94,7 @@ def make_requests(n: int = 256, rate: float = 20.0, seed: int = 0,
 @dataclass
 class Outcome:
     rid: int
-    reason: str           # "steady", "breakup", "dissolved", "cap" or "invalid" (refused parameters)
+    reason: str           # "steady", "breakup", "dissolved", "cap", "failed" (non-finite) or "invalid"
     arrival: float
     admitted: float
     retired: float
@@ -122,6 +126,7 @@ class Report:
             "breakup": sum(o.reason == "breakup" for o in self.outcomes),
             "capped": sum(o.reason == "cap" for o in self.outcomes),
             "dissolved": sum(o.reason == "dissolved" for o in self.outcomes),
+            "failed": sum(o.reason == "failed" for o in self.outcomes),
             "invalid": sum(o.reason == "invalid" for o in self.outcomes),
             "p50_time_to_steady_s": float(np.percentile(tts, 50)) if st else None,
             "p99_time_to_steady_s": float(np.percentile(tts, 99)) if st else None,
@@ -153,8 +158,8 @@ class Server:
     engine.footprint(req) -> bytes (raises InvalidRequest for parameters the
     library refuses, e.g. a wall speed beyond the Mach guard);
     engine.admit(req) -> (handle, strain per step) or None when the engine
-    cannot take it now; engine.step(n); engine.phi(handle) -> phi field;
-    engine.periodic(req) -> periodic flags (x, y, z); engine.retire(handle)."""
+    cannot take it now; engine.step(n); engine.phi(handle) -> phi field
+    (raises RunFailed for a lattice gone non-finite); engine.periodic(req) -> periodic flags (x, y, z); engine.retire(handle)."""
 
     def __init__(self, engine, budget_bytes: int, max_members: int, chunk: int = 200,
                  strain_cap: float = 25.0, step_cap: int = 200_000, clock=time.monotonic,
@@ -170,7 +175,10 @@ class Server:
 
     def _sample(self, m: _Member, now: float):
         """Sample D (and breakup); return the retirement reason or None."""
-        phi = self.engine.phi(m.handle)
+        try:
+            phi = self.engine.phi(m.handle)
+        except RunFailed:
+            return "failed"
         req = m.req
         per = self.engine.periodic(req)
         comps = Dg.components(phi, per)
@@ -345,6 +353,12 @@ class GpuEngine:
         self.batch.step(n)
 
     def phi(self, L):
+        try:
+            L.reduce()          # FP64 totals and the non-finite check
+        except self.F.FreError as e:
+            if e.status == self.F.FRE_ENUMERIC:
+                raise RunFailed(str(e)) from e
+            raise
         return L.read(("phi",))["phi"]
 
     def retire(self, L):

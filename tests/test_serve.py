@@ -179,6 +179,24 @@ def test_dissolved_drop_retires():
     assert by[1].reason == "dissolved" and rep.summary()["dissolved"] == 1
 
 
+def test_failed_run_retires():
+    clock = Clock()
+    rs = _requests(4, seed=9)
+
+    class Failing(FakeEngine):
+        def phi(self, h):
+            req, t, rate = self.members[h]
+            if req.rid == 2 and t * rate > 0.5:
+                raise serve.RunFailed("non-finite")
+            return super().phi(h)
+
+    budget = 4 * max(r.cells for r in rs) * 160
+    eng = Failing(clock, budget)
+    rep = serve.Server(eng, budget, max_members=4, chunk=500, clock=clock, sleep=clock.sleep).run(rs)
+    by = {o.rid: o for o in rep.outcomes}
+    assert by[2].reason == "failed" and rep.summary()["failed"] == 1 and len(by) == 4
+
+
 def test_invalid_requests_are_reported_not_run():
     clock = Clock()
     rs = _requests(6)
