@@ -169,20 +169,26 @@ fre_status fre_load(fre_lattice *L, const void *host, size_t bytes);
 
 /* Measurement: advance n >= 1 steps launching each kernel of the step
  * separately with HIP events around it on the bound stream (no graph), and
- * write the mean duration in ms of each kernel per step into kernel_ms
- * (max_kernels entries); *n_kernels receives the number of kernels per step.
- * fre_kernel_name(k) names kernel k (NULL beyond the last).  Syncs. */
+ * write the mean duration in ms per step of each kernel into kernel_ms
+ * (max_kernels >= 6 entries), indexed by kernel slot: 0 k_moments,
+ * 1 k_fill_m, 2 k_potential, 3 k_fill_c, 4 k_collide, 5 k_combine.  A step
+ * launches five of them (FP32 storage: slots 1-5, the moments at t+1 being a
+ * by-product of k_collide completed by k_combine; FP16: slots 0-4); the slot
+ * a lattice does not launch reads -1.  *n_kernels receives 6.
+ * fre_kernel_name(k) names slot k (NULL beyond the last).  Syncs. */
 fre_status fre_profile_step(fre_lattice *L, int64_t n, double *kernel_ms,
                             int32_t max_kernels, int32_t *n_kernels);
 const char *fre_kernel_name(int32_t k);
 
-/* Launch shapes of the three cell kernels of the step (k_moments,
- * k_potential, k_collide), cfg = {rows, xcd} per kernel in that order:
- * rows of 64 cells per thread block (1, 2, 4 or 8) and xcd = 1 for the
- * XCD-aware block order (0: plain order).  A shape decides only which
- * thread updates which cell, never the arithmetic: results are bitwise the
- * same under every shape.  Default {4, 1} for all three.  Set syncs the
- * bound stream; FRE_EINVAL for other values. */
+/* Launch shapes of the three cell kernels of the step, cfg = {rows, xcd}
+ * for the moments pass (k_moments, or k_combine with FP32 storage),
+ * k_potential and k_collide in that order: rows of 64 cells per thread block
+ * (1, 2, 4 or 8; with FP32 storage k_collide always 4, its tile being the
+ * footprint of its on-chip moment sums) and xcd = 1 for the XCD-aware block
+ * order (0: plain order).  A shape decides only which thread updates which
+ * cell, never the arithmetic: results are bitwise the same under every
+ * shape.  Default {4, 1} for all three.  Set syncs the bound stream;
+ * FRE_EINVAL for other values. */
 fre_status fre_set_launch_shape(fre_lattice *L, const int32_t cfg[6]);
 fre_status fre_get_launch_shape(const fre_lattice *L, int32_t cfg[6]);
 
@@ -214,9 +220,8 @@ void fre_lattice_destroy(fre_lattice *L);
  * fre_lattice_batch_needs).  No device work. */
 fre_status fre_batch_footprint(int32_t max_slots, int64_t max_work, int64_t max_fill, size_t *bytes);
 
-/* Work items a lattice adds to a batch (cell blocks, solid-boundary cells),
- * counted at the smallest tile (one row of 64 cells), so that capacities
- * summed from these numbers hold the members at every launch shape. */
+/* Work items a lattice adds to a batch: cell tiles of 64 x 4 cells and
+ * solid-boundary cells. */
 fre_status fre_lattice_batch_needs(const fre_lattice *L, int64_t *n_work, int64_t *n_fill);
 
 /* Create a batch in the caller's device buffer (>= fre_batch_footprint,
@@ -239,21 +244,20 @@ fre_status fre_batch_remove(fre_batch *B, int32_t slot);
  * FRE_ESTATE if a member has failed. */
 fre_status fre_batch_step(fre_batch *B, int64_t n);
 
-/* Batch launch shape: rows of 64 cells per work item and block (1, 2, 4 or
- * 8) and the persistent grid of the cell kernels in blocks per compute unit
- * (1..32).  Default 4 rows, 8 blocks per CU.  Rebuilds the work lists
- * (FRE_ENOMEM, shape unchanged, when they exceed the capacity).  Results are
- * bitwise the same under every shape. */
-fre_status fre_batch_set_launch_shape(fre_batch *B, int32_t rows, int32_t blocks_per_cu);
-fre_status fre_batch_get_launch_shape(const fre_batch *B, int32_t out[2]);
+/* Batch launch shape: the persistent grid of the cell kernels in blocks per
+ * compute unit (1..32; default 8).  Work items are tiles of 64 x 4 cells.
+ * Results are bitwise the same under every shape.  Syncs the batch's
+ * stream. */
+fre_status fre_batch_set_launch_shape(fre_batch *B, int32_t blocks_per_cu);
+fre_status fre_batch_get_launch_shape(const fre_batch *B, int32_t *blocks_per_cu);
 
 /* Batch autotuner: times the batch step over n (rounded up to even,
- * 2..10000) directly launched steps for rows 1, 2, 4, 8 x blocks per CU
- * 2, 4, 8, 16 and keeps the fastest.  Every member's state is copied to host
- * memory before and restored after.  out (may be NULL) receives {rows,
- * blocks per CU}, ms_per_step (may be NULL) the best mean step time.  Syncs.
- * FRE_ESTATE for an empty batch or a failed member. */
-fre_status fre_batch_autotune(fre_batch *B, int64_t n, int32_t out[2], double *ms_per_step);
+ * 2..10000) directly launched steps for 2, 4, 8 and 16 blocks per CU and
+ * keeps the fastest.  Every member's state is copied to host memory before
+ * and restored after.  blocks_per_cu and ms_per_step (may be NULL) receive
+ * the choice and its mean step time.  Syncs.  FRE_ESTATE for an empty batch
+ * or a failed member. */
+fre_status fre_batch_autotune(fre_batch *B, int64_t n, int32_t *blocks_per_cu, double *ms_per_step);
 
 /* Number of members and the common AA parity. */
 fre_status fre_batch_info(const fre_batch *B, int32_t *members, int32_t *parity);

@@ -54,7 +54,7 @@ struct Plan {
   int off[3];
   int px;          // row pitch: ext[0] rounded up to a multiple of 64
   long long ncell;  // px * ext[1] * ext[2]
-  size_t o_f, o_g, o_g0, o_mask, o_nbm, o_M, o_C, o_MUP, o_AUX, o_fill, o_part, total;
+  size_t o_f, o_g, o_g0, o_mask, o_nbm, o_M, o_C, o_MUP, o_P0, o_PU, o_PD, o_AUX, o_fill, o_part, total;
 };
 
 fre_status validate(const fre_params *p) {
@@ -128,6 +128,11 @@ Plan make_plan(const fre_params *p) {
   P.o_M = take((size_t)P.ncell * 8);
   P.o_C = take((size_t)P.ncell * 16);
   P.o_MUP = take((size_t)P.ncell * 4);
+  // FP32: first-pass moment sums of the collide (same plane; below and above in 3D)
+  const bool bp = p->storage == FRE_FP32;
+  P.o_P0 = bp ? take((size_t)P.ncell * 8) : 0;
+  P.o_PU = bp && P.q == 19 ? take((size_t)P.ncell * 8) : 0;
+  P.o_PD = bp && P.q == 19 ? take((size_t)P.ncell * 8) : 0;
   P.o_AUX = take((size_t)P.ncell * 16);
   P.o_fill = take((size_t)P.ncell * 4);
   P.o_part = take((size_t)reduce_blocks() * 8 * sizeof(double));
@@ -295,6 +300,9 @@ void bind_args(fre_lattice *L) {
   a.M = (float2 *)(L->base + P.o_M);
   a.C = (float4 *)(L->base + P.o_C);
   a.MUP = (float *)(L->base + P.o_MUP);
+  a.P0 = P.o_P0 ? (float2 *)(L->base + P.o_P0) : nullptr;
+  a.PU = P.o_PU ? (float2 *)(L->base + P.o_PU) : nullptr;
+  a.PD = P.o_PD ? (float2 *)(L->base + P.o_PD) : nullptr;
   a.AUX = (float4 *)(L->base + P.o_AUX);
   a.fill_list = (int *)(L->base + P.o_fill);
   a.n_fill = (int)L->fill_host.size();
@@ -608,8 +616,10 @@ fre_status fre_load(fre_lattice *L, const void *host, size_t bytes) {
   fre_status s = fre_set_params(L, &h.params);
   if (s != FRE_OK) return s;
   HIP_TRY(hipMemcpyAsync(L->base + L->plan.o_f, (const uint8_t *)host + sizeof h, h.pops_bytes, hipMemcpyHostToDevice, L->a.stream));
-  HIP_TRY(hipStreamSynchronize(L->a.stream));
   L->t = h.step;
+  launch_moments(L->a, (int)(L->t & 1));  // M of the restored populations
+  HIP_TRY(hipGetLastError());
+  HIP_TRY(hipStreamSynchronize(L->a.stream));
   L->state = 0;
   return FRE_OK;
 }
@@ -622,9 +632,12 @@ namespace {
 // steps, from HIP events recorded on the lattice's stream around every launch.
 fre_status time_kernels(fre_lattice *L, int64_t n, double *kernel_ms) {
   const int K = step_kernel_count();
+  int slot[8];
+  const int nslot = step_kernel_slots(L->a, slot);
   std::vector<hipEvent_t> ev((size_t)(K + 1) * n);
   for (auto &e : ev) HIP_TRY(hipEventCreate(&e));
-  for (int k = 0; k < K; ++k) kernel_ms[k] = 0.0;
+  for (int k = 0; k < nslot; ++k) kernel_ms[k] = -1.0;  // slots this class does not launch
+  for (int k = 0; k < K; ++k) kernel_ms[slot[k]] = 0.0;
   fre_status st = FRE_OK;
   for (int64_t s = 0; s < n; ++s) {
     launch_step_events(L->a, (int)(L->t & 1), &ev[(size_t)s * (K + 1)]);
@@ -641,7 +654,7 @@ fre_status time_kernels(fre_lattice *L, int64_t n, double *kernel_ms) {
       for (int k = 0; k < K; ++k) {
         float ms = 0.0f;
         (void)hipEventElapsedTime(&ms, ev[(size_t)s * (K + 1) + k], ev[(size_t)s * (K + 1) + k + 1]);
-        kernel_ms[k] += ms / (double)n;
+        kernel_ms[slot[k]] += ms / (double)n;
       }
   for (auto &e : ev) (void)hipEventDestroy(e);
   return st;
@@ -664,13 +677,19 @@ fre_status snapshot(fre_lattice *L, HostState &h) {
 
 fre_status restore(fre_lattice *L, const HostState &h) {
   HIP_TRY(hipMemcpyAsync(L->base + L->plan.o_f, h.pops.data(), h.pops.size(), hipMemcpyHostToDevice, L->a.stream));
-  HIP_TRY(hipStreamSynchronize(L->a.stream));
   L->t = h.t;
+  launch_moments(L->a, (int)(L->t & 1));  // M of the restored populations
+  HIP_TRY(hipGetLastError());
+  HIP_TRY(hipStreamSynchronize(L->a.stream));
   return FRE_OK;
 }
 
-// Stage kernels whose launch shape is tuned, as indices into the kernel list.
-const int kStageKernel[N_SHAPES] = {0, 2, 4};  // k_moments, k_potential, k_collide
+// Kernel slot timed for each launch shape: the moments pass (k_moments, or
+// k_combine with the by-product), k_potential, k_collide.
+int stage_slot(const fre_lattice *L, int shape) {
+  if (shape == SHAPE_MOMENTS) return uses_by_product(L->a) ? 5 : 0;
+  return shape == SHAPE_POTENTIAL ? 2 : 4;
+}
 const Shape kCandidates[] = {{1, 0}, {2, 0}, {4, 0}, {8, 0}, {1, 1}, {2, 1}, {4, 1}, {8, 1}};
 
 }  // namespace
@@ -682,7 +701,8 @@ fre_status fre_profile_step(fre_lattice *L, int64_t n, double *kernel_ms, int32_
   if (!L || !kernel_ms || !n_kernels) return fail(FRE_EINVAL, "NULL argument");
   if (n < 1) return fail(FRE_EINVAL, "n must be >= 1");
   if (L->state) return fail(FRE_ESTATE, "lattice is in the failed state");
-  const int K = step_kernel_count();
+  int slot[8];
+  const int K = step_kernel_slots(L->a, slot);
   if (max_kernels < K) return fail(FRE_EINVAL, "kernel_ms needs %d entries", K);
   if (L->batch) return fail(FRE_ESTATE, "lattice is a batch member: profile it alone");
   fre_status st = time_kernels(L, n, kernel_ms);
@@ -696,6 +716,8 @@ fre_status fre_set_launch_shape(fre_lattice *L, const int32_t cfg[6]) {
   for (int k = 0; k < N_SHAPES; ++k) {
     sh[k] = Shape{cfg[2 * k], cfg[2 * k + 1]};
     if (!shape_ok(sh[k])) return fail(FRE_EINVAL, "bad launch shape (%d rows, xcd %d)", sh[k].rows, sh[k].xcd);
+    if (k == SHAPE_COLLIDE && uses_by_product(L->a) && sh[k].rows != COLLIDE_ROWS)
+      return fail(FRE_EINVAL, "with FP32 storage the collide tile has %d rows", COLLIDE_ROWS);
   }
   if (fre_status bs = sync_batch(L)) return bs;
   HIP_TRY(hipStreamSynchronize(L->a.stream));
@@ -731,8 +753,12 @@ fre_status fre_autotune(fre_lattice *L, int64_t n, int32_t cfg_out[6], double st
     s = time_kernels(L, 2, ms);  // warm-up
     if (s == FRE_OK) s = time_kernels(L, n, ms);
     if (s != FRE_OK) break;
-    for (int k = 0; k < N_SHAPES; ++k)
-      if (ms[kStageKernel[k]] < best[k]) { best[k] = ms[kStageKernel[k]]; pick[k] = c; }
+    for (int k = 0; k < N_SHAPES; ++k) {
+      // the by-product collide runs COLLIDE_ROWS rows whatever the shape says
+      if (k == SHAPE_COLLIDE && uses_by_product(L->a) && c.rows != COLLIDE_ROWS) continue;
+      const double t = ms[stage_slot(L, k)];
+      if (t < best[k]) { best[k] = t; pick[k] = c; }
+    }
   }
   fre_status r = restore(L, h);
   for (int k = 0; k < N_SHAPES; ++k) L->a.shape[k] = s == FRE_OK ? pick[k] : saved[k];
@@ -783,10 +809,9 @@ int64_t work_items(const Geom &G, int rows) {
   return (int64_t)((G.ex + 63) / 64) * ((G.ey + rows - 1) / rows) * G.ez;
 }
 
-// Work items at the smallest tile (one row), so a batch sized from these
-// numbers holds its members at every launch shape.
+// Work items are tiles of 64 x COLLIDE_ROWS cells.
 void lattice_needs(const fre_lattice *L, int64_t *n_work, int64_t *n_fill) {
-  *n_work = work_items(L->a.G, 1);
+  *n_work = work_items(L->a.G, COLLIDE_ROWS);
   *n_fill = (int64_t)L->fill_host.size();
 }
 
@@ -804,6 +829,9 @@ Inst inst_of(const fre_lattice *L, const void *base) {
   I.M = rel(L->a.M, base);
   I.C = rel(L->a.C, base);
   I.MUP = rel(L->a.MUP, base);
+  I.P0 = L->a.P0 ? rel(L->a.P0, base) : 0;
+  I.PU = L->a.PU ? rel(L->a.PU, base) : 0;
+  I.PD = L->a.PD ? rel(L->a.PD, base) : 0;
   I.fill = rel(L->a.fill_list, base);
   I.n_fill = L->a.n_fill;
   return I;
@@ -922,7 +950,7 @@ fre_status fre_batch_create(void *device_buf, size_t bytes, void *hip_stream, in
     if (hipDeviceGetAttribute(&v, hipDeviceAttributeMultiprocessorCount, dev) == hipSuccess && v > 0) ncu = v;
   }
   B->ncu = ncu;
-  B->rows = 4;
+  B->rows = COLLIDE_ROWS;
   B->blocks_per_cu = 8;
   B->grid_cells = ncu * B->blocks_per_cu;
   B->grid_fill = ncu * 2;
@@ -1018,34 +1046,24 @@ fre_status fre_batch_step(fre_batch *B, int64_t n) {
   return s;
 }
 
-fre_status fre_batch_set_launch_shape(fre_batch *B, int32_t rows, int32_t blocks_per_cu) {
+fre_status fre_batch_set_launch_shape(fre_batch *B, int32_t blocks_per_cu) {
   if (!B) return fail(FRE_EINVAL, "batch is NULL");
-  if (!shape_ok(Shape{rows, 0}) || blocks_per_cu < 1 || blocks_per_cu > 32)
-    return fail(FRE_EINVAL, "bad batch launch shape (%d rows, %d blocks per CU)", rows, blocks_per_cu);
+  if (blocks_per_cu < 1 || blocks_per_cu > 32)
+    return fail(FRE_EINVAL, "bad batch launch shape (%d blocks per CU)", blocks_per_cu);
   HIP_TRY(hipStreamSynchronize(B->stream));
-  const int old_rows = B->rows, old_bpc = B->blocks_per_cu;
-  B->rows = rows;
   B->blocks_per_cu = blocks_per_cu;
   B->grid_cells = B->ncu * blocks_per_cu;
   batch_reset_graph(B);
-  fre_status s = batch_rebuild(B);
-  if (s != FRE_OK) {
-    B->rows = old_rows;
-    B->blocks_per_cu = old_bpc;
-    B->grid_cells = B->ncu * old_bpc;
-    (void)batch_rebuild(B);
-  }
-  return s;
-}
-
-fre_status fre_batch_get_launch_shape(const fre_batch *B, int32_t out[2]) {
-  if (!B || !out) return fail(FRE_EINVAL, "NULL argument");
-  out[0] = B->rows;
-  out[1] = B->blocks_per_cu;
   return FRE_OK;
 }
 
-fre_status fre_batch_autotune(fre_batch *B, int64_t n, int32_t out[2], double *ms_per_step) {
+fre_status fre_batch_get_launch_shape(const fre_batch *B, int32_t *blocks_per_cu) {
+  if (!B || !blocks_per_cu) return fail(FRE_EINVAL, "NULL argument");
+  *blocks_per_cu = B->blocks_per_cu;
+  return FRE_OK;
+}
+
+fre_status fre_batch_autotune(fre_batch *B, int64_t n, int32_t *blocks_per_cu, double *ms_per_step) {
   if (!B) return fail(FRE_EINVAL, "batch is NULL");
   if (n < 2 || n > 10000) return fail(FRE_EINVAL, "n must be in [2, 10000]");
   if (!B->classes) return fail(FRE_ESTATE, "batch has no members to tune on");
@@ -1059,30 +1077,28 @@ fre_status fre_batch_autotune(fre_batch *B, int64_t n, int32_t out[2], double *m
       fre_status s = snapshot(B->slot[k], hs[k]);
       if (s != FRE_OK) return s;
     }
-  const int parity0 = B->parity, rows0 = B->rows, bpc0 = B->blocks_per_cu;
-  static const int kRows[] = {1, 2, 4, 8};
+  const int parity0 = B->parity, bpc0 = B->blocks_per_cu;
   static const int kBpc[] = {2, 4, 8, 16};
   double best = 1e300;
-  int best_rows = rows0, best_bpc = bpc0;
+  int best_bpc = bpc0;
   hipEvent_t e0, e1;
   HIP_TRY(hipEventCreate(&e0));
   HIP_TRY(hipEventCreate(&e1));
   fre_status s = FRE_OK;
-  for (int rows : kRows)
-    for (int bpc : kBpc) {
-      if (fre_batch_set_launch_shape(B, rows, bpc) != FRE_OK) continue;  // lists do not fit
-      int par = B->parity;
-      for (int w = 0; w < 2; ++w, par ^= 1) batch_launch_step(B, par);
-      (void)hipEventRecord(e0, B->stream);
-      for (int64_t k = 0; k < n; ++k, par ^= 1) batch_launch_step(B, par);
-      (void)hipEventRecord(e1, B->stream);
-      hipError_t e = hipStreamSynchronize(B->stream);
-      if (e == hipSuccess) e = hipGetLastError();
-      if (e != hipSuccess) { s = fail(FRE_EDEVICE, "batch tuning step failed: %s", hipGetErrorString(e)); break; }
-      float ms = 0.0f;
-      (void)hipEventElapsedTime(&ms, e0, e1);
-      if (ms / n < best) { best = ms / n; best_rows = rows; best_bpc = bpc; }
-    }
+  for (int bpc : kBpc) {
+    if ((s = fre_batch_set_launch_shape(B, bpc)) != FRE_OK) break;
+    int par = B->parity;
+    for (int w = 0; w < 2; ++w, par ^= 1) batch_launch_step(B, par);
+    (void)hipEventRecord(e0, B->stream);
+    for (int64_t k = 0; k < n; ++k, par ^= 1) batch_launch_step(B, par);
+    (void)hipEventRecord(e1, B->stream);
+    hipError_t e = hipStreamSynchronize(B->stream);
+    if (e == hipSuccess) e = hipGetLastError();
+    if (e != hipSuccess) { s = fail(FRE_EDEVICE, "batch tuning step failed: %s", hipGetErrorString(e)); break; }
+    float ms = 0.0f;
+    (void)hipEventElapsedTime(&ms, e0, e1);
+    if (ms / n < best) { best = ms / n; best_bpc = bpc; }
+  }
   (void)hipEventDestroy(e0);
   (void)hipEventDestroy(e1);
   for (size_t k = 0; k < B->slot.size(); ++k)
@@ -1091,10 +1107,10 @@ fre_status fre_batch_autotune(fre_batch *B, int64_t n, int32_t out[2], double *m
       if (r != FRE_OK && s == FRE_OK) s = r;
     }
   B->parity = parity0;
-  fre_status r = fre_batch_set_launch_shape(B, s == FRE_OK ? best_rows : rows0, s == FRE_OK ? best_bpc : bpc0);
+  fre_status r = fre_batch_set_launch_shape(B, s == FRE_OK ? best_bpc : bpc0);
   if (s != FRE_OK) return s;
   if (r != FRE_OK) return r;
-  if (out) { out[0] = B->rows; out[1] = B->blocks_per_cu; }
+  if (blocks_per_cu) *blocks_per_cu = B->blocks_per_cu;
   if (ms_per_step) *ms_per_step = best;
   return FRE_OK;
 }

@@ -17,6 +17,10 @@ struct Shape {
 };
 enum { SHAPE_MOMENTS = 0, SHAPE_POTENTIAL = 1, SHAPE_COLLIDE = 2, N_SHAPES = 3 };
 constexpr int MAX_ROWS = 8;
+// Rows of the collide tiles (64 x COLLIDE_ROWS cells) with FP32 storage: the
+// tile is also the footprint over which collide sums next-step moments on
+// chip, so it is fixed (another footprint would group the sums differently).
+constexpr int COLLIDE_ROWS = 4;
 inline bool shape_ok(const Shape &s) {
   return (s.rows == 1 || s.rows == 2 || s.rows == 4 || s.rows == 8) && (s.xcd == 0 || s.xcd == 1);
 }
@@ -35,6 +39,7 @@ struct LaunchArgs {
   float2 *M;    // (rho - 1, phi)
   float4 *C;    // (rho - 1, phi, Pi = rho mu_rho + phi mu_phi, mu_rho)
   float *MUP;   // mu_phi
+  float2 *P0, *PU, *PD;  // FP32: first-pass moment sums by source plane (same, below, above)
   float4 *AUX;  // u0 at init; (ux, uy, uz, P) after observe
   int *fill_list;
   int n_fill;
@@ -57,6 +62,7 @@ template <int Q, int S> struct LatView {
   float2 *M;
   float4 *C;
   float *MUP;
+  float2 *P0, *PU, *PD;
   Geom G;
   Phys ph;
   const int *fill;
@@ -70,7 +76,7 @@ template <int Q, int S> struct LatView {
 struct Inst {
   Geom G;
   Phys ph;
-  long long f, g, g0, mask, nbm, M, C, MUP, fill;
+  long long f, g, g0, mask, nbm, M, C, MUP, P0, PU, PD, fill;
   int n_fill;
 };
 
@@ -99,9 +105,16 @@ inline int batch_class(int q, int storage) { return (q == 19 ? 2 : 0) + storage;
 
 void launch_batch_step(const BatchArgs &b, int cls, int odd);
 void launch_step(const LaunchArgs &a, int odd);
+// A step launches 5 kernels; ev receives an event before the first and after
+// each.  The kernels are named by slot: step_kernel_name(0..5) = k_moments,
+// k_fill_m, k_potential, k_fill_c, k_collide, k_combine; step_kernel_slots
+// gives, for the lattice's class, the slot of each of its 5 launches.
 void launch_step_events(const LaunchArgs &a, int odd, hipEvent_t *ev);
 int step_kernel_count();
+int step_kernel_slots(const LaunchArgs &a, int *slot);
 const char *step_kernel_name(int k);
+void launch_moments(const LaunchArgs &a, int odd);
+bool uses_by_product(const LaunchArgs &a);
 void launch_observe(const LaunchArgs &a, int odd);
 void launch_init(const LaunchArgs &a);
 void launch_read_pops(const LaunchArgs &a, int odd, float *out);

@@ -9,6 +9,10 @@
 //   k_collide   force (eq. F), velocity (eq. veloMoment), BGK collision of f
 //               with Guo forcing (eqs. bgk, feq, Fi) and of g (eqs. LBEg,
 //               geq), streaming with moving bounce-back, in place.
+// With FP32 storage the moments at t+1 are instead a by-product of k_collide
+// (partial sums on chip) completed by k_combine, so a step is k_fill_m,
+// k_potential, k_fill_c, k_collide, k_combine and k_moments runs only after
+// the populations are set from outside (initialisation, restores).
 //
 // Streaming is in place with the AA access pattern: at even time steps a
 // cell reads and writes only its own slots (writing direction i into slot
@@ -112,20 +116,141 @@ __device__ __forceinline__ void load_pops(const Pops<Q, S> &P, const Nbr &N, lon
 // call these, so a lattice advanced alone or inside a batch takes exactly
 // the same arithmetic.
 // ---------------------------------------------------------------------------
+// ---------------------------------------------------------------------------
+// Moments at t+1 as a by-product of collide (FP32 storage).
+//
+// rho(y, t+1) = sum_i f_i(y, t+1), where f_i(y, t+1) is f*_i(y - c_i) for a
+// fluid source y - c_i and cell y's own bounce-back value otherwise (phi
+// likewise with g).  The sum is split by the plane of the source: group UP
+// (c_z = +1, sources one plane below), S0 (c_z = 0) and DN (c_z = -1),
+// combined as (UP + S0) + DN, each group summed in ascending direction order
+// in two passes: first the "available" sources -- fluid and inside the
+// destination's tile footprint, the 64 x COLLIDE_ROWS columns of the collide
+// tile grid that contains it -- then the others.  k_collide forms the first
+// pass on chip from the post-collision values of its tile and stores it per
+// group; k_combine adds the second pass from the population arrays (tile-edge
+// sources and bounce-backs) and stores M; k_moments performs both passes from
+// the population arrays.  The additions are the same in every case, so M does
+// not depend on which path computed it.  FP16 storage keeps the plain moment
+// pass, which reads half the bytes and costs less than the partial planes.
+// ---------------------------------------------------------------------------
+template <int S> struct ByProduct { static constexpr bool on = S == 0; };
+
+__device__ __forceinline__ bool in_footprint(const Geom &G, int x, int y, int cx, int cy) {
+  const int sx = x - cx, sy = y - cy;
+  const int xlo = x & ~(BX - 1), ylo = (y / COLLIDE_ROWS) * COLLIDE_ROWS;
+  return sx >= xlo && sx < min(xlo + BX, G.ex) && sy >= ylo && sy < min(ylo + COLLIDE_ROWS, G.ey);
+}
+
+// Population i of fluid cell c at parity `odd` (AA pattern), as load_pops.
+template <int Q, int S>
+__device__ __forceinline__ void pop_at(const Pops<Q, S> &P, const Nbr &N, long long c, int odd, int i,
+                                       float &f, float &g) {
+  using V = VSet<Q>;
+  if (!odd || i == 0) {
+    f = P.ldf(i, c);
+    g = P.ldg(i, c);
+  } else {
+    const long long s = N.template back<V>(i);
+    f = P.ldf(opp(i), s);
+    g = P.ldg(opp(i), s);
+  }
+}
+
+// Whether source y - c_i of fluid cell (x, y) (neighbour word `bits`) is
+// summed in the first pass.
+template <class V>
+__device__ __forceinline__ bool available(const Geom &G, int x, int y, uint32_t bits, int i) {
+  if (i == 0) return true;
+  return in_footprint(G, x, y, V::cx(i), V::cy(i)) && !((bits >> opp(i)) & 1u);
+}
+
+template <int Q>
+__device__ __forceinline__ float2 group_total(float2 up, float2 s0, float2 dn) {
+  if (VSet<Q>::D == 2) return s0;
+  return make_float2((up.x + s0.x) + dn.x, (up.y + s0.y) + dn.y);
+}
+
+// Second pass for fluid cell c: adds the unavailable sources of each group,
+// in ascending direction order, to the first-pass sums grp[cz + 1].  All
+// needed loads are issued before the sums.
+template <int Q, int S>
+__device__ __forceinline__ void second_pass(const LatView<Q, S> &L, const Nbr &N, long long c, int odd, int x,
+                                            int y, uint32_t bits, float2 grp[3]) {
+  using V = VSet<Q>;
+  float vf[Q], vg[Q];
+#pragma unroll
+  for (int i = 0; i < Q; ++i) {
+    vf[i] = vg[i] = 0.0f;
+    if (!available<V>(L.G, x, y, bits, i)) pop_at<Q, S>(L.P, N, c, odd, i, vf[i], vg[i]);
+  }
+#pragma unroll
+  for (int k = 0; k < 3; ++k)
+#pragma unroll
+    for (int i = 0; i < Q; ++i) {
+      if (V::cz(i) != k - 1 || available<V>(L.G, x, y, bits, i)) continue;
+      grp[k].x += vf[i];
+      grp[k].y += vg[i];
+    }
+}
+
+// M from the populations alone (state parity ODD).
 template <int Q, int S, int ODD>
 __device__ __forceinline__ void stage_moments(const LatView<Q, S> &L, int x, int y, int z) {
+  using V = VSet<Q>;
   const long long c = (long long)x + (long long)L.G.px * ((long long)y + (long long)L.G.ey * z);
-  if (L.nbm[c] & NB_SELF_SOLID) return;
+  const uint32_t bits = L.nbm[c];
+  if (bits & NB_SELF_SOLID) return;
   const Nbr N(L.G, x, y, z);
   float df[Q], g[Q];
   load_pops<Q, S>(L.P, N, c, ODD, df, g);
-  float drho = 0.0f, phi = 0.0f;
+  if (!ByProduct<S>::on) {
+    float drho = 0.0f, phi = 0.0f;
+#pragma unroll
+    for (int i = 0; i < Q; ++i) {
+      drho += df[i];
+      phi += g[i];
+    }
+    L.M[c] = make_float2(drho, phi);
+    return;
+  }
+  float2 grp[3];
+#pragma unroll
+  for (int k = 0; k < 3; ++k) grp[k] = make_float2(0.0f, 0.0f);
 #pragma unroll
   for (int i = 0; i < Q; ++i) {
-    drho += df[i];
-    phi += g[i];
+    if (!available<V>(L.G, x, y, bits, i)) continue;
+    grp[V::cz(i) + 1].x += df[i];
+    grp[V::cz(i) + 1].y += g[i];
   }
-  L.M[c] = make_float2(drho, phi);
+#pragma unroll
+  for (int k = 0; k < 3; ++k)
+#pragma unroll
+    for (int i = 0; i < Q; ++i) {
+      if (V::cz(i) != k - 1 || available<V>(L.G, x, y, bits, i)) continue;
+      grp[k].x += df[i];
+      grp[k].y += g[i];
+    }
+  L.M[c] = group_total<Q>(grp[2], grp[1], grp[0]);
+}
+
+// Second pass after collide; the state at t+1 has parity PAR.
+template <int Q, int S, int PAR>
+__device__ __forceinline__ void stage_combine(const LatView<Q, S> &L, int x, int y, int z) {
+  const long long c = (long long)x + (long long)L.G.px * ((long long)y + (long long)L.G.ey * z);
+  const uint32_t bits = L.nbm[c];
+  if (bits & NB_SELF_SOLID) return;
+  const Nbr N(L.G, x, y, z);
+  float2 grp[3];
+  grp[1] = L.P0[c];
+  if (VSet<Q>::D == 3) {
+    grp[0] = L.PD[c];
+    grp[2] = L.PU[c];
+  } else {
+    grp[0] = grp[2] = make_float2(0.0f, 0.0f);
+  }
+  second_pass<Q, S>(L, N, c, PAR, x, y, bits, grp);
+  L.M[c] = group_total<Q>(grp[2], grp[1], grp[0]);
 }
 
 // Weighted mean over the fluid neighbours of solid cell s (coordinates x, y,
@@ -252,13 +377,15 @@ __device__ __forceinline__ void force(const float4 *__restrict__ C, const Nbr &N
 }
 
 // Collision of one fluid cell and streaming of its populations (AA pattern
-// of parity ODD): every population goes to the slot it streams to.  For a
+// of parity ODD): every population goes to the slot it streams to (and, if
+// `post` is given, its stored value to post[][tid]).  For a
 // link into a solid cell that slot is never read; bounce_back() then moves
 // the population to the slot the cell reads it from next step.
-template <int Q, int S, int ODD>
+template <int Q, int S, int ODD, int NT>
 __device__ __forceinline__ void collide_cell(const Pops<Q, S> &P, const Nbr &N, long long c,
                                              const float4 *__restrict__ C, const float *__restrict__ MUP,
-                                             const Phys &ph, float &rho_out, float &phi_out) {
+                                             const Phys &ph, float (*post)[NT], int tid, float &rho_out,
+                                             float &phi_out) {
   using V = VSet<Q>;
   const float mu_rho = C[c].w, mu_phi = MUP[c];
   float F[3];
@@ -290,6 +417,7 @@ __device__ __forceinline__ void collide_cell(const Pops<Q, S> &P, const Nbr &N, 
     const float dfeq = wi * (drho + rho * poly);                         // f_i^eq - w_i
     const float src = ph.guo * wi * (3.0f * (cF - uF) + 9.0f * cu * cF);  // Guo term
     const float fs = P.round(df[i] + ph.om_f * (dfeq - df[i]) + src);
+    if (post) post[i][tid] = fs;
     if (i == 0) {
       P.stf(0, c, fs);
       continue;
@@ -297,12 +425,14 @@ __device__ __forceinline__ void collide_cell(const Pops<Q, S> &P, const Nbr &N, 
     const float geq = wi * (ph.gam3 * mu_phi + phi * poly);
     geq_rest += geq;
     const float gs = P.round(g[i] + ph.om_g * (geq - g[i]));
+    if (post) post[Q + i][tid] = gs;
     // streamed: slot (x, opp(i)) after an even step, (x + c_i, i) after an odd one
     if (!ODD) { P.stf(opp(i), c, fs); P.stg(opp(i), c, gs); }
     else { const long long n = N.template at<V>(i); P.stf(i, n, fs); P.stg(i, n, gs); }
   }
   const float g0s = g[0] + ph.om_g * ((phi - geq_rest) - g[0]);  // g_0 is stored in FP32
   P.stg(0, c, g0s);
+  if (post) post[Q][tid] = g0s;
   rho_out = rho;
   phi_out = phi;
 }
@@ -339,36 +469,92 @@ __device__ __forceinline__ void bounce_back(const Pops<Q, S> &P, const Nbr &N, l
   }
 }
 
+// Collide and stream a cell.  With the by-product (FP32), every thread of
+// the 64 x COLLIDE_ROWS block must call this (it holds a barrier); `active`
+// marks threads on a storage cell.  After the barrier each thread forms the
+// first pass of the moment groups of its column: S0 for this plane, UP for
+// the plane above and DN for the plane below (all their sources lie in this
+// plane), from the tile's post-collision values.
 template <int Q, int S, int ODD>
-__device__ __forceinline__ void stage_collide(const LatView<Q, S> &L, int x, int y, int z) {
+__device__ __forceinline__ void stage_collide(const LatView<Q, S> &L, int x, int y, int z, bool active) {
+  using V = VSet<Q>;
+  constexpr int NT = BX * COLLIDE_ROWS;
   const long long c = (long long)x + (long long)L.G.px * ((long long)y + (long long)L.G.ey * z);
-  const uint32_t bits = L.nbm[c];
-  if (bits & NB_SELF_SOLID) return;
-  const Nbr N(L.G, x, y, z);
-  float rho, phi;
-  collide_cell<Q, S, ODD>(L.P, N, c, L.C, L.MUP, L.ph, rho, phi);
-  if (bits != 0u) bounce_back<Q, S, ODD>(L.P, N, c, bits, L.mask, L.G, L.ph, x, y, z, rho, phi);
+  if (!ByProduct<S>::on) {
+    if (!active) return;
+    const uint32_t bits = L.nbm[c];
+    if (bits & NB_SELF_SOLID) return;
+    const Nbr N(L.G, x, y, z);
+    float rho, phi;
+    collide_cell<Q, S, ODD, NT>(L.P, N, c, L.C, L.MUP, L.ph, nullptr, 0, rho, phi);
+    if (bits != 0u) bounce_back<Q, S, ODD>(L.P, N, c, bits, L.mask, L.G, L.ph, x, y, z, rho, phi);
+    return;
+  }
+  __shared__ float post[2 * Q][NT];
+  __shared__ unsigned char live[NT];
+  const int tid = threadIdx.y * BX + threadIdx.x;
+  bool fluid = false;
+  if (active) {
+    const uint32_t bits = L.nbm[c];
+    fluid = !(bits & NB_SELF_SOLID);
+    if (fluid) {
+      const Nbr N(L.G, x, y, z);
+      float rho, phi;
+      collide_cell<Q, S, ODD, NT>(L.P, N, c, L.C, L.MUP, L.ph, post, tid, rho, phi);
+      if (bits != 0u) bounce_back<Q, S, ODD>(L.P, N, c, bits, L.mask, L.G, L.ph, x, y, z, rho, phi);
+    }
+  }
+  live[tid] = fluid ? 1 : 0;
+  __syncthreads();
+  if (!active) return;
+  float2 grp[3];
+#pragma unroll
+  for (int k = 0; k < 3; ++k) grp[k] = make_float2(0.0f, 0.0f);
+#pragma unroll
+  for (int i = 0; i < Q; ++i) {
+    if (!in_footprint(L.G, x, y, V::cx(i), V::cy(i))) continue;
+    const int st = tid - V::cx(i) - BX * V::cy(i);
+    if (!live[st]) continue;
+    grp[V::cz(i) + 1].x += post[i][st];
+    grp[V::cz(i) + 1].y += post[Q + i][st];
+  }
+  L.P0[c] = grp[1];
+  if (V::D == 3) {
+    const long long pl = (long long)L.G.px * L.G.ey;
+    int zu = z + 1, zd = z - 1;
+    if (zu == L.G.ez) zu = L.G.per[2] ? 0 : -1;
+    if (zd < 0) zd = L.G.per[2] ? L.G.ez - 1 : -1;
+    if (zu >= 0) L.PU[c + (zu - z) * pl] = grp[2];
+    if (zd >= 0) L.PD[c + (zd - z) * pl] = grp[0];
+  }
 }
 
 // ---------------------------------------------------------------------------
 // Kernels over one lattice: one thread per storage cell (64 x 4 blocks), one
 // thread per solid boundary cell for the fills.
 // ---------------------------------------------------------------------------
-enum Stage { ST_MOMENTS = 0, ST_POTENTIAL = 1, ST_COLLIDE = 2 };
+// Stage ids; the first three double as indices of the launch shapes (the
+// moments pass, k_moments or k_combine, shares shape 0).
+enum Stage { ST_MOMENTS = SHAPE_MOMENTS, ST_POTENTIAL = SHAPE_POTENTIAL, ST_COLLIDE = SHAPE_COLLIDE, ST_COMBINE = 3 };
 
+// Per-cell stages other than collide (ODD: parity of the state they read).
 template <int Q, int S, int STAGE, int ODD>
 __device__ __forceinline__ void run_stage(const LatView<Q, S> &L, int x, int y, int z) {
   if (STAGE == ST_MOMENTS) stage_moments<Q, S, ODD>(L, x, y, z);
-  else if (STAGE == ST_POTENTIAL) stage_potential<Q, S>(L, x, y, z);
-  else stage_collide<Q, S, ODD>(L, x, y, z);
+  else if (STAGE == ST_COMBINE) stage_combine<Q, S, ODD>(L, x, y, z);
+  else stage_potential<Q, S>(L, x, y, z);
 }
 
 template <int Q, int S, int STAGE, int ODD>
 __global__ __launch_bounds__(BX *MAX_ROWS) void k_cells(LatView<Q, S> L) {
   int x, y, z;
   long long c;
-  if (!cell_of_tile(L.G, L.xcd, x, y, z, c)) return;
-  run_stage<Q, S, STAGE, ODD>(L, x, y, z);
+  const bool in = cell_of_tile(L.G, L.xcd, x, y, z, c);
+  if (STAGE == ST_COLLIDE) {
+    stage_collide<Q, S, ODD>(L, x, y, z, in);
+    return;
+  }
+  if (in) run_stage<Q, S, STAGE, ODD>(L, x, y, z);
 }
 
 template <int Q, int S, int PI>
@@ -454,6 +640,7 @@ __device__ __forceinline__ LatView<Q, S> view_of(char *base, const Inst &I) {
   L.P = pops_of<Q, S>(base + I.f, base + I.g, (float *)(base + I.g0));
   L.nbm = (const uint32_t *)(base + I.nbm); L.mask = (const uint8_t *)(base + I.mask);
   L.M = (float2 *)(base + I.M); L.C = (float4 *)(base + I.C); L.MUP = (float *)(base + I.MUP);
+  L.P0 = (float2 *)(base + I.P0); L.PU = (float2 *)(base + I.PU); L.PD = (float2 *)(base + I.PD);
   L.G = I.G; L.ph = I.ph; L.fill = (const int *)(base + I.fill); L.n_fill = I.n_fill;
   L.xcd = 0;
   return L;
@@ -467,7 +654,13 @@ __global__ __launch_bounds__(BX *MAX_ROWS) void k_batch_cells(char *base, const 
     const int4 it = work[start + w];
     const LatView<Q, S> L = view_of<Q, S>(base, inst[it.x]);
     const int x = it.y * BX + threadIdx.x, y = it.z * (int)blockDim.y + threadIdx.y, z = it.w;
-    if (x < L.G.ex && y < L.G.ey) run_stage<Q, S, STAGE, ODD>(L, x, y, z);
+    const bool in = x < L.G.ex && y < L.G.ey;
+    if (STAGE == ST_COLLIDE) {
+      stage_collide<Q, S, ODD>(L, x, y, z, in);
+      if (ByProduct<S>::on) __syncthreads();  // the tile buffer is reused by the next item
+    } else if (in) {
+      run_stage<Q, S, STAGE, ODD>(L, x, y, z);
+    }
   }
 }
 
@@ -635,19 +828,22 @@ static LatView<Q, S> view_of_args(const LaunchArgs &a) {
   LatView<Q, S> L;
   L.P = make_pops<Q, S>(a);
   L.nbm = a.nbm; L.mask = a.mask; L.M = a.M; L.C = a.C; L.MUP = a.MUP;
+  L.P0 = a.P0; L.PU = a.PU; L.PD = a.PD;
   L.G = a.G; L.ph = a.ph; L.fill = a.fill_list; L.n_fill = a.n_fill;
   L.xcd = 1;
   return L;
 }
 
-// STAGE (ST_MOMENTS, ST_POTENTIAL, ST_COLLIDE) doubles as the index of the
-// stage's launch shape.
+// Launch of a cell stage with its shape (the moments pass -- k_moments or
+// k_combine -- uses shape 0; with the by-product the collide tile always has
+// COLLIDE_ROWS rows and only its block order varies).
 template <int Q, int S, int STAGE>
 static void cells_launch(const LaunchArgs &a, int odd) {
   LatView<Q, S> L = view_of_args<Q, S>(a);
-  const Shape sh = a.shape[STAGE];
+  const Shape sh = a.shape[STAGE == ST_COMBINE ? SHAPE_MOMENTS : STAGE];
+  const int rows = (STAGE == ST_COLLIDE && ByProduct<S>::on) ? COLLIDE_ROWS : sh.rows;
   L.xcd = sh.xcd;
-  const dim3 grid = tile_grid(a.G, sh.rows), block(BX, sh.rows, 1);
+  const dim3 grid = tile_grid(a.G, rows), block(BX, rows, 1);
   if (odd) k_cells<Q, S, STAGE, 1><<<grid, block, 0, a.stream>>>(L);
   else k_cells<Q, S, STAGE, 0><<<grid, block, 0, a.stream>>>(L);
 }
@@ -688,17 +884,25 @@ static void couple_seq(const LaunchArgs &a, hipEvent_t *ev, int &k) {
   mark();
 }
 
-// One step: moments, coupling fields, collide + stream.  ev (if not null)
-// receives an event before the first launch and after each.
+// One step from state parity `odd`.  Plain: moments, coupling fields,
+// collide + stream.  By-product (M valid at entry): coupling fields, collide
+// + stream with the first moment pass, second moment pass (M valid again).
+// ev (if not null) receives an event before the first launch and after each.
 template <int Q, int S>
 static void step_seq(const LaunchArgs &a, int odd, hipEvent_t *ev) {
   int k = 0;
   if (ev) (void)hipEventRecord(ev[k++], a.stream);
-  moments_launch<Q, S>(a, odd);
-  if (ev) (void)hipEventRecord(ev[k++], a.stream);
+  if (!ByProduct<S>::on) {
+    moments_launch<Q, S>(a, odd);
+    if (ev) (void)hipEventRecord(ev[k++], a.stream);
+  }
   couple_seq<Q, S>(a, ev, k);
   cells_launch<Q, S, ST_COLLIDE>(a, odd);
   if (ev) (void)hipEventRecord(ev[k++], a.stream);
+  if (ByProduct<S>::on) {
+    cells_launch<Q, S, ST_COMBINE>(a, odd ^ 1);
+    if (ev) (void)hipEventRecord(ev[k++], a.stream);
+  }
 }
 
 template <int Q, int S> static void step_impl(const LaunchArgs &a, int odd) { step_seq<Q, S>(a, odd, nullptr); }
@@ -708,7 +912,7 @@ template <int Q, int S> static void step_events_impl(const LaunchArgs &a, int od
 template <int Q, int S>
 static void observe_impl(const LaunchArgs &a, int odd) {
   int k = 0;
-  moments_launch<Q, S>(a, odd);
+  if (!ByProduct<S>::on) moments_launch<Q, S>(a, odd);  // by-product: M is valid
   couple_seq<Q, S>(a, nullptr, k);
   k_observe<Q, S><<<cell_grid(a.G), cell_block(), 0, a.stream>>>(make_pops<Q, S>(a), a.nbm, a.C, a.MUP, a.AUX, a.G, a.ph, odd);
 }
@@ -718,6 +922,7 @@ static void init_impl(const LaunchArgs &a) {
   Pops<Q, S> P = make_pops<Q, S>(a);
   fill_launch<Q, S, 0>(a);
   k_init<Q, S><<<cell_grid(a.G), cell_block(), 0, a.stream>>>(P, a.nbm, a.M, a.AUX, a.G, a.ph);
+  moments_launch<Q, S>(a, 0);  // M of the populations just set
 }
 
 template <int Q, int S>
@@ -736,10 +941,20 @@ static void read_pops_impl(const LaunchArgs &a, int odd, float *out) {
 void launch_step(const LaunchArgs &a, int odd) { FRE_DISPATCH(step_impl, a, odd); }
 void launch_step_events(const LaunchArgs &a, int odd, hipEvent_t *ev) { FRE_DISPATCH(step_events_impl, a, odd, ev); }
 int step_kernel_count() { return 5; }
-const char *step_kernel_name(int k) {
-  static const char *names[5] = {"k_moments", "k_fill_m", "k_potential", "k_fill_c", "k_collide"};
-  return (k >= 0 && k < 5) ? names[k] : nullptr;
+template <int Q, int S> static void slots_impl(int *slot) {
+  static const int plain[5] = {0, 1, 2, 3, 4}, bp[5] = {1, 2, 3, 4, 5};
+  for (int k = 0; k < 5; ++k) slot[k] = ByProduct<S>::on ? bp[k] : plain[k];
 }
+int step_kernel_slots(const LaunchArgs &a, int *slot) {
+  FRE_DISPATCH(slots_impl, slot);
+  return 6;
+}
+const char *step_kernel_name(int k) {
+  static const char *names[6] = {"k_moments", "k_fill_m", "k_potential", "k_fill_c", "k_collide", "k_combine"};
+  return (k >= 0 && k < 6) ? names[k] : nullptr;
+}
+void launch_moments(const LaunchArgs &a, int odd) { FRE_DISPATCH(moments_launch, a, odd); }
+bool uses_by_product(const LaunchArgs &a) { return a.storage == 0; }
 void launch_observe(const LaunchArgs &a, int odd) { FRE_DISPATCH(observe_impl, a, odd); }
 void launch_init(const LaunchArgs &a) { FRE_DISPATCH(init_impl, a); }
 void launch_read_pops(const LaunchArgs &a, int odd, float *out) { FRE_DISPATCH(read_pops_impl, a, odd, out); }
@@ -751,13 +966,19 @@ template <int Q, int S>
 static void batch_step_impl(const BatchArgs &b, int cls, int odd) {
   const int *rc = b.range + 4 * cls, *rf = rc + 2;
   const dim3 bl(BX, b.rows, 1);
-  if (odd) k_batch_cells<Q, S, ST_MOMENTS, 1><<<b.grid_cells, bl, 0, b.stream>>>(b.base, b.inst, b.work, rc);
-  else k_batch_cells<Q, S, ST_MOMENTS, 0><<<b.grid_cells, bl, 0, b.stream>>>(b.base, b.inst, b.work, rc);
+  if (!ByProduct<S>::on) {
+    if (odd) k_batch_cells<Q, S, ST_MOMENTS, 1><<<b.grid_cells, bl, 0, b.stream>>>(b.base, b.inst, b.work, rc);
+    else k_batch_cells<Q, S, ST_MOMENTS, 0><<<b.grid_cells, bl, 0, b.stream>>>(b.base, b.inst, b.work, rc);
+  }
   k_batch_fill<Q, S, 0><<<b.grid_fill, 256, 0, b.stream>>>(b.base, b.inst, b.fill, rf);
   k_batch_cells<Q, S, ST_POTENTIAL, 0><<<b.grid_cells, bl, 0, b.stream>>>(b.base, b.inst, b.work, rc);
   k_batch_fill<Q, S, 1><<<b.grid_fill, 256, 0, b.stream>>>(b.base, b.inst, b.fill, rf);
   if (odd) k_batch_cells<Q, S, ST_COLLIDE, 1><<<b.grid_cells, bl, 0, b.stream>>>(b.base, b.inst, b.work, rc);
   else k_batch_cells<Q, S, ST_COLLIDE, 0><<<b.grid_cells, bl, 0, b.stream>>>(b.base, b.inst, b.work, rc);
+  if (ByProduct<S>::on) {
+    if (odd) k_batch_cells<Q, S, ST_COMBINE, 0><<<b.grid_cells, bl, 0, b.stream>>>(b.base, b.inst, b.work, rc);
+    else k_batch_cells<Q, S, ST_COMBINE, 1><<<b.grid_cells, bl, 0, b.stream>>>(b.base, b.inst, b.work, rc);
+  }
 }
 
 void launch_batch_step(const BatchArgs &b, int cls, int odd) {

@@ -81,9 +81,9 @@ _SIGS = [
     ("fre_batch_remove", C.c_int32, [C.c_void_p, C.c_int32]),
     ("fre_batch_step", C.c_int32, [C.c_void_p, C.c_int64]),
     ("fre_batch_info", C.c_int32, [C.c_void_p, C.POINTER(C.c_int32), C.POINTER(C.c_int32)]),
-    ("fre_batch_set_launch_shape", C.c_int32, [C.c_void_p, C.c_int32, C.c_int32]),
-    ("fre_batch_get_launch_shape", C.c_int32, [C.c_void_p, C.c_void_p]),
-    ("fre_batch_autotune", C.c_int32, [C.c_void_p, C.c_int64, C.c_void_p, C.POINTER(C.c_double)]),
+    ("fre_batch_set_launch_shape", C.c_int32, [C.c_void_p, C.c_int32]),
+    ("fre_batch_get_launch_shape", C.c_int32, [C.c_void_p, C.POINTER(C.c_int32)]),
+    ("fre_batch_autotune", C.c_int32, [C.c_void_p, C.c_int64, C.POINTER(C.c_int32), C.POINTER(C.c_double)]),
     ("fre_batch_destroy", None, [C.c_void_p]),
     ("fre_last_error", C.c_char_p, []),
 ]
@@ -243,7 +243,7 @@ class Lattice:
         ms = np.zeros(16)
         k = C.c_int32()
         _check(lib().fre_profile_step(self._h, int(n), _ptr(ms), 16, C.byref(k)))
-        return {lib().fre_kernel_name(i).decode(): float(ms[i]) for i in range(k.value)}
+        return {lib().fre_kernel_name(i).decode(): float(ms[i]) for i in range(k.value) if ms[i] >= 0.0}
 
     STAGES = ("k_moments", "k_potential", "k_collide")
 
@@ -319,22 +319,22 @@ class Batch:
         _check(lib().fre_batch_info(self._h, C.byref(m), C.byref(p)))
         return m.value, p.value
 
-    def launch_shape(self):
-        """(rows per work item, persistent blocks per CU)."""
-        out = np.zeros(2, np.int32)
-        _check(lib().fre_batch_get_launch_shape(self._h, _ptr(out)))
-        return int(out[0]), int(out[1])
+    def launch_shape(self) -> int:
+        """Persistent blocks per CU of the cell kernels."""
+        b = C.c_int32()
+        _check(lib().fre_batch_get_launch_shape(self._h, C.byref(b)))
+        return b.value
 
-    def set_launch_shape(self, rows: int, blocks_per_cu: int):
-        _check(lib().fre_batch_set_launch_shape(self._h, int(rows), int(blocks_per_cu)))
+    def set_launch_shape(self, blocks_per_cu: int):
+        _check(lib().fre_batch_set_launch_shape(self._h, int(blocks_per_cu)))
 
     def autotune(self, n: int = 10):
-        """Pick the fastest (rows, blocks per CU) on the current members
-        (their states are restored); returns (rows, blocks_per_cu, ms/step)."""
-        out = np.zeros(2, np.int32)
+        """Pick the fastest blocks per CU on the current members (their
+        states are restored); returns (blocks_per_cu, ms/step)."""
+        b = C.c_int32()
         ms = C.c_double()
-        _check(lib().fre_batch_autotune(self._h, int(n), _ptr(out), C.byref(ms)))
-        return int(out[0]), int(out[1]), ms.value
+        _check(lib().fre_batch_autotune(self._h, int(n), C.byref(b), C.byref(ms)))
+        return b.value, ms.value
 
     def close(self):
         if getattr(self, "_h", None):
