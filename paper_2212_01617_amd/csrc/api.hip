@@ -54,7 +54,7 @@ struct Plan {
   int off[3];
   int px;          // row pitch: ext[0] rounded up to a multiple of 64
   long long ncell;  // px * ext[1] * ext[2]
-  size_t o_f, o_g, o_g0, o_mask, o_nbm, o_M, o_C, o_MUP, o_P0, o_PU, o_PD, o_AUX, o_fill, o_part, total;
+  size_t o_f, o_g, o_g0, o_mask, o_nbm, o_M, o_C, o_MUP, o_P0, o_PU, o_PD, o_XE, o_AUX, o_fill, o_part, total;
 };
 
 fre_status validate(const fre_params *p) {
@@ -133,6 +133,9 @@ Plan make_plan(const fre_params *p) {
   P.o_P0 = bp ? take((size_t)P.ncell * 8) : 0;
   P.o_PU = bp && P.q == 19 ? take((size_t)P.ncell * 8) : 0;
   P.o_PD = bp && P.q == 19 ? take((size_t)P.ncell * 8) : 0;
+  // FP32: per 64-cell row segment, the post-collision (f, g) of the
+  // populations that leave it through its first and last column
+  P.o_XE = bp ? take((size_t)(P.ncell / 64) * 2 * (P.q == 19 ? 5 : 3) * 8) : 0;
   P.o_AUX = take((size_t)P.ncell * 16);
   P.o_fill = take((size_t)P.ncell * 4);
   P.o_part = take((size_t)reduce_blocks() * 8 * sizeof(double));
@@ -303,6 +306,7 @@ void bind_args(fre_lattice *L) {
   a.P0 = P.o_P0 ? (float2 *)(L->base + P.o_P0) : nullptr;
   a.PU = P.o_PU ? (float2 *)(L->base + P.o_PU) : nullptr;
   a.PD = P.o_PD ? (float2 *)(L->base + P.o_PD) : nullptr;
+  a.XE = P.o_XE ? (float2 *)(L->base + P.o_XE) : nullptr;
   a.AUX = (float4 *)(L->base + P.o_AUX);
   a.fill_list = (int *)(L->base + P.o_fill);
   a.n_fill = (int)L->fill_host.size();
@@ -832,6 +836,7 @@ Inst inst_of(const fre_lattice *L, const void *base) {
   I.P0 = L->a.P0 ? rel(L->a.P0, base) : 0;
   I.PU = L->a.PU ? rel(L->a.PU, base) : 0;
   I.PD = L->a.PD ? rel(L->a.PD, base) : 0;
+  I.XE = L->a.XE ? rel(L->a.XE, base) : 0;
   I.fill = rel(L->a.fill_list, base);
   I.n_fill = L->a.n_fill;
   return I;

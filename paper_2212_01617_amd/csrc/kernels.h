@@ -40,6 +40,7 @@ struct LaunchArgs {
   float4 *C;    // (rho - 1, phi, Pi = rho mu_rho + phi mu_phi, mu_rho)
   float *MUP;   // mu_phi
   float2 *P0, *PU, *PD;  // FP32: first-pass moment sums by source plane (same, below, above)
+  float2 *XE;   // FP32: post-collision (f, g) leaving each 64-cell row segment sideways
   float4 *AUX;  // u0 at init; (ux, uy, uz, P) after observe
   int *fill_list;
   int n_fill;
@@ -63,6 +64,7 @@ template <int Q, int S> struct LatView {
   float4 *C;
   float *MUP;
   float2 *P0, *PU, *PD;
+  float2 *XE;
   Geom G;
   Phys ph;
   const int *fill;
@@ -76,7 +78,7 @@ template <int Q, int S> struct LatView {
 struct Inst {
   Geom G;
   Phys ph;
-  long long f, g, g0, mask, nbm, M, C, MUP, P0, PU, PD, fill;
+  long long f, g, g0, mask, nbm, M, C, MUP, P0, PU, PD, XE, fill;
   int n_fill;
 };
 

@@ -128,9 +128,10 @@ __device__ __forceinline__ void load_pops(const Pops<Q, S> &P, const Nbr &N, lon
 // destination's tile footprint, the 64 x COLLIDE_ROWS columns of the collide
 // tile grid that contains it -- then the others.  k_collide forms the first
 // pass on chip from the post-collision values of its tile and stores it per
-// group; k_combine adds the second pass from the population arrays (tile-edge
-// sources and bounce-backs) and stores M; k_moments performs both passes from
-// the population arrays.  The additions are the same in every case, so M does
+// group; k_combine adds the second pass (tile-edge sources and bounce-backs)
+// from the population arrays and, for sources across a tile's x edge, from
+// the compact copy XE that k_collide leaves, and stores M; k_moments
+// performs both passes from the population arrays.  The additions are the same in every case, so M does
 // not depend on which path computed it.  FP16 storage keeps the plain moment
 // pass, which reads half the bytes and costs less than the partial planes.
 // ---------------------------------------------------------------------------
@@ -141,6 +142,35 @@ __device__ __forceinline__ bool in_footprint(const Geom &G, int x, int y, int cx
   const int xlo = x & ~(BX - 1), ylo = (y / COLLIDE_ROWS) * COLLIDE_ROWS;
   return sx >= xlo && sx < min(xlo + BX, G.ex) && sy >= ylo && sy < min(ylo + COLLIDE_ROWS, G.ey);
 }
+
+// Populations that leave a 64-cell row segment sideways.  XE holds, for each
+// segment, the post-collision (f, g) of the directions with c_x = -1 at the
+// segment's first column (side 0) and of those with c_x = +1 at its last
+// storage column (side 1; ex - 1 for a short last segment).  It is laid out
+// [z][side][e][segment column bx][y], e counting a side's directions in
+// ascending order, so that the rows of one tile read and write consecutive
+// entries.  k_collide writes them for every fluid cell on those columns and
+// k_combine reads them in place of the population arrays, where each value
+// would cost a 128-byte line of its own.
+template <class V> struct XEdge {
+  static constexpr int NE = V::D == 3 ? 5 : 3;
+  // rank of direction i among the directions with the same c_x != 0, in
+  // ascending order (D3Q19: 1 7 9 11 13 and 2 8 10 12 14; D2Q9: 1 5 7 and 2 6 8)
+  __host__ __device__ static constexpr int slot(int i) {
+    return i < 3 ? 0 : (V::D == 3 ? (i - 5) / 2 : (i - 3) / 2);
+  }
+  // direction of entry e of a side (the inverse of slot)
+  __device__ static int dir(int side, int e) { return e == 0 ? 2 - side : 2 * e + (V::D == 3 ? 6 : 4) - side; }
+  // entry e of `side` for the segment holding cell (x, y, z)
+  __device__ static uint32_t index(const Geom &G, int x, int y, int z, int side, int e) {
+    return ((((uint32_t)z * (uint32_t)(G.px >> 6) + (uint32_t)(x >> 6)) * (uint32_t)G.ey + (uint32_t)y) * 2u +
+            (uint32_t)side) * NE + (uint32_t)e;
+  }
+  // entry of direction i (c_x != 0) leaving cell (x, y, z)
+  __device__ static uint32_t index(const Geom &G, int x, int y, int z, int i) {
+    return index(G, x, y, z, V::cx(i) > 0 ? 1 : 0, slot(i));
+  }
+};
 
 // Population i of fluid cell c at parity `odd` (AA pattern), as load_pops.
 template <int Q, int S>
@@ -171,24 +201,72 @@ __device__ __forceinline__ float2 group_total(float2 up, float2 s0, float2 dn) {
   return make_float2((up.x + s0.x) + dn.x, (up.y + s0.y) + dn.y);
 }
 
+// Direction sets as bit masks (bit i for direction i).
+template <class V> struct DirBits {
+  static constexpr int Q = V::D == 3 ? 19 : 9;
+  static constexpr uint32_t with(int ax, int sgn) {
+    uint32_t m = 0;
+    for (int i = 1; i < Q; ++i)
+      if ((ax == 0 ? V::cx(i) : ax == 1 ? V::cy(i) : V::cz(i)) == sgn) m |= 1u << i;
+    return m;
+  }
+  static constexpr uint32_t parity(int r) {
+    uint32_t m = 0;
+    for (int i = 1; i < Q; ++i)
+      if ((i & 1) == r) m |= 1u << i;
+    return m;
+  }
+  static constexpr uint32_t XP = with(0, 1), XM = with(0, -1), YP = with(1, 1), YM = with(1, -1);
+  static constexpr uint32_t ODD = parity(1), EVEN = parity(0);
+  // bit i: the source x - c_i of a fluid cell with neighbour word `bits` is
+  // not fluid (bit opp(i) of the word; opp pairs 2k-1 with 2k)
+  __device__ static uint32_t solid_sources(uint32_t bits) { return ((bits >> 1) & ODD) | ((bits << 1) & EVEN); }
+};
+
 // Second pass for fluid cell c: adds the unavailable sources of each group,
 // in ascending direction order, to the first-pass sums grp[cz + 1].  All
-// needed loads are issued before the sums.
+// needed loads are issued before the sums.  With XE given (FP32), fluid
+// sources across the x edge of the footprint are read from it (the same
+// values) through the same load as the population arrays.
 template <int Q, int S>
 __device__ __forceinline__ void second_pass(const LatView<Q, S> &L, const Nbr &N, long long c, int odd, int x,
-                                            int y, uint32_t bits, float2 grp[3]) {
+                                            int y, int z, uint32_t bits, float2 grp[3], const float2 *XE) {
   using V = VSet<Q>;
+  using B = DirBits<V>;
+  const int xlo = x & ~(BX - 1), ylo = (y / COLLIDE_ROWS) * COLLIDE_ROWS;
+  const uint32_t solid = B::solid_sources(bits);
+  // sources across each footprint edge (the complement of in_footprint)
+  const uint32_t xe = (x == xlo ? B::XP : 0u) | (x == min(xlo + BX, L.G.ex) - 1 ? B::XM : 0u);
+  const uint32_t ye = (y == ylo ? B::YP : 0u) | (y == min(ylo + COLLIDE_ROWS, L.G.ey) - 1 ? B::YM : 0u);
+  const uint32_t un = solid | xe | ye;           // unavailable sources
+  const uint32_t side = XE ? (xe & ~solid) : 0u;  // of those, read from XE
   float vf[Q], vg[Q];
 #pragma unroll
-  for (int i = 0; i < Q; ++i) {
+  for (int i = 1; i < Q; ++i) {
     vf[i] = vg[i] = 0.0f;
-    if (!available<V>(L.G, x, y, bits, i)) pop_at<Q, S>(L.P, N, c, odd, i, vf[i], vg[i]);
+    if (!((un >> i) & 1u)) continue;
+    if constexpr (S == 0) {
+      const long long s = !odd ? c : (long long)N.template back<V>(i);
+      const int slot = !odd ? i : opp(i);
+      const float *pf = L.P.f + blk_offset<4>(Q, slot, s) / 4;
+      const float *pg = L.P.g + blk_offset<4>(Q, slot, s) / 4;
+      if (V::cx(i) != 0 && ((side >> i) & 1u)) {
+        const int sx = wrap(x - V::cx(i), L.G.ex), sy = wrap(y - V::cy(i), L.G.ey);
+        const int sz = V::D == 3 ? wrap(z - V::cz(i), L.G.ez) : 0;
+        pf = &XE[XEdge<V>::index(L.G, sx, sy, sz, i)].x;
+        pg = pf + 1;
+      }
+      vf[i] = __builtin_nontemporal_load(pf);
+      vg[i] = __builtin_nontemporal_load(pg);
+    } else {
+      pop_at<Q, S>(L.P, N, c, odd, i, vf[i], vg[i]);
+    }
   }
 #pragma unroll
   for (int k = 0; k < 3; ++k)
 #pragma unroll
-    for (int i = 0; i < Q; ++i) {
-      if (V::cz(i) != k - 1 || available<V>(L.G, x, y, bits, i)) continue;
+    for (int i = 1; i < Q; ++i) {
+      if (V::cz(i) != k - 1 || !((un >> i) & 1u)) continue;
       grp[k].x += vf[i];
       grp[k].y += vg[i];
     }
@@ -249,7 +327,7 @@ __device__ __forceinline__ void stage_combine(const LatView<Q, S> &L, int x, int
   } else {
     grp[0] = grp[2] = make_float2(0.0f, 0.0f);
   }
-  second_pass<Q, S>(L, N, c, PAR, x, y, bits, grp);
+  second_pass<Q, S>(L, N, c, PAR, x, y, z, bits, grp, L.XE);
   L.M[c] = group_total<Q>(grp[2], grp[1], grp[0]);
 }
 
@@ -377,15 +455,17 @@ __device__ __forceinline__ void force(const float4 *__restrict__ C, const Nbr &N
 }
 
 // Collision of one fluid cell and streaming of its populations (AA pattern
-// of parity ODD): every population goes to the slot it streams to (and, if
-// `post` is given, its stored value to post[][tid]).  For a
+// of parity ODD): every population goes to the slot it streams to.  If
+// `post` is given, the stored value of each moving population i > 0 also goes
+// to post[i - 1][tid] (f) and post[Q - 1 + i - 1][tid] (g); the rest
+// populations are returned in rest_out.  For a
 // link into a solid cell that slot is never read; bounce_back() then moves
 // the population to the slot the cell reads it from next step.
 template <int Q, int S, int ODD, int NT>
 __device__ __forceinline__ void collide_cell(const Pops<Q, S> &P, const Nbr &N, long long c,
                                              const float4 *__restrict__ C, const float *__restrict__ MUP,
                                              const Phys &ph, float (*post)[NT], int tid, float &rho_out,
-                                             float &phi_out) {
+                                             float &phi_out, float2 &rest_out) {
   using V = VSet<Q>;
   const float mu_rho = C[c].w, mu_phi = MUP[c];
   float F[3];
@@ -417,22 +497,23 @@ __device__ __forceinline__ void collide_cell(const Pops<Q, S> &P, const Nbr &N, 
     const float dfeq = wi * (drho + rho * poly);                         // f_i^eq - w_i
     const float src = ph.guo * wi * (3.0f * (cF - uF) + 9.0f * cu * cF);  // Guo term
     const float fs = P.round(df[i] + ph.om_f * (dfeq - df[i]) + src);
-    if (post) post[i][tid] = fs;
     if (i == 0) {
       P.stf(0, c, fs);
+      rest_out.x = fs;
       continue;
     }
+    if (post) post[i - 1][tid] = fs;
     const float geq = wi * (ph.gam3 * mu_phi + phi * poly);
     geq_rest += geq;
     const float gs = P.round(g[i] + ph.om_g * (geq - g[i]));
-    if (post) post[Q + i][tid] = gs;
+    if (post) post[Q - 1 + i - 1][tid] = gs;
     // streamed: slot (x, opp(i)) after an even step, (x + c_i, i) after an odd one
     if (!ODD) { P.stf(opp(i), c, fs); P.stg(opp(i), c, gs); }
     else { const long long n = N.template at<V>(i); P.stf(i, n, fs); P.stg(i, n, gs); }
   }
   const float g0s = g[0] + ph.om_g * ((phi - geq_rest) - g[0]);  // g_0 is stored in FP32
   P.stg(0, c, g0s);
-  if (post) post[Q][tid] = g0s;
+  rest_out.y = g0s;
   rho_out = rho;
   phi_out = phi;
 }
@@ -486,37 +567,52 @@ __device__ __forceinline__ void stage_collide(const LatView<Q, S> &L, int x, int
     if (bits & NB_SELF_SOLID) return;
     const Nbr N(L.G, x, y, z);
     float rho, phi;
-    collide_cell<Q, S, ODD, NT>(L.P, N, c, L.C, L.MUP, L.ph, nullptr, 0, rho, phi);
+    float2 rest;
+    collide_cell<Q, S, ODD, NT>(L.P, N, c, L.C, L.MUP, L.ph, nullptr, 0, rho, phi, rest);
     if (bits != 0u) bounce_back<Q, S, ODD>(L.P, N, c, bits, L.mask, L.G, L.ph, x, y, z, rho, phi);
     return;
   }
-  __shared__ float post[2 * Q][NT];
+  __shared__ float post[2 * (Q - 1)][NT];
   __shared__ unsigned char live[NT];
   const int tid = threadIdx.y * BX + threadIdx.x;
   bool fluid = false;
+  float2 rest = make_float2(0.0f, 0.0f);
   if (active) {
     const uint32_t bits = L.nbm[c];
     fluid = !(bits & NB_SELF_SOLID);
     if (fluid) {
       const Nbr N(L.G, x, y, z);
       float rho, phi;
-      collide_cell<Q, S, ODD, NT>(L.P, N, c, L.C, L.MUP, L.ph, post, tid, rho, phi);
+      collide_cell<Q, S, ODD, NT>(L.P, N, c, L.C, L.MUP, L.ph, post, tid, rho, phi, rest);
       if (bits != 0u) bounce_back<Q, S, ODD>(L.P, N, c, bits, L.mask, L.G, L.ph, x, y, z, rho, phi);
     }
   }
   live[tid] = fluid ? 1 : 0;
   __syncthreads();
+  // XE entries of this row: lane e < NE stores entry e of side 0 (first
+  // column), lane NE + e entry e of side 1 (last column), if that cell is fluid
+  if (threadIdx.x < 2 * XEdge<V>::NE) {
+    const int side = threadIdx.x >= XEdge<V>::NE ? 1 : 0, e = threadIdx.x - side * XEdge<V>::NE;
+    const int xlo = x & ~(BX - 1), xs = side ? min(xlo + BX, L.G.ex) - 1 : xlo;
+    const int st = threadIdx.y * BX + (xs - xlo);
+    if (live[st]) {
+      const int i = XEdge<V>::dir(side, e);
+      L.XE[XEdge<V>::index(L.G, xs, y, z, side, e)] = make_float2(post[i - 1][st], post[Q - 1 + i - 1][st]);
+    }
+  }
   if (!active) return;
   float2 grp[3];
+  grp[0] = grp[2] = make_float2(0.0f, 0.0f);
+  // direction 0 first, added to zero as in the other paths (a solid cell's
+  // sums are never read)
+  grp[1] = make_float2(0.0f + rest.x, 0.0f + rest.y);
 #pragma unroll
-  for (int k = 0; k < 3; ++k) grp[k] = make_float2(0.0f, 0.0f);
-#pragma unroll
-  for (int i = 0; i < Q; ++i) {
+  for (int i = 1; i < Q; ++i) {
     if (!in_footprint(L.G, x, y, V::cx(i), V::cy(i))) continue;
     const int st = tid - V::cx(i) - BX * V::cy(i);
     if (!live[st]) continue;
-    grp[V::cz(i) + 1].x += post[i][st];
-    grp[V::cz(i) + 1].y += post[Q + i][st];
+    grp[V::cz(i) + 1].x += post[i - 1][st];
+    grp[V::cz(i) + 1].y += post[Q - 1 + i - 1][st];
   }
   L.P0[c] = grp[1];
   if (V::D == 3) {
@@ -641,6 +737,7 @@ __device__ __forceinline__ LatView<Q, S> view_of(char *base, const Inst &I) {
   L.nbm = (const uint32_t *)(base + I.nbm); L.mask = (const uint8_t *)(base + I.mask);
   L.M = (float2 *)(base + I.M); L.C = (float4 *)(base + I.C); L.MUP = (float *)(base + I.MUP);
   L.P0 = (float2 *)(base + I.P0); L.PU = (float2 *)(base + I.PU); L.PD = (float2 *)(base + I.PD);
+  L.XE = (float2 *)(base + I.XE);
   L.G = I.G; L.ph = I.ph; L.fill = (const int *)(base + I.fill); L.n_fill = I.n_fill;
   L.xcd = 0;
   return L;
@@ -828,7 +925,7 @@ static LatView<Q, S> view_of_args(const LaunchArgs &a) {
   LatView<Q, S> L;
   L.P = make_pops<Q, S>(a);
   L.nbm = a.nbm; L.mask = a.mask; L.M = a.M; L.C = a.C; L.MUP = a.MUP;
-  L.P0 = a.P0; L.PU = a.PU; L.PD = a.PD;
+  L.P0 = a.P0; L.PU = a.PU; L.PD = a.PD; L.XE = a.XE;
   L.G = a.G; L.ph = a.ph; L.fill = a.fill_list; L.n_fill = a.n_fill;
   L.xcd = 1;
   return L;
