@@ -470,13 +470,21 @@ __device__ __forceinline__ void collide_cell(const Pops<Q, S> &P, const Nbr &N, 
   const float mu_rho = C[c].w, mu_phi = MUP[c];
   float F[3];
   force<Q>(C, N, mu_rho, mu_phi, F);
+  // FP16 storage loads g only after f is collided and stored, which holds the
+  // kernel to 128 VGPRs (4 waves per SIMD); with FP32 storage and the moment
+  // sums the split costs registers instead, so f and g are loaded together.
+  constexpr bool SPLIT = S == 1;
   float df[Q], g[Q];
-  load_pops<Q, S>(P, N, c, ODD, df, g);
-  float drho = 0.0f, phi = 0.0f, j[3] = {0, 0, 0};
+  if constexpr (SPLIT) {
+#pragma unroll
+    for (int i = 0; i < Q; ++i) df[i] = (!ODD || i == 0) ? P.ldf(i, c) : P.ldf(opp(i), N.template back<V>(i));
+  } else {
+    load_pops<Q, S>(P, N, c, ODD, df, g);
+  }
+  float drho = 0.0f, j[3] = {0, 0, 0};
 #pragma unroll
   for (int i = 0; i < Q; ++i) {
     drho += df[i];
-    phi += g[i];
     j[0] += V::cx(i) * df[i];
     j[1] += V::cy(i) * df[i];
     j[2] += V::cz(i) * df[i];
@@ -487,13 +495,33 @@ __device__ __forceinline__ void collide_cell(const Pops<Q, S> &P, const Nbr &N, 
                       (j[2] + 0.5f * F[2]) * inv_rho};
   const float uu = u[0] * u[0] + u[1] * u[1] + u[2] * u[2];
   const float uF = u[0] * F[0] + u[1] * F[1] + u[2] * F[2];
+  // the same expression in both loops, so f and g see the same value
+  auto poly_of = [&](int i) {
+    const float cu = V::cx(i) * u[0] + V::cy(i) * u[1] + V::cz(i) * u[2];
+    return 3.0f * cu + 4.5f * cu * cu - 1.5f * uu;
+  };
+  float phi = 0.0f;
+  if constexpr (!SPLIT) {
+#pragma unroll
+    for (int i = 0; i < Q; ++i) phi += g[i];
+  }
   float geq_rest = 0.0f;
+  // post-collision g_i of direction i > 0, stored to the slot it streams to
+  auto collide_g = [&](int i) {
+    const float geq = V::w(i) * (ph.gam3 * mu_phi + phi * poly_of(i));
+    geq_rest += geq;
+    const float gs = P.round(g[i] + ph.om_g * (geq - g[i]));
+    if (post) post[Q - 1 + i - 1][tid] = gs;
+    // streamed: slot (x, opp(i)) after an even step, (x + c_i, i) after an odd one
+    if (!ODD) P.stg(opp(i), c, gs);
+    else P.stg(i, N.template at<V>(i), gs);
+  };
 #pragma unroll
   for (int i = 0; i < Q; ++i) {
-    const float cu = V::cx(i) * u[0] + V::cy(i) * u[1] + V::cz(i) * u[2];
     const float cF = V::cx(i) * F[0] + V::cy(i) * F[1] + V::cz(i) * F[2];
+    const float cu = V::cx(i) * u[0] + V::cy(i) * u[1] + V::cz(i) * u[2];
     const float wi = V::w(i);
-    const float poly = 3.0f * cu + 4.5f * cu * cu - 1.5f * uu;
+    const float poly = poly_of(i);
     const float dfeq = wi * (drho + rho * poly);                         // f_i^eq - w_i
     const float src = ph.guo * wi * (3.0f * (cF - uF) + 9.0f * cu * cF);  // Guo term
     const float fs = P.round(df[i] + ph.om_f * (dfeq - df[i]) + src);
@@ -503,13 +531,17 @@ __device__ __forceinline__ void collide_cell(const Pops<Q, S> &P, const Nbr &N, 
       continue;
     }
     if (post) post[i - 1][tid] = fs;
-    const float geq = wi * (ph.gam3 * mu_phi + phi * poly);
-    geq_rest += geq;
-    const float gs = P.round(g[i] + ph.om_g * (geq - g[i]));
-    if (post) post[Q - 1 + i - 1][tid] = gs;
-    // streamed: slot (x, opp(i)) after an even step, (x + c_i, i) after an odd one
-    if (!ODD) { P.stf(opp(i), c, fs); P.stg(opp(i), c, gs); }
-    else { const long long n = N.template at<V>(i); P.stf(i, n, fs); P.stg(i, n, gs); }
+    if (!ODD) P.stf(opp(i), c, fs);
+    else P.stf(i, N.template at<V>(i), fs);
+    if constexpr (!SPLIT) collide_g(i);
+  }
+  if constexpr (SPLIT) {
+#pragma unroll
+    for (int i = 0; i < Q; ++i) g[i] = (!ODD || i == 0) ? P.ldg(i, c) : P.ldg(opp(i), N.template back<V>(i));
+#pragma unroll
+    for (int i = 0; i < Q; ++i) phi += g[i];
+#pragma unroll
+    for (int i = 1; i < Q; ++i) collide_g(i);
   }
   const float g0s = g[0] + ph.om_g * ((phi - geq_rest) - g[0]);  // g_0 is stored in FP32
   P.stg(0, c, g0s);
@@ -642,7 +674,9 @@ __device__ __forceinline__ void run_stage(const LatView<Q, S> &L, int x, int y, 
 }
 
 template <int Q, int S, int STAGE, int ODD>
-__global__ __launch_bounds__(BX *MAX_ROWS) void k_cells(LatView<Q, S> L) {
+// FP16 storage: at most 128 VGPRs, 4 waves per SIMD for the collide (measured
+// faster than 3 waves without spills); FP32 keeps the compiler's choice.
+__global__ __launch_bounds__(BX *MAX_ROWS) __attribute__((amdgpu_waves_per_eu(S == 1 ? 4 : 1))) void k_cells(LatView<Q, S> L) {
   int x, y, z;
   long long c;
   const bool in = cell_of_tile(L.G, L.xcd, x, y, z, c);
