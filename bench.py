@@ -62,12 +62,14 @@ def measured_traffic():
         return None
 
 
-def workload(storage: int):
+def workload(storage: int, shape=(256, 128, 128), R: float = 25.0):
+    """The shear-droplet lattice: D3Q19, walls in z moving at -+u_w, periodic
+    x and y, a drop of radius R mid-domain, Ca = 0.1, Re = 1, xi = 2."""
     from paper_2212_01617_amd import frelbm as F
     from paper_2212_01617_amd import synth
     from paper_2212_01617_amd.params import derive_params
-    nx, ny, nz = 256, 128, 128
-    xi, R = 2.0, 25.0
+    nx, ny, nz = shape
+    xi = 2.0
     dp = derive_params(Re=1.0, Ca=0.1, radius=R, xi=xi, H=nz, Pe=0.43)
     gamma, uw = dp.rate, dp.wall_u
     wu = np.zeros((3, 2, 3)); wu[2, 0, 0] = -uw; wu[2, 1, 0] = uw
@@ -104,6 +106,30 @@ def time_steps(L, steps, warmup, reps):
     return float(np.median(times)), times
 
 
+def large_lattice(steps: int = 100) -> dict:
+    """The same workload scaled 2x per axis (512x256x256, R = 50, 33.6 M
+    cells), a footprint many times the 256 MB Infinity Cache, FP32 and FP16
+    storage, autotuned like the main leg."""
+    import torch
+    from paper_2212_01617_amd import frelbm as F
+    out = {"workload": "D3Q19 shear droplet 512x256x256, walls in z, R=50, xi=2, Ca=0.1, Re=1"}
+    for storage, key in ((0, "fp32"), (1, "fp16")):
+        p, phi0, u0, meta = workload(storage, (512, 256, 256), 50.0)
+        L = F.Lattice(p, phi0, None, u0, stream=torch.cuda.Stream())
+        del phi0, u0
+        L.autotune(5)
+        ms, _ = time_steps(L, steps, 10, 3)
+        n = 512 * 256 * 256
+        mlups = n / (ms * 1e-3) / 1e6
+        b = bytes_per_lu(19, storage)
+        out[key] = {"value": round(mlups, 1), "unit": "MLUPS", "ms_per_step": round(ms, 5), "bytes_per_lu": b,
+                    "step_frac": round(mlups * 1e6 * b / 1e9 / PEAK_HBM_GBS, 4),
+                    "device_bytes": int(L._nbytes)}
+        L.close()
+        torch.cuda.empty_cache()
+    return out
+
+
 def cpu_baseline(p_gpu, phi0, u0, meta, steps=60):
     from oracle import oracle as O
     nx, ny, nz = meta["shape"]
@@ -127,6 +153,7 @@ def main():
     ap.add_argument("--reps", type=int, default=5)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-fp16", action="store_true")
+    ap.add_argument("--no-large", action="store_true", help="skip the 512x256x256 leg")
     ap.add_argument("--serve", type=int, default=24, help="requests in the serving leg (0: skip)")
     ap.add_argument("--kernels-only", type=int, default=0)
     ap.add_argument("--no-tune", action="store_true", help="keep the default launch shapes")
@@ -213,6 +240,8 @@ def main():
     for v in res.values():
         v["L"].close()
     res.clear()
+    if not args.no_large:
+        out["large_lattice"] = large_lattice()
     if args.serve:
         out["serving"] = serving(args.serve)
     if not args.no_cpu_baseline:

@@ -185,9 +185,14 @@ class Lattice:
         self._h = h
 
     def close(self):
+        """Destroy the handle and release the device buffer once the
+        lattice's stream has finished with it."""
         if getattr(self, "_h", None):
             lib().fre_lattice_destroy(self._h)
             self._h = None
+            if getattr(self, "stream", None) is not None:
+                self.stream.synchronize()
+        self.buf = None
 
     def __del__(self):
         self.close()
