@@ -52,6 +52,13 @@
  *     A ghost cell lying in the ghost layers of several axes moves with the
  *     mean of those walls' velocities.
  *   - Initialisation: f = f^eq(rho0,u0), g = g^eq(phi0, mu_phi(rho0,phi0), u0).
+ *   - Consistent initialisation (Sec. 2.3 cites Mei, Luo, Lallemand and
+ *     d'Humieres 2006, without details): pre-iterations of the f population
+ *     in which the velocity of the equilibrium and of the forcing term is
+ *     held at the prescribed u0 and phi at phi0, while rho evolves and the
+ *     non-equilibrium part of f develops; g is not stepped.  Afterwards g is
+ *     reset to g^eq(phi0, mu_phi(rho, phi0), u0) with the new rho.  The time
+ *     counter stays at 0.
  */
 #include <math.h>
 #include <stdint.h>
@@ -556,6 +563,75 @@ static void or_step1(or_state *s) {
 
 void or_step(or_state *s, long n) {
   for (long k = 0; k < n; ++k) or_step1(s);
+}
+
+/* Consistent initialisation after Mei et al. (2006), as cited in Sec. 2.3:
+ * n pre-iterations of f with the velocity held at u0 (layout [3][N], NULL =
+ * 0) and phi held at phi0 (N values), both on the fluid domain; rho = sum f
+ * evolves.  Each pre-iteration takes the step's own moments, potentials and
+ * force (eqs. densMoment, mu_rho, mu_phi, F) on (rho, phi0), then collides f
+ * towards f^eq(rho, u0) with the Guo term S(u0, F) and streams it with the
+ * moving bounce-back (eqs. bgk, feq, Fi; Sec. 2.3).  g is left alone during
+ * the iterations and is then set to g^eq(phi0, mu_phi(rho, phi0), u0)
+ * (eq. geq).  Returns -1 if called after the first step. */
+int or_consistent_init(or_state *s, const double *phi0, const double *u0, long n) {
+  if (s->t != 0) return -1;
+  int q = s->q, kind = s->p.kind;
+  const int(*c)[3] = or_c(kind);
+  const double *w = or_w(kind);
+  double tf = s->p.tau_f;
+  long N = (long)s->p.nx * s->p.ny * s->p.nz;
+  double *ph0 = (double *)or_zalloc(s->ncell * sizeof(double));
+  double *U[3];
+  for (int a = 0; a < 3; ++a) U[a] = (double *)or_zalloc(s->ncell * sizeof(double));
+  for (long u = 0; u < N; ++u) {
+    long e = or_user_to_ext(s, u);
+    ph0[e] = phi0[u];
+    if (u0)
+      for (int a = 0; a < 3; ++a) U[a][e] = u0[(long)a * N + u];
+  }
+  for (long k = 0; k < n; ++k) {
+    or_moments(s);
+    for (long x = 0; x < s->ncell; ++x)
+      if (s->kind[x] == OR_FLUID) s->phi[x] = ph0[x];
+    or_potentials(s);
+    or_force_velocity(s);
+#pragma omp parallel for schedule(static)
+    for (long x = 0; x < s->ncell; ++x) {
+      if (s->kind[x] != OR_FLUID) continue;
+      double u[3] = {U[0][x], U[1][x], U[2][x]};
+      double F[3] = {s->Fx[x], s->Fy[x], s->Fz[x]};
+      double feq[OR_MAXQ], S[OR_MAXQ];
+      or_feq(kind, s->rho[x], u, feq);
+      or_guo(kind, tf, u, F, S);
+      for (int i = 0; i < q; ++i) {
+        double fs = s->f[x * q + i] - (s->f[x * q + i] - feq[i]) / tf + S[i];
+        long y = or_nb(s, x, i);
+        if (y >= 0 && s->kind[y] == OR_FLUID) {
+          s->fn[y * q + i] = fs;
+        } else {
+          double uw[3];
+          or_body_velocity(s, x, y, i, uw);
+          double cu = c[i][0] * uw[0] + c[i][1] * uw[1] + c[i][2] * uw[2];
+          s->fn[x * q + or_opp(i)] = fs - 2.0 * w[i] * s->rho[x] * cu / CS2;
+        }
+      }
+    }
+    double *t1 = s->f; s->f = s->fn; s->fn = t1;
+  }
+  or_moments(s);
+  for (long x = 0; x < s->ncell; ++x)
+    if (s->kind[x] == OR_FLUID) s->phi[x] = ph0[x];
+  or_potentials(s);
+  double G = or_gamma(s);
+  for (long x = 0; x < s->ncell; ++x) {
+    if (s->kind[x] != OR_FLUID) continue;
+    double u[3] = {U[0][x], U[1][x], U[2][x]};
+    or_geq(kind, ph0[x], s->mup[x], G, u, &s->g[x * q]);
+  }
+  free(ph0);
+  for (int a = 0; a < 3; ++a) free(U[a]);
+  return 0;
 }
 
 long or_time(const or_state *s) { return s->t; }

@@ -77,6 +77,8 @@ def lib():
         L.or_create_geometry.argtypes = [C.POINTER(Params), C.c_void_p]
         L.or_destroy.argtypes = [C.c_void_p]
         L.or_step.argtypes = [C.c_void_p, C.c_long]
+        L.or_consistent_init.argtypes = [C.c_void_p, dp, C.c_void_p, C.c_long]
+        L.or_consistent_init.restype = C.c_int
         L.or_time.argtypes = [C.c_void_p]
         L.or_time.restype = C.c_long
         L.or_observe.argtypes = [C.c_void_p, dp]
@@ -207,6 +209,16 @@ class Lattice:
 
     def step(self, n: int = 1):
         lib().or_step(self._h, int(n))
+        return self
+
+    def consistent_init(self, phi0, u0=None, n: int = 100):
+        """n pre-iterations of f with u held at u0 and phi at phi0, then g
+        reset to its equilibrium (Sec. 2.3, after Mei et al. 2006)."""
+        phi0 = np.ascontiguousarray(np.asarray(phi0, dtype=np.float64).reshape(-1))
+        u0 = None if u0 is None else np.ascontiguousarray(np.asarray(u0, np.float64).reshape(-1))
+        r = lib().or_consistent_init(self._h, _dp(phi0), None if u0 is None else u0.ctypes.data, int(n))
+        if r != 0:
+            raise ValueError("consistent initialisation is only possible before the first step")
         return self
 
     def observe(self) -> dict:

@@ -15,7 +15,8 @@ ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
 SRC = os.path.join(ROOT, "oracle", "frelbm_oracle.c")
 PINS = ["tests/test_oracle_node.py", "tests/test_oracle_stencils.py", "tests/test_oracle_brute.py",
         "tests/test_oracle_physics.py::test_p7_couette",
-        "tests/test_oracle_physics.py::test_p4_conservation_moving_walls"]
+        "tests/test_oracle_physics.py::test_p4_conservation_moving_walls",
+        "tests/test_oracle_consistent_init.py"]
 
 # (name, text in the source, replacement, which occurrence)
 MUTANTS = [
@@ -34,6 +35,9 @@ MUTANTS = [
     ("moving-wall bounce-back sign", "fs - 2.0 * w[i] * s->rho[x] * cu / CS2",
      "fs + 2.0 * w[i] * s->rho[x] * cu / CS2", 0),
     ("solid fill without lattice weights", "num += w[i] * X[n];", "num += X[n];", 0),
+    ("pre-iterations without the Guo term", "- feq[i]) / tf + S[i];", "- feq[i]) / tf + 0.0 * S[i];", 1),
+    ("g not reset after the pre-iterations", "or_geq(kind, ph0[x], s->mup[x], G, u, &s->g[x * q]);",
+     "(void)G;", 0),
 ]
 
 
