@@ -126,6 +126,22 @@ fre_status fre_lattice_init(const fre_params *p, void *device_buf, size_t bytes,
                             const double *rho0, const double *u0,
                             const uint8_t *solid_mask, fre_lattice **out);
 
+/* Consistent initialisation (Sec. 2.3, which starts from equilibrium and
+ * aligns the kinetic moments by collisions, citing Mei, Luo, Lallemand and
+ * d'Humieres 2006): n pre-iterations of the f population in which the
+ * velocity of the equilibrium and of the Guo forcing term is held at u0 and
+ * the order parameter at phi0, while rho = sum f evolves (the pressure field
+ * and the non-equilibrium part of f develop); g is not stepped.  Then g is set
+ * to g^eq(phi0, mu_phi(rho, phi0), u0) and the moments are recomputed.  The
+ * time counter stays at 0.
+ *  phi0: N doubles, u0: 3N doubles ([3][N]) or NULL (= 0), on the fluid
+ *  domain, x fastest, as for fre_lattice_init (normally the same fields).
+ *  n: number of pre-iterations, even and >= 0 (0 resets g only).
+ * FRE_EINVAL for odd or negative n, NULL phi0 or non-finite values;
+ * FRE_ESTATE after the first step, for a batch member or a failed lattice.
+ * Synchronises the stream before returning. */
+fre_status fre_consistent_init(fre_lattice *L, const double *phi0, const double *u0, int64_t n);
+
 /* Replace the physical parameters (free energy, tau, M, wall and roller
  * velocities) of an existing lattice; shape, storage and bc must not change.
  * Takes effect for the next step. */

@@ -405,6 +405,40 @@ fre_status fre_lattice_init(const fre_params *p, void *device_buf, size_t bytes,
   return FRE_OK;
 }
 
+fre_status fre_consistent_init(fre_lattice *L, const double *phi0, const double *u0, int64_t n) {
+  if (!L) return fail(FRE_EINVAL, "lattice is NULL");
+  if (!phi0) return fail(FRE_EINVAL, "phi0 is NULL");
+  if (n < 0 || (n & 1)) return fail(FRE_EINVAL, "the number of pre-iterations must be even and >= 0 (got %lld)",
+                                    (long long)n);
+  if (L->state) return fail(FRE_ESTATE, "lattice is in the failed state");
+  if (L->batch) return fail(FRE_ESTATE, "lattice is a batch member: remove it first");
+  if (L->t != 0) return fail(FRE_ESTATE, "consistent initialisation is only possible before the first step");
+  const fre_params *p = &L->p;
+  const Plan &P = L->plan;
+  const long long N = L->n_user;
+  for (long long u = 0; u < N; ++u)
+    if (!std::isfinite(phi0[u]) ||
+        (u0 && !(std::isfinite(u0[u]) && std::isfinite(u0[N + u]) && std::isfinite(u0[2 * N + u]))))
+      return fail(FRE_EINVAL, "non-finite value at cell %lld", u);
+  // AUX = (u0, phi0) in storage layout
+  std::vector<float> U((size_t)P.ncell * 4, 0.0f);
+  for (int z = 0; z < p->nz; ++z)
+    for (int y = 0; y < p->ny; ++y)
+      for (int x = 0; x < p->nx; ++x) {
+        const long long u = x + (long long)p->nx * (y + (long long)p->ny * z);
+        const long long e = ext_index(P, x, y, z);
+        if (u0)
+          for (int k = 0; k < 3; ++k) U[4 * e + k] = (float)u0[(long long)k * N + u];
+        U[4 * e + 3] = (float)phi0[u];
+      }
+  hipStream_t st = L->a.stream;
+  HIP_TRY(hipMemcpyAsync(L->a.AUX, U.data(), U.size() * 4, hipMemcpyHostToDevice, st));
+  launch_consistent_init(L->a, (long long)n);
+  HIP_TRY(hipGetLastError());
+  HIP_TRY(hipStreamSynchronize(st));
+  return FRE_OK;
+}
+
 fre_status fre_set_params(fre_lattice *L, const fre_params *p) {
   if (!L) return fail(FRE_EINVAL, "lattice is NULL");
   fre_status s = validate(p);

@@ -65,6 +65,7 @@ template <int Q, int S> struct LatView {
   float *MUP;
   float2 *P0, *PU, *PD;
   float2 *XE;
+  const float4 *AUX;  // (u0, phi0) during the consistent initialisation
   Geom G;
   Phys ph;
   const int *fill;
@@ -119,6 +120,9 @@ void launch_moments(const LaunchArgs &a, int odd);
 bool uses_by_product(const LaunchArgs &a);
 void launch_observe(const LaunchArgs &a, int odd);
 void launch_init(const LaunchArgs &a);
+// n (even) pre-iterations of f with u held at AUX.xyz and phi at AUX.w, then
+// g reset to its equilibrium and M recomputed (consistent initialisation).
+void launch_consistent_init(const LaunchArgs &a, long long n);
 void launch_read_pops(const LaunchArgs &a, int odd, float *out);
 int reduce_blocks();
 void launch_reduce(const LaunchArgs &a, double *part);

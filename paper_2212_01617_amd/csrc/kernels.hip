@@ -557,7 +557,7 @@ __device__ __forceinline__ void collide_cell(const Pops<Q, S> &P, const Nbr &N, 
 // i) after an even step, (x, opp(i)) after an odd one.  Only cells next to
 // a solid take this path; keeping it after the branch-free main loop (rather
 // than a branch per direction inside it) holds the register count down.
-template <int Q, int S, int ODD>
+template <int Q, int S, int ODD, bool WITH_G = true>
 __device__ __forceinline__ void bounce_back(const Pops<Q, S> &P, const Nbr &N, long long c, uint32_t bits,
                                          const uint8_t *__restrict__ mask, const Geom &G, const Phys &ph,
                                          int x, int y, int z, float rho, float phi) {
@@ -568,7 +568,7 @@ __device__ __forceinline__ void bounce_back(const Pops<Q, S> &P, const Nbr &N, l
     const long long n = N.template at<V>(i);
     const int sp = ODD ? i : opp(i);
     const long long sc = ODD ? n : c;
-    const float fs = P.ldf(sp, sc), gs = P.ldg(sp, sc);
+    const float fs = P.ldf(sp, sc), gs = WITH_G ? P.ldg(sp, sc) : 0.0f;
     const int xs = wrap(x + V::cx(i), G.ex), ys = wrap(y + V::cy(i), G.ey);
     const int zs = V::D == 3 ? wrap(z + V::cz(i), G.ez) : z;
     float uw[3];
@@ -578,7 +578,7 @@ __device__ __forceinline__ void bounce_back(const Pops<Q, S> &P, const Nbr &N, l
     const int bp = ODD ? opp(i) : i;
     const long long bc = ODD ? c : n;
     P.stf(bp, bc, fb);
-    P.stg(bp, bc, gb);
+    if (WITH_G) P.stg(bp, bc, gb);
   }
 }
 
@@ -663,13 +663,73 @@ __device__ __forceinline__ void stage_collide(const LatView<Q, S> &L, int x, int
 // ---------------------------------------------------------------------------
 // Stage ids; the first three double as indices of the launch shapes (the
 // moments pass, k_moments or k_combine, shares shape 0).
-enum Stage { ST_MOMENTS = SHAPE_MOMENTS, ST_POTENTIAL = SHAPE_POTENTIAL, ST_COLLIDE = SHAPE_COLLIDE, ST_COMBINE = 3 };
+enum Stage {
+  ST_MOMENTS = SHAPE_MOMENTS, ST_POTENTIAL = SHAPE_POTENTIAL, ST_COLLIDE = SHAPE_COLLIDE, ST_COMBINE = 3,
+  ST_PRE_MOMENTS = 4, ST_PRE_COLLIDE = 5  // consistent initialisation
+};
+
+// ---------------------------------------------------------------------------
+// Consistent initialisation (Sec. 2.3, after Mei et al. 2006): pre-iterations
+// of f in which the velocity of the equilibrium and of the Guo term is held
+// at the prescribed u0 and phi at phi0 (both in AUX = (u0, phi0)), while
+// rho = sum f evolves; g is not stepped.  The potential and force stages of
+// the step are reused on M = (rho - 1, phi0).
+// ---------------------------------------------------------------------------
+template <int Q, int S, int ODD>
+__device__ __forceinline__ void stage_pre_moments(const LatView<Q, S> &L, int x, int y, int z) {
+  using V = VSet<Q>;
+  const long long c = (long long)x + (long long)L.G.px * ((long long)y + (long long)L.G.ey * z);
+  if (L.nbm[c] & NB_SELF_SOLID) return;
+  const Nbr N(L.G, x, y, z);
+  float drho = 0.0f;
+#pragma unroll
+  for (int i = 0; i < Q; ++i) drho += (!ODD || i == 0) ? L.P.ldf(i, c) : L.P.ldf(opp(i), N.template back<V>(i));
+  L.M[c] = make_float2(drho, L.AUX[c].w);
+}
+
+template <int Q, int S, int ODD>
+__device__ __forceinline__ void stage_pre_collide(const LatView<Q, S> &L, int x, int y, int z) {
+  using V = VSet<Q>;
+  const long long c = (long long)x + (long long)L.G.px * ((long long)y + (long long)L.G.ey * z);
+  const uint32_t bits = L.nbm[c];
+  if (bits & NB_SELF_SOLID) return;
+  const Nbr N(L.G, x, y, z);
+  const float mu_rho = L.C[c].w, mu_phi = L.MUP[c];
+  float F[3];
+  force<Q>(L.C, N, mu_rho, mu_phi, F);
+  float df[Q];
+#pragma unroll
+  for (int i = 0; i < Q; ++i) df[i] = (!ODD || i == 0) ? L.P.ldf(i, c) : L.P.ldf(opp(i), N.template back<V>(i));
+  float drho = 0.0f;
+#pragma unroll
+  for (int i = 0; i < Q; ++i) drho += df[i];
+  const float rho = 1.0f + drho;
+  const float4 a = L.AUX[c];
+  const float u[3] = {a.x, a.y, a.z};
+  const float uu = u[0] * u[0] + u[1] * u[1] + u[2] * u[2];
+  const float uF = u[0] * F[0] + u[1] * F[1] + u[2] * F[2];
+#pragma unroll
+  for (int i = 0; i < Q; ++i) {
+    const float cu = V::cx(i) * u[0] + V::cy(i) * u[1] + V::cz(i) * u[2];
+    const float cF = V::cx(i) * F[0] + V::cy(i) * F[1] + V::cz(i) * F[2];
+    const float wi = V::w(i);
+    const float poly = 3.0f * cu + 4.5f * cu * cu - 1.5f * uu;
+    const float dfeq = wi * (drho + rho * poly);
+    const float src = L.ph.guo * wi * (3.0f * (cF - uF) + 9.0f * cu * cF);
+    const float fs = L.P.round(df[i] + L.ph.om_f * (dfeq - df[i]) + src);
+    if (!ODD) L.P.stf(opp(i), c, fs);
+    else L.P.stf(i, N.template at<V>(i), fs);
+  }
+  if (bits != 0u) bounce_back<Q, S, ODD, false>(L.P, N, c, bits, L.mask, L.G, L.ph, x, y, z, rho, 0.0f);
+}
 
 // Per-cell stages other than collide (ODD: parity of the state they read).
 template <int Q, int S, int STAGE, int ODD>
 __device__ __forceinline__ void run_stage(const LatView<Q, S> &L, int x, int y, int z) {
-  if (STAGE == ST_MOMENTS) stage_moments<Q, S, ODD>(L, x, y, z);
-  else if (STAGE == ST_COMBINE) stage_combine<Q, S, ODD>(L, x, y, z);
+  if constexpr (STAGE == ST_MOMENTS) stage_moments<Q, S, ODD>(L, x, y, z);
+  else if constexpr (STAGE == ST_COMBINE) stage_combine<Q, S, ODD>(L, x, y, z);
+  else if constexpr (STAGE == ST_PRE_MOMENTS) stage_pre_moments<Q, S, ODD>(L, x, y, z);
+  else if constexpr (STAGE == ST_PRE_COLLIDE) stage_pre_collide<Q, S, ODD>(L, x, y, z);
   else stage_potential<Q, S>(L, x, y, z);
 }
 
@@ -772,6 +832,7 @@ __device__ __forceinline__ LatView<Q, S> view_of(char *base, const Inst &I) {
   L.M = (float2 *)(base + I.M); L.C = (float4 *)(base + I.C); L.MUP = (float *)(base + I.MUP);
   L.P0 = (float2 *)(base + I.P0); L.PU = (float2 *)(base + I.PU); L.PD = (float2 *)(base + I.PD);
   L.XE = (float2 *)(base + I.XE);
+  L.AUX = nullptr;
   L.G = I.G; L.ph = I.ph; L.fill = (const int *)(base + I.fill); L.n_fill = I.n_fill;
   L.xcd = 0;
   return L;
@@ -838,6 +899,33 @@ __global__ __launch_bounds__(BX *BY) void k_init(Pops<Q, S> P, const uint32_t *_
       rest += geq;
       P.stg(i, c, geq);
     }
+  }
+  P.stg(0, c, phi - rest);
+}
+
+// g at its equilibrium g^eq(phi0, mu_phi, u0) (eq. geq; g_0 by complement),
+// parity-0 slots, with AUX = (u0, phi0) and MUP = mu_phi current.
+template <int Q, int S>
+__global__ __launch_bounds__(BX *BY) void k_reinit_g(Pops<Q, S> P, const uint32_t *__restrict__ nbm,
+                                                     const float *__restrict__ MUP,
+                                                     const float4 *__restrict__ AUX, Geom G, Phys ph) {
+  using V = VSet<Q>;
+  int x, y, z;
+  long long c;
+  if (!cell_of_thread(G, x, y, z, c)) return;
+  if (nbm[c] & NB_SELF_SOLID) return;
+  const float4 a = AUX[c];
+  const float u[3] = {a.x, a.y, a.z};
+  const float uu = u[0] * u[0] + u[1] * u[1] + u[2] * u[2];
+  const float phi = a.w, mp = MUP[c];
+  float rest = 0.0f;
+#pragma unroll
+  for (int i = 1; i < Q; ++i) {
+    const float cu = V::cx(i) * u[0] + V::cy(i) * u[1] + V::cz(i) * u[2];
+    const float poly = 3.0f * cu + 4.5f * cu * cu - 1.5f * uu;
+    const float geq = V::w(i) * (ph.gam3 * mp + phi * poly);
+    rest += geq;
+    P.stg(i, c, geq);
   }
   P.stg(0, c, phi - rest);
 }
@@ -959,7 +1047,7 @@ static LatView<Q, S> view_of_args(const LaunchArgs &a) {
   LatView<Q, S> L;
   L.P = make_pops<Q, S>(a);
   L.nbm = a.nbm; L.mask = a.mask; L.M = a.M; L.C = a.C; L.MUP = a.MUP;
-  L.P0 = a.P0; L.PU = a.PU; L.PD = a.PD; L.XE = a.XE;
+  L.P0 = a.P0; L.PU = a.PU; L.PD = a.PD; L.XE = a.XE; L.AUX = a.AUX;
   L.G = a.G; L.ph = a.ph; L.fill = a.fill_list; L.n_fill = a.n_fill;
   L.xcd = 1;
   return L;
@@ -971,7 +1059,7 @@ static LatView<Q, S> view_of_args(const LaunchArgs &a) {
 template <int Q, int S, int STAGE>
 static void cells_launch(const LaunchArgs &a, int odd) {
   LatView<Q, S> L = view_of_args<Q, S>(a);
-  const Shape sh = a.shape[STAGE == ST_COMBINE ? SHAPE_MOMENTS : STAGE];
+  const Shape sh = a.shape[STAGE <= ST_COLLIDE ? STAGE : SHAPE_MOMENTS];
   const int rows = (STAGE == ST_COLLIDE && ByProduct<S>::on) ? COLLIDE_ROWS : sh.rows;
   L.xcd = sh.xcd;
   const dim3 grid = tile_grid(a.G, rows), block(BX, rows, 1);
@@ -1057,6 +1145,22 @@ static void init_impl(const LaunchArgs &a) {
 }
 
 template <int Q, int S>
+static void consistent_init_impl(const LaunchArgs &a, long long n) {
+  int k = 0;
+  for (long long it = 0; it < n; ++it) {
+    const int odd = (int)(it & 1);
+    cells_launch<Q, S, ST_PRE_MOMENTS>(a, odd);
+    couple_seq<Q, S>(a, nullptr, k);
+    cells_launch<Q, S, ST_PRE_COLLIDE>(a, odd);
+  }
+  // mu_phi of the new rho with phi0, then g^eq(phi0, mu_phi, u0) and M
+  cells_launch<Q, S, ST_PRE_MOMENTS>(a, 0);
+  couple_seq<Q, S>(a, nullptr, k);
+  k_reinit_g<Q, S><<<cell_grid(a.G), cell_block(), 0, a.stream>>>(make_pops<Q, S>(a), a.nbm, a.MUP, a.AUX, a.G, a.ph);
+  moments_launch<Q, S>(a, 0);
+}
+
+template <int Q, int S>
 static void read_pops_impl(const LaunchArgs &a, int odd, float *out) {
   k_read_pops<Q, S><<<cell_grid(a.G), cell_block(), 0, a.stream>>>(make_pops<Q, S>(a), a.nbm, out, a.G, odd);
 }
@@ -1085,6 +1189,7 @@ const char *step_kernel_name(int k) {
   return (k >= 0 && k < 6) ? names[k] : nullptr;
 }
 void launch_moments(const LaunchArgs &a, int odd) { FRE_DISPATCH(moments_launch, a, odd); }
+void launch_consistent_init(const LaunchArgs &a, long long n) { FRE_DISPATCH(consistent_init_impl, a, n); }
 bool uses_by_product(const LaunchArgs &a) { return a.storage == 0; }
 void launch_observe(const LaunchArgs &a, int odd) { FRE_DISPATCH(observe_impl, a, odd); }
 void launch_init(const LaunchArgs &a) { FRE_DISPATCH(init_impl, a); }

@@ -58,6 +58,7 @@ _SIGS = [
                                      C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p,
                                      C.POINTER(C.c_void_p)]),
     ("fre_set_params", C.c_int32, [C.c_void_p, C.POINTER(fre_params)]),
+    ("fre_consistent_init", C.c_int32, [C.c_void_p, C.c_void_p, C.c_void_p, C.c_int64]),
     ("fre_step", C.c_int32, [C.c_void_p, C.c_int64]),
     ("fre_read_moments", C.c_int32, [C.c_void_p, C.c_uint32, C.c_void_p, C.c_size_t]),
     ("fre_read_populations", C.c_int32, [C.c_void_p, C.c_void_p, C.c_void_p, C.c_size_t]),
@@ -200,6 +201,16 @@ class Lattice:
     @property
     def handle(self):
         return self._h
+
+    def consistent_init(self, phi0, u0=None, n: int = 100):
+        """n (even) pre-iterations of f with u held at u0 and phi at phi0,
+        then g reset to its equilibrium; only before the first step."""
+        phi0 = np.ascontiguousarray(np.asarray(phi0, np.float64).reshape(-1))
+        u0 = None if u0 is None else np.ascontiguousarray(np.asarray(u0, np.float64).reshape(-1))
+        if phi0.size != self.N or (u0 is not None and u0.size != 3 * self.N):
+            raise ValueError("phi0 needs N values and u0 3N")
+        _check(lib().fre_consistent_init(self._h, _ptr(phi0), None if u0 is None else _ptr(u0), int(n)))
+        return self
 
     def step(self, n=1):
         _check(lib().fre_step(self._h, int(n)))

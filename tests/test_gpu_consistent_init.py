@@ -1,0 +1,105 @@
+"""Parity of the consistent initialisation (pre-iterations of f with u held at
+u0 and phi at phi0, then g reset to equilibrium; Sec. 2.3 after Mei et al.
+2006) between the GPU path, through the C ABI, and the FP64 oracle: every
+field and population right after the pre-iterations and again after normal
+steps from that state.  Error paths: odd counts, a lattice already stepped,
+a batch member."""
+import numpy as np
+import pytest
+import torch
+
+from oracle import oracle as O
+from paper_2212_01617_amd import frelbm as F
+
+from _pair import case_inputs, ensure_gpu_lib, field_errors, log, pop_errors
+
+pytestmark = pytest.mark.gpu
+
+TOL = {"rho": 1e-5, "phi": 1e-5, "u": 1e-5, "mu_rho": 1e-6, "mu_phi": 1e-6, "P": 1e-6}
+
+
+@pytest.fixture(scope="module", autouse=True)
+def _lib():
+    assert torch.cuda.is_available(), "GPU tests need a GPU"
+    ensure_gpu_lib()
+
+
+def _pair(kind, shape, n_pre, *, phi0, u0=None, rho0=None, mask=None, bc=(0, 0, 0), wall_u=None,
+          rollers=(), storage=0, **phys):
+    po = O.make_params(kind, shape, bc=bc, wall_u=wall_u, rollers=[(r[0], r[1], r[2]) for r in rollers], **phys)
+    ref = O.Lattice(po, phi0, rho0, u0, mask).consistent_init(phi0, u0, n_pre)
+    pg = F.make_params(kind, shape, storage=storage, bc=bc, wall_u=wall_u, rollers=rollers, **phys)
+    gpu = F.Lattice(pg, phi0, rho0, u0, mask, stream=torch.cuda.Stream()).consistent_init(phi0, u0, n_pre)
+    return ref, gpu
+
+
+def _check(name, ref, gpu, tol=TOL, pop_tol=1e-5):
+    err = field_errors(ref, gpu)
+    pf, pg = pop_errors(ref, gpu)
+    log(f"[parity] {name}: " + " ".join(f"{k}={v:.2e}" for k, v in err.items()) + f" f={pf:.2e} g={pg:.2e}")
+    for k, v in tol.items():
+        assert err[k] < v, (name, k, err[k])
+    assert pf < pop_tol and pg < pop_tol, (name, pf, pg)
+
+
+def test_static_drop_d2q9_then_steps():
+    shape = (64, 48, 1)
+    phi0, _, _ = case_inputs(0, shape, radius=12, xi=1.5, noise=1e-4, seed=0)
+    ref, gpu = _pair(0, shape, 300, phi0=phi0, A=0.04, kappa=0.09, tau_f=1.0, tau_g=1.0, M=0.1)
+    assert gpu.info()[0] == 0
+    _check("consistent_init_drop_d2q9", ref, gpu)
+    ref.step(101)
+    gpu.step(101)
+    _check("consistent_init_drop_d2q9_101", ref, gpu)
+
+
+def test_shear_d3q19_walls_ragged_then_steps():
+    # x spans two 64-wide blocks with a ragged tail; walls in z moving
+    shape = (70, 9, 12)
+    uw = 0.017
+    wu = np.zeros((3, 2, 3)); wu[2, 0, 0] = -uw; wu[2, 1, 0] = uw
+    phi0, rho0, u0 = case_inputs(1, shape, radius=4, xi=2.0, shear=(2 * uw / 12, 2), center=(30.0, 4.0, 5.5))
+    ref, gpu = _pair(1, shape, 120, phi0=phi0, u0=u0, bc=(0, 0, 1), wall_u=wu,
+                     A=5.89e-3, kappa=2.36e-2, tau_f=1.0, tau_g=1.75, M=5.26)
+    _check("consistent_init_shear_d3q19", ref, gpu)
+    ref.step(60)
+    gpu.step(60)
+    _check("consistent_init_shear_d3q19_60", ref, gpu)
+
+
+def test_zero_pre_iterations_resets_g_only():
+    shape = (40, 24, 1)
+    phi0, rho0, u0 = case_inputs(0, shape, radius=8, xi=1.5, rho_amp=0.01, u_amp=0.005, seed=2)
+    ref, gpu = _pair(0, shape, 0, phi0=phi0, rho0=rho0, u0=u0, A=0.04, kappa=0.09, tau_f=0.9, tau_g=1.1, M=0.1)
+    _check("consistent_init_zero", ref, gpu)
+
+
+def test_fp16_storage_error_stated():
+    shape = (64, 48, 1)
+    phi0, _, _ = case_inputs(0, shape, radius=12, xi=1.5, noise=1e-4, seed=0)
+    ref, gpu = _pair(0, shape, 200, phi0=phi0, storage=1, A=0.04, kappa=0.09, tau_f=1.0, tau_g=1.0, M=0.1)
+    err = field_errors(ref, gpu)
+    log("[parity] consistent_init_fp16: " + " ".join(f"{k}={v:.2e}" for k, v in err.items()))
+    assert err["phi"] < 5e-3 and err["u"] < 5e-4 and err["rho"] < 5e-4
+
+
+def test_error_paths():
+    shape = (16, 8, 1)
+    phi0, _, _ = case_inputs(0, shape, radius=3, xi=1.5)
+    p = F.make_params(0, shape, A=0.04, kappa=0.09)
+    L = F.Lattice(p, phi0)
+    with pytest.raises(F.FreError) as e:
+        L.consistent_init(phi0, None, 3)          # odd count
+    assert e.value.status == F.FRE_EINVAL
+    L.step(1)
+    with pytest.raises(F.FreError) as e:
+        L.consistent_init(phi0, None, 2)          # already stepped
+    assert e.value.status == F.FRE_ESTATE
+    L2 = F.Lattice(p, phi0)
+    w, f = F.Batch.needs(L2)
+    B = F.Batch(max_slots=2, max_work=w, max_fill=f)
+    B.add(L2)
+    with pytest.raises(F.FreError) as e:
+        L2.consistent_init(phi0, None, 2)         # batch member
+    assert e.value.status == F.FRE_ESTATE
+    B.close()
