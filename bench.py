@@ -130,6 +130,30 @@ def large_lattice(steps: int = 100) -> dict:
     return out
 
 
+def consistent_init_rate(n: int = 400) -> dict:
+    """Throughput of the consistent initialisation's pre-iterations on the
+    256x128x128 workload (FP32): n pre-iterations timed against zero, so the
+    host upload of (u0, phi0) and the final g reset cancel out."""
+    import torch
+    from paper_2212_01617_amd import frelbm as F
+    p, phi0, u0, _ = workload(0)
+    L = F.Lattice(p, phi0, None, u0, stream=torch.cuda.Stream())
+    L.autotune(5)
+    t = {}
+    for k in (0, n, 0, n):
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        L.consistent_init(phi0, u0, k)   # synchronises
+        t.setdefault(k, []).append(time.perf_counter() - t0)
+    L.close()
+    ms = (min(t[n]) - min(t[0])) / n * 1e3
+    cells = 256 * 128 * 128
+    mlups = cells / (ms * 1e-3) / 1e6
+    return {"value": round(mlups, 1), "unit": "MLUPS", "ms_per_iteration": round(ms, 5),
+            "bytes_per_lu": 152, "frac": round(mlups * 1e6 * 152 / 1e9 / PEAK_HBM_GBS, 4),
+            "sample": f"{n} pre-iterations minus 0, best of 2, FP32, 256x128x128"}
+
+
 def cpu_baseline(p_gpu, phi0, u0, meta, steps=60):
     from oracle import oracle as O
     nx, ny, nz = meta["shape"]
@@ -242,6 +266,7 @@ def main():
     res.clear()
     if not args.no_large:
         out["large_lattice"] = large_lattice()
+    out["consistent_init"] = consistent_init_rate()
     if args.serve:
         out["serving"] = serving(args.serve)
     if not args.no_cpu_baseline:
