@@ -23,9 +23,9 @@ from . import serve
 
 
 def sweep_requests(cas, *, kind: int = 0, n: int = 150, Re: float = 0.0625, xi: float = 1.5,
-                   storage: int = 0) -> list:
+                   storage: int = 0, Pe: float | None = None) -> list:
     """One shear request per capillary number, all arriving at t = 0."""
-    return [serve.Request(k, 0.0, kind, int(n), "shear", storage, float(ca), float(Re), float(xi))
+    return [serve.Request(k, 0.0, kind, int(n), "shear", storage, float(ca), float(Re), float(xi), Pe)
             for k, ca in enumerate(cas)]
 
 
@@ -53,12 +53,12 @@ class _Logged:
 
 def breakup_sweep(cas, *, kind: int = 0, n: int = 150, Re: float = 0.0625, xi: float = 1.5,
                   storage: int = 0, strain_cap: float = 30.0, budget_bytes: int = 8 << 30,
-                  engine=None, log=None) -> list[dict]:
+                  engine=None, log=None, Pe: float | None = None) -> list[dict]:
     """Serve the sweep and return one row per capillary number: the reason
     it retired ("breakup", "steady", "cap", ...), the strain reached and the
     last Taylor deformation D sampled before retirement.  `log`, if given,
     receives progress lines."""
-    reqs = sweep_requests(cas, kind=kind, n=n, Re=Re, xi=xi, storage=storage)
+    reqs = sweep_requests(cas, kind=kind, n=n, Re=Re, xi=xi, storage=storage, Pe=Pe)
     own = engine is None
     eng = serve.GpuEngine(budget_bytes, max_members=len(reqs)) if own else engine
     srv = serve.Server(_Logged(eng, log) if log else eng, budget_bytes, max_members=len(reqs), chunk=4000,
@@ -90,13 +90,14 @@ def main(argv=None):
     ap.add_argument("--cas", default="0.5,0.7,1.0,1.5,2.0")
     ap.add_argument("--cap", type=float, default=30.0, help="strain cap")
     ap.add_argument("--storage", type=int, default=0)
+    ap.add_argument("--Pe", type=float, default=serve.SERVE_PE)
     a = ap.parse_args(argv)
     rows = breakup_sweep([float(c) for c in a.cas.split(",")], kind=a.kind, n=a.n, Re=a.Re, xi=a.xi,
-                         storage=a.storage, strain_cap=a.cap,
+                         storage=a.storage, strain_cap=a.cap, Pe=a.Pe,
                          log=lambda line: print(line, file=sys.stderr, flush=True))
     lo, hi = critical_range(rows)
     print(json.dumps({"kind": a.kind, "n": a.n, "radius": 0.2 * a.n, "Re": a.Re, "xi": a.xi,
-                      "Pe": serve.SERVE_PE, "runs": rows, "critical_Ca_between": [lo, hi]}), flush=True)
+                      "Pe": a.Pe, "runs": rows, "critical_Ca_between": [lo, hi]}), flush=True)
 
 
 if __name__ == "__main__":

@@ -49,6 +49,7 @@ class Request:
     Ca: float
     Re: float
     xi: float = 2.0
+    Pe: float | None = None  # Peclet number; None: SERVE_PE
 
     @property
     def radius(self) -> float:
@@ -271,16 +272,18 @@ SERVE_PE = 10.0
 def lattice_inputs(req: Request):
     """Parameters and initial fields of a request (shear: walls normal to the
     last axis moving at -+u_w with the linear shear profile; rollers: four
-    cylinders along z, all axes periodic), Peclet number SERVE_PE."""
+    cylinders along z, all axes periodic), Peclet number req.Pe (default
+    SERVE_PE)."""
     from . import frelbm as F
     from .params import derive_params
     nx, ny, nz = req.shape
     sh = (nz, ny, nx)
     R = req.radius
+    Pe = SERVE_PE if req.Pe is None else req.Pe
     if req.flow == "shear":
         wall_axis = 1 if req.kind == 0 else 2
         H = (ny, nz)[wall_axis - 1]
-        dp = derive_params(Re=req.Re, Ca=req.Ca, radius=R, xi=req.xi, H=H, Pe=SERVE_PE)
+        dp = derive_params(Re=req.Re, Ca=req.Ca, radius=R, xi=req.xi, H=H, Pe=Pe)
         wu = np.zeros((3, 2, 3))
         wu[wall_axis, 0, 0] = -dp.wall_u
         wu[wall_axis, 1, 0] = dp.wall_u
@@ -293,7 +296,7 @@ def lattice_inputs(req: Request):
     # four rollers: tip speed eps * d with d the gap from the domain centre to
     # the roller surface (the stagnation flow u = eps (x, -y) there);
     # uncalibrated against a single-phase run
-    dp = derive_params(Re=req.Re, Ca=req.Ca, radius=R, xi=req.xi, Pe=SERVE_PE)
+    dp = derive_params(Re=req.Re, Ca=req.Ca, radius=R, xi=req.xi, Pe=Pe)
     rr = 0.117 * nx
     cs, signs = synth.four_roller_geometry(nx, ny, rr, nz=nz)
     d = math.hypot(nx / 4.0, ny / 4.0) - rr
