@@ -196,7 +196,9 @@ class Lattice:
         self.buf = None
 
     def __del__(self):
-        self.close()
+        # at interpreter exit the module's globals may already be gone
+        if lib is not None:
+            self.close()
 
     @property
     def handle(self):
@@ -359,4 +361,6 @@ class Batch:
             self.members = {}
 
     def __del__(self):
-        self.close()
+        # at interpreter exit the module's globals may already be gone
+        if lib is not None:
+            self.close()

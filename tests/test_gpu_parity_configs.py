@@ -65,8 +65,10 @@ def test_static_drop_100x100_full_run():
 
 def test_parallel_band_shear_400x200():
     """300 steps at the 1e-5 bar; then to 2000 steps, where the max-abs phi
-    difference has grown past it (FP32 against FP64 over a long shear run
-    at Gamma = 10.5): stated, with the deformation D within 1%."""
+    difference has grown past it: the FP32 collision conserves momentum only
+    to rounding, and in this low-Re, 200-cell channel the velocity
+    difference grows linearly over the run (viscous time about 240k steps),
+    moving the interface.  Stated, with u below 1e-5 and D within 1%."""
     nx, ny = 400, 200
     dp = derive_params(Re=0.5, Ca=0.1, radius=40.0, xi=2.0, H=ny, Pe=0.43)
     wu = np.zeros((3, 2, 3)); wu[1, 0, 0] = -dp.wall_u; wu[1, 1, 0] = dp.wall_u
