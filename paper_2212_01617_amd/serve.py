@@ -53,15 +53,17 @@ class Request:
 
     @property
     def radius(self) -> float:
-        return 0.2 * self.n
+        """Drop radius, 0.2 of the smallest box dimension (N for every shape)."""
+        return 0.2 * min(d for d in self.shape if d > 1)
 
     @property
     def shape(self) -> tuple:
-        """(nx, ny, nz) of the lattice."""
+        """(nx, ny, nz) of the lattice: shear boxes are twice as long as wide
+        along the flow, four-roller cells are N^2 (2D) or N^3 (3D)."""
         n = self.n
         if self.kind == 0:
             return (2 * n, n, 1) if self.flow == "shear" else (n, n, 1)
-        return (2 * n, n, n) if self.flow == "shear" else (n, n, max(n // 2, 8))
+        return (2 * n, n, n) if self.flow == "shear" else (n, n, n)
 
     @property
     def cells(self) -> int:
@@ -268,6 +270,50 @@ class Server:
 # mixture has less free energy than the drop), so served runs use Pe = 10.
 SERVE_PE = 10.0
 
+# Four-roller cells: the extension rate eps at the centre per unit roller
+# angular speed, by cell size N, once calibrated in this process.  Cylinders
+# along z in a z-periodic box drive a two-dimensional flow, so one D2Q9 run
+# serves 2D and 3D cells of the same N.
+_ROLLER_RATE: dict[int, float] = {}
+
+
+def roller_radius(n: int) -> float:
+    """Roller radius of an N-cell four-roller box."""
+    return 0.117 * n
+
+
+def calibrate_rollers(n: int, tip_speed: float = 1e-3, tol: float = 1e-3, max_chunks: int = 12) -> float:
+    """Extension rate at the centre of the N x N four-roller cell per unit
+    roller angular speed, from a single-phase run at Stokes-like speeds
+    (tip speed `tip_speed`) stepped until the centre rate changes by less
+    than `tol` relative over a chunk of a quarter viscous time over the
+    half box; the rate is the least-squares slope of u_x against x over the
+    6 x 6 cells around the centre.  Cached per N."""
+    from . import frelbm as F
+    rr = roller_radius(n)
+    cs, signs = synth.four_roller_geometry(n, n, rr)
+    om = tip_speed / rr
+    mask = synth.roller_mask((1, n, n), cs, rr)
+    rollers = [(c, s * om, 2, rr) for c, s in zip(cs, signs)]
+    p = F.make_params(F.FRE_D2Q9, (n, n, 1), rollers=rollers, A=1e-3, kappa=4e-3, tau_f=1.0, tau_g=1.0, M=0.1)
+    L = F.Lattice(p, -np.ones((1, n, n)), None, None, mask)
+    nu = (1.0 - 0.5) / 3.0
+    chunk = max(100, int(0.25 * (n / 2.0) ** 2 / nu))
+    c0 = n // 2 - 3
+    xs = np.arange(c0, c0 + 6) - (n - 1) / 2.0
+    prev = None
+    eps = 0.0
+    for _ in range(max_chunks):
+        L.step(chunk)
+        ux = L.read(("u",))["u"][0, 0, c0:c0 + 6, c0:c0 + 6]
+        eps = float((ux * xs[None, :]).sum() / (6.0 * (xs * xs).sum()))
+        if prev is not None and abs(eps - prev) <= tol * abs(eps):
+            break
+        prev = eps
+    L.close()
+    _ROLLER_RATE[n] = eps / om
+    return _ROLLER_RATE[n]
+
 
 def lattice_inputs(req: Request):
     """Parameters and initial fields of a request (shear: walls normal to the
@@ -293,14 +339,15 @@ def lattice_inputs(req: Request):
         u0 = synth.shear_velocity(sh, dp.rate, axis_normal=wall_axis)
         p = F.make_params(req.kind, (nx, ny, nz), storage=req.storage, bc=tuple(bc), wall_u=wu, **dp.phys())
         return p, phi0, u0, None, dp.rate
-    # four rollers: tip speed eps * d with d the gap from the domain centre to
-    # the roller surface (the stagnation flow u = eps (x, -y) there);
-    # uncalibrated against a single-phase run
+    # four rollers: the angular speed that gives the extension rate eps at the
+    # centre, from the calibration of this N when there is one (see
+    # calibrate_rollers), else the stagnation-flow estimate: tip speed eps * d
+    # with d the gap from the centre to the roller surface
     dp = derive_params(Re=req.Re, Ca=req.Ca, radius=R, xi=req.xi, Pe=Pe)
-    rr = 0.117 * nx
+    rr = roller_radius(nx)
     cs, signs = synth.four_roller_geometry(nx, ny, rr, nz=nz)
-    d = math.hypot(nx / 4.0, ny / 4.0) - rr
-    om = dp.rate * d / rr
+    k = _ROLLER_RATE.get(nx)
+    om = dp.rate / k if k else dp.rate * (math.hypot(nx / 4.0, ny / 4.0) - rr) / rr
     mask = synth.roller_mask(sh, cs, rr)
     rollers = [(c, s * om, 2, rr) for c, s in zip(cs, signs)]
     phi0 = synth.droplet_phi(sh, R, req.xi, noise=1e-4, seed=req.rid, dims=2 if req.kind == 0 else 3)
@@ -311,7 +358,8 @@ def lattice_inputs(req: Request):
 class GpuEngine:
     """Lattices in torch-allocated device buffers, stepped by one Batch."""
 
-    def __init__(self, budget_bytes: int, max_members: int, keep_final: bool = False):
+    def __init__(self, budget_bytes: int, max_members: int, keep_final: bool = False,
+                 calibrate_rollers: bool = True):
         from . import frelbm as F
         self.F = F
         cap = max(1 << 16, budget_bytes // 2048)
@@ -322,6 +370,7 @@ class GpuEngine:
         self.keep_final = keep_final
         self.final = {}
         self._fp = {}
+        self.calibrate = calibrate_rollers
 
     def footprint(self, req: Request) -> int:
         if req.rid not in self._fp:
@@ -340,6 +389,8 @@ class GpuEngine:
         return (True, True, True)
 
     def admit(self, req: Request):
+        if self.calibrate and req.flow == "rollers" and req.shape[0] not in _ROLLER_RATE:
+            calibrate_rollers(req.shape[0])
         p, phi0, u0, mask, rate = lattice_inputs(req)
         L = self.F.Lattice(p, phi0, None, u0, mask)
         w, f = self.F.Batch.needs(L)
