@@ -162,7 +162,8 @@ class Server:
     library refuses, e.g. a wall speed beyond the Mach guard);
     engine.admit(req) -> (handle, strain per step) or None when the engine
     cannot take it now; engine.step(n); engine.phi(handle) -> phi field
-    (raises RunFailed for a lattice gone non-finite); engine.periodic(req) -> periodic flags (x, y, z); engine.retire(handle)."""
+    (raises RunFailed for a lattice gone non-finite); engine.periodic(req) -> periodic flags (x, y, z); engine.retire(handle);
+    optionally engine.prepare(requests), called once before the clock starts."""
 
     def __init__(self, engine, budget_bytes: int, max_members: int, chunk: int = 200,
                  strain_cap: float = 25.0, step_cap: int = 200_000, clock=time.monotonic,
@@ -210,6 +211,8 @@ class Server:
             if need > self.budget:
                 raise ValueError(f"request {r.rid} needs more than the whole memory budget")
             ok.append(r)
+        if hasattr(self.engine, "prepare"):
+            self.engine.prepare(ok)   # per-geometry set-up, before the clock starts
         pending = deque(ok)
         active: list[_Member] = []
         used = 0
@@ -387,6 +390,13 @@ class GpuEngine:
         if req.flow == "shear":
             return (True, req.kind != 0, req.kind == 0)
         return (True, True, True)
+
+    def prepare(self, requests):
+        """Calibrate the roller speed of every four-roller cell size the
+        requests use (once per N and process)."""
+        if self.calibrate:
+            for n in sorted({r.shape[0] for r in requests if r.flow == "rollers"} - set(_ROLLER_RATE)):
+                calibrate_rollers(n)
 
     def admit(self, req: Request):
         if self.calibrate and req.flow == "rollers" and req.shape[0] not in _ROLLER_RATE:
