@@ -1,10 +1,10 @@
 // api.hip -- host side of the C ABI declared in include/frelbm.h.
 //
-// A lattice lives entirely in the caller's device buffer: population planes
-// (structure of arrays, one plane per direction, each plane padded to 256 B),
-// the cell mask, the coupling fields (rho - 1, phi), (mu_rho, mu_phi), Pi, an
-// auxiliary float4 field, the list of solid cells next to fluid, and the
-// reduction partials.  Steps are enqueued on the caller's stream; on a
+// A lattice lives entirely in the caller's device buffer: population blocks
+// (64 cells by direction), the cell mask and neighbour words, the moments
+// (rho - 1, phi), the coupling values (rho - 1, phi, Pi, mu_phi), the FP32
+// path's partial moment sums, an auxiliary float4 field, the list of solid
+// cells next to fluid, and the reduction partials.  Steps are enqueued on the caller's stream; on a
 // non-default stream a pair of steps (even + odd AA parity) is captured once
 // into a HIP graph and replayed.
 #include <hip/hip_runtime.h>
@@ -54,7 +54,7 @@ struct Plan {
   int off[3];
   int px;          // row pitch: ext[0] rounded up to a multiple of 64
   long long ncell;  // px * ext[1] * ext[2]
-  size_t o_f, o_g, o_g0, o_mask, o_nbm, o_M, o_C, o_MUP, o_P0, o_PU, o_PD, o_XE, o_AUX, o_fill, o_part, total;
+  size_t o_f, o_g, o_g0, o_mask, o_nbm, o_M, o_C, o_P0, o_PU, o_PD, o_XE, o_AUX, o_fill, o_part, total;
 };
 
 fre_status validate(const fre_params *p) {
@@ -127,7 +127,6 @@ Plan make_plan(const fre_params *p) {
   P.o_nbm = take((size_t)P.ncell * 4);
   P.o_M = take((size_t)P.ncell * 8);
   P.o_C = take((size_t)P.ncell * 16);
-  P.o_MUP = take((size_t)P.ncell * 4);
   // FP32: first-pass moment sums of the collide (same plane; below and above in 3D)
   const bool bp = p->storage == FRE_FP32;
   P.o_P0 = bp ? take((size_t)P.ncell * 8) : 0;
@@ -302,7 +301,6 @@ void bind_args(fre_lattice *L) {
   a.nbm = (uint32_t *)(L->base + P.o_nbm);
   a.M = (float2 *)(L->base + P.o_M);
   a.C = (float4 *)(L->base + P.o_C);
-  a.MUP = (float *)(L->base + P.o_MUP);
   a.P0 = P.o_P0 ? (float2 *)(L->base + P.o_P0) : nullptr;
   a.PU = P.o_PU ? (float2 *)(L->base + P.o_PU) : nullptr;
   a.PD = P.o_PD ? (float2 *)(L->base + P.o_PD) : nullptr;
@@ -396,7 +394,6 @@ fre_status fre_lattice_init(const fre_params *p, void *device_buf, size_t bytes,
     INIT_TRY(hipMemcpyAsync(L->a.fill_list, L->fill_host.data(), L->fill_host.size() * 4, hipMemcpyHostToDevice, st));
   INIT_TRY(hipMemcpyAsync(L->a.nbm, nbm.data(), nbm.size() * 4, hipMemcpyHostToDevice, st));
   INIT_TRY(hipMemsetAsync(L->a.C, 0, (size_t)P.ncell * 16, st));
-  INIT_TRY(hipMemsetAsync(L->a.MUP, 0, (size_t)P.ncell * 4, st));
   launch_init(L->a);
   INIT_TRY(hipGetLastError());
   INIT_TRY(hipStreamSynchronize(st));
@@ -510,11 +507,10 @@ fre_status fre_read_moments(fre_lattice *L, uint32_t field_mask, double *host_ou
   const Plan &P = L->plan;
   fre_status s = observe(L);
   if (s != FRE_OK) return s;
-  std::vector<float> Cv((size_t)P.ncell * 4), MUP((size_t)P.ncell), AUX((size_t)P.ncell * 4);
+  std::vector<float> Cv((size_t)P.ncell * 4), AUX((size_t)P.ncell * 4);
   std::vector<uint8_t> mask((size_t)P.ncell);
   hipStream_t st = L->a.stream;
   HIP_TRY(hipMemcpyAsync(Cv.data(), L->a.C, Cv.size() * 4, hipMemcpyDeviceToHost, st));
-  HIP_TRY(hipMemcpyAsync(MUP.data(), L->a.MUP, MUP.size() * 4, hipMemcpyDeviceToHost, st));
   HIP_TRY(hipMemcpyAsync(AUX.data(), L->a.AUX, AUX.size() * 4, hipMemcpyDeviceToHost, st));
   HIP_TRY(hipMemcpyAsync(mask.data(), L->a.mask, mask.size(), hipMemcpyDeviceToHost, st));
   HIP_TRY(hipStreamSynchronize(st));
@@ -535,8 +531,9 @@ fre_status fre_read_moments(fre_lattice *L, uint32_t field_mask, double *host_ou
                 case 0: v = 1.0 + (double)Cv[4 * e]; break;
                 case 1: v = Cv[4 * e + 1]; break;
                 case 2: v = AUX[4 * e + k]; break;
-                case 3: v = Cv[4 * e + 3]; break;
-                case 4: v = MUP[e]; break;
+                // C = (rho - 1, phi, Pi, mu_phi): mu_rho = (Pi - phi mu_phi) / rho
+                case 3: v = ((double)Cv[4 * e + 2] - (double)Cv[4 * e + 1] * Cv[4 * e + 3]) / (1.0 + Cv[4 * e]); break;
+                case 4: v = Cv[4 * e + 3]; break;
                 default: v = AUX[4 * e + 3]; break;
               }
             }
@@ -866,7 +863,6 @@ Inst inst_of(const fre_lattice *L, const void *base) {
   I.nbm = rel(L->a.nbm, base);
   I.M = rel(L->a.M, base);
   I.C = rel(L->a.C, base);
-  I.MUP = rel(L->a.MUP, base);
   I.P0 = L->a.P0 ? rel(L->a.P0, base) : 0;
   I.PU = L->a.PU ? rel(L->a.PU, base) : 0;
   I.PD = L->a.PD ? rel(L->a.PD, base) : 0;

@@ -37,8 +37,7 @@ struct LaunchArgs {
   uint8_t *mask;
   uint32_t *nbm;  // per cell: non-fluid neighbour bits, NB_SELF_SOLID
   float2 *M;    // (rho - 1, phi)
-  float4 *C;    // (rho - 1, phi, Pi = rho mu_rho + phi mu_phi, mu_rho)
-  float *MUP;   // mu_phi
+  float4 *C;    // (rho - 1, phi, Pi = rho mu_rho + phi mu_phi, mu_phi)
   float2 *P0, *PU, *PD;  // FP32: first-pass moment sums by source plane (same, below, above)
   float2 *XE;   // FP32: post-collision (f, g) leaving each 64-cell row segment sideways
   float4 *AUX;  // u0 at init; (ux, uy, uz, P) after observe
@@ -62,7 +61,6 @@ template <int Q, int S> struct LatView {
   const uint8_t *mask;
   float2 *M;
   float4 *C;
-  float *MUP;
   float2 *P0, *PU, *PD;
   float2 *XE;
   const float4 *AUX;  // (u0, phi0) during the consistent initialisation
@@ -79,7 +77,7 @@ template <int Q, int S> struct LatView {
 struct Inst {
   Geom G;
   Phys ph;
-  long long f, g, g0, mask, nbm, M, C, MUP, P0, PU, PD, XE, fill;
+  long long f, g, g0, mask, nbm, M, C, P0, PU, PD, XE, fill;
   int n_fill;
 };
 

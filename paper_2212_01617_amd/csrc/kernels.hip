@@ -411,15 +411,18 @@ __device__ __forceinline__ void laplacians(Fetch fetch, float2 m0, float &lr, fl
   lp = 6.0f * ap;
 }
 
-// mu_rho, mu_phi and Pi of fluid cell c into C and MUP.
+// Pi and mu_phi of fluid cell c into C = (rho - 1, phi, Pi, mu_phi); mu_rho
+// is recovered where needed as (Pi - phi mu_phi) / rho (coupling_mu_rho).
 template <int Q, int S>
 __device__ __forceinline__ void store_potential(const LatView<Q, S> &L, long long c, float2 m0, float lr,
                                                 float lp) {
   float mr, mp;
   chem_pot(L.ph, m0.x, m0.y, lr, lp, mr, mp);
-  L.C[c] = make_float4(m0.x, m0.y, (1.0f + m0.x) * mr + m0.y * mp, mr);
-  L.MUP[c] = mp;
+  L.C[c] = make_float4(m0.x, m0.y, (1.0f + m0.x) * mr + m0.y * mp, mp);
 }
+
+// mu_rho of a cell from its coupling values C = (rho - 1, phi, Pi, mu_phi).
+__device__ __forceinline__ float coupling_mu_rho(float4 c) { return (c.z - c.y * c.w) / (1.0f + c.x); }
 
 template <int Q, int S>
 __device__ __forceinline__ void stage_potential(const LatView<Q, S> &L, int x, int y, int z) {
@@ -463,11 +466,12 @@ __device__ __forceinline__ void force(const float4 *__restrict__ C, const Nbr &N
 // the population to the slot the cell reads it from next step.
 template <int Q, int S, int ODD, int NT>
 __device__ __forceinline__ void collide_cell(const Pops<Q, S> &P, const Nbr &N, long long c,
-                                             const float4 *__restrict__ C, const float *__restrict__ MUP,
+                                             const float4 *__restrict__ C,
                                              const Phys &ph, float (*post)[NT], int tid, float &rho_out,
                                              float &phi_out, float2 &rest_out) {
   using V = VSet<Q>;
-  const float mu_rho = C[c].w, mu_phi = MUP[c];
+  const float4 cc = C[c];
+  const float mu_phi = cc.w, mu_rho = coupling_mu_rho(cc);
   float F[3];
   force<Q>(C, N, mu_rho, mu_phi, F);
   // FP16 storage loads g only after f is collided and stored, which holds the
@@ -600,7 +604,7 @@ __device__ __forceinline__ void stage_collide(const LatView<Q, S> &L, int x, int
     const Nbr N(L.G, x, y, z);
     float rho, phi;
     float2 rest;
-    collide_cell<Q, S, ODD, NT>(L.P, N, c, L.C, L.MUP, L.ph, nullptr, 0, rho, phi, rest);
+    collide_cell<Q, S, ODD, NT>(L.P, N, c, L.C, L.ph, nullptr, 0, rho, phi, rest);
     if (bits != 0u) bounce_back<Q, S, ODD>(L.P, N, c, bits, L.mask, L.G, L.ph, x, y, z, rho, phi);
     return;
   }
@@ -615,7 +619,7 @@ __device__ __forceinline__ void stage_collide(const LatView<Q, S> &L, int x, int
     if (fluid) {
       const Nbr N(L.G, x, y, z);
       float rho, phi;
-      collide_cell<Q, S, ODD, NT>(L.P, N, c, L.C, L.MUP, L.ph, post, tid, rho, phi, rest);
+      collide_cell<Q, S, ODD, NT>(L.P, N, c, L.C, L.ph, post, tid, rho, phi, rest);
       if (bits != 0u) bounce_back<Q, S, ODD>(L.P, N, c, bits, L.mask, L.G, L.ph, x, y, z, rho, phi);
     }
   }
@@ -694,7 +698,8 @@ __device__ __forceinline__ void stage_pre_collide(const LatView<Q, S> &L, int x,
   const uint32_t bits = L.nbm[c];
   if (bits & NB_SELF_SOLID) return;
   const Nbr N(L.G, x, y, z);
-  const float mu_rho = L.C[c].w, mu_phi = L.MUP[c];
+  const float4 cc = L.C[c];
+  const float mu_phi = cc.w, mu_rho = coupling_mu_rho(cc);
   float F[3];
   force<Q>(L.C, N, mu_rho, mu_phi, F);
   float df[Q];
@@ -829,7 +834,7 @@ __device__ __forceinline__ LatView<Q, S> view_of(char *base, const Inst &I) {
   LatView<Q, S> L;
   L.P = pops_of<Q, S>(base + I.f, base + I.g, (float *)(base + I.g0));
   L.nbm = (const uint32_t *)(base + I.nbm); L.mask = (const uint8_t *)(base + I.mask);
-  L.M = (float2 *)(base + I.M); L.C = (float4 *)(base + I.C); L.MUP = (float *)(base + I.MUP);
+  L.M = (float2 *)(base + I.M); L.C = (float4 *)(base + I.C);
   L.P0 = (float2 *)(base + I.P0); L.PU = (float2 *)(base + I.PU); L.PD = (float2 *)(base + I.PD);
   L.XE = (float2 *)(base + I.XE);
   L.AUX = nullptr;
@@ -904,10 +909,10 @@ __global__ __launch_bounds__(BX *BY) void k_init(Pops<Q, S> P, const uint32_t *_
 }
 
 // g at its equilibrium g^eq(phi0, mu_phi, u0) (eq. geq; g_0 by complement),
-// parity-0 slots, with AUX = (u0, phi0) and MUP = mu_phi current.
+// parity-0 slots, with AUX = (u0, phi0) and C (mu_phi in C.w) current.
 template <int Q, int S>
 __global__ __launch_bounds__(BX *BY) void k_reinit_g(Pops<Q, S> P, const uint32_t *__restrict__ nbm,
-                                                     const float *__restrict__ MUP,
+                                                     const float4 *__restrict__ C,
                                                      const float4 *__restrict__ AUX, Geom G, Phys ph) {
   using V = VSet<Q>;
   int x, y, z;
@@ -917,7 +922,7 @@ __global__ __launch_bounds__(BX *BY) void k_reinit_g(Pops<Q, S> P, const uint32_
   const float4 a = AUX[c];
   const float u[3] = {a.x, a.y, a.z};
   const float uu = u[0] * u[0] + u[1] * u[1] + u[2] * u[2];
-  const float phi = a.w, mp = MUP[c];
+  const float phi = a.w, mp = C[c].w;
   float rest = 0.0f;
 #pragma unroll
   for (int i = 1; i < Q; ++i) {
@@ -930,12 +935,11 @@ __global__ __launch_bounds__(BX *BY) void k_reinit_g(Pops<Q, S> P, const uint32_
   P.stg(0, c, phi - rest);
 }
 
-// Observables (u with F/2, bulk pressure) at the current time; M, C, MUP must
+// Observables (u with F/2, bulk pressure) at the current time; M and C must
 // be current.  OUT[c] = (ux, uy, uz, P).
 template <int Q, int S>
 __global__ __launch_bounds__(BX *BY) void k_observe(Pops<Q, S> P, const uint32_t *__restrict__ nbm,
                                                     const float4 *__restrict__ C,
-                                                    const float *__restrict__ MUP,
                                                     float4 *__restrict__ OUT, Geom G, Phys ph, int odd) {
   using V = VSet<Q>;
   int x, y, z;
@@ -955,13 +959,13 @@ __global__ __launch_bounds__(BX *BY) void k_observe(Pops<Q, S> P, const uint32_t
     j[1] += V::cy(i) * df[i];
     j[2] += V::cz(i) * df[i];
   }
-  float4 m0 = C[c];
-  float mu_phi = MUP[c];
+  const float4 m0 = C[c];
   float F[3];
-  force<Q>(C, N, m0.w, mu_phi, F);
-  float rho = 1.0f + m0.x;
-  float inv = 1.0f / rho;
-  float pres = rho / 3.0f + rho * m0.w + m0.y * mu_phi - psi_bulk(ph, rho, m0.y);
+  force<Q>(C, N, coupling_mu_rho(m0), m0.w, F);
+  const float rho = 1.0f + m0.x;
+  const float inv = 1.0f / rho;
+  // P = cs^2 rho + rho mu_rho + phi mu_phi - psi_b, with Pi = rho mu_rho + phi mu_phi
+  const float pres = rho / 3.0f + m0.z - psi_bulk(ph, rho, m0.y);
   OUT[c] = make_float4((j[0] + 0.5f * F[0]) * inv, (j[1] + 0.5f * F[1]) * inv,
                        (j[2] + 0.5f * F[2]) * inv, pres);
 }
@@ -1046,7 +1050,7 @@ template <int Q, int S>
 static LatView<Q, S> view_of_args(const LaunchArgs &a) {
   LatView<Q, S> L;
   L.P = make_pops<Q, S>(a);
-  L.nbm = a.nbm; L.mask = a.mask; L.M = a.M; L.C = a.C; L.MUP = a.MUP;
+  L.nbm = a.nbm; L.mask = a.mask; L.M = a.M; L.C = a.C;
   L.P0 = a.P0; L.PU = a.PU; L.PD = a.PD; L.XE = a.XE; L.AUX = a.AUX;
   L.G = a.G; L.ph = a.ph; L.fill = a.fill_list; L.n_fill = a.n_fill;
   L.xcd = 1;
@@ -1133,7 +1137,7 @@ static void observe_impl(const LaunchArgs &a, int odd) {
   int k = 0;
   if (!ByProduct<S>::on) moments_launch<Q, S>(a, odd);  // by-product: M is valid
   couple_seq<Q, S>(a, nullptr, k);
-  k_observe<Q, S><<<cell_grid(a.G), cell_block(), 0, a.stream>>>(make_pops<Q, S>(a), a.nbm, a.C, a.MUP, a.AUX, a.G, a.ph, odd);
+  k_observe<Q, S><<<cell_grid(a.G), cell_block(), 0, a.stream>>>(make_pops<Q, S>(a), a.nbm, a.C, a.AUX, a.G, a.ph, odd);
 }
 
 template <int Q, int S>
@@ -1156,7 +1160,7 @@ static void consistent_init_impl(const LaunchArgs &a, long long n) {
   // mu_phi of the new rho with phi0, then g^eq(phi0, mu_phi, u0) and M
   cells_launch<Q, S, ST_PRE_MOMENTS>(a, 0);
   couple_seq<Q, S>(a, nullptr, k);
-  k_reinit_g<Q, S><<<cell_grid(a.G), cell_block(), 0, a.stream>>>(make_pops<Q, S>(a), a.nbm, a.MUP, a.AUX, a.G, a.ph);
+  k_reinit_g<Q, S><<<cell_grid(a.G), cell_block(), 0, a.stream>>>(make_pops<Q, S>(a), a.nbm, a.C, a.AUX, a.G, a.ph);
   moments_launch<Q, S>(a, 0);
 }
 
