@@ -154,6 +154,126 @@ def consistent_init_rate(n: int = 400) -> dict:
             "sample": f"{n} pre-iterations minus 0, best of 2, FP32, 256x128x128"}
 
 
+def four_roller(steps: int = 200) -> dict:
+    """The four-roller cell: D3Q19 256x256x64, all axes periodic, four
+    staircase cylinders of radius 30 along z at the quarter points spinning in
+    alternation, a drop of radius 24 in the centre (xi = 2, Re = 0.5,
+    Ca = 0.1).  17% of the cells are solid; MLUPS count fluid cells only."""
+    import torch
+    from paper_2212_01617_amd import frelbm as F
+    from paper_2212_01617_amd import synth
+    from paper_2212_01617_amd.params import derive_params
+    nx, ny, nz, rr = 256, 256, 64, 30.0
+    dp = derive_params(Re=0.5, Ca=0.1, radius=24.0, xi=2.0, Pe=0.43)
+    cs, signs = synth.four_roller_geometry(nx, ny, rr, nz=nz)
+    om = dp.rate * (np.hypot(nx / 4.0, ny / 4.0) - rr) / rr
+    sh = (nz, ny, nx)
+    mask = synth.roller_mask(sh, cs, rr)
+    phi0 = synth.droplet_phi(sh, 24.0, 2.0, noise=1e-4, seed=0)
+    n_fluid = int((mask == 0).sum())
+    out = {"workload": "D3Q19 four-roller cell 256x256x64, rollers r=30 along z, drop R=24, xi=2, Re=0.5, Ca=0.1",
+           "fluid_cells": n_fluid}
+    for storage, key in ((0, "fp32"), (1, "fp16")):
+        p = F.make_params(F.FRE_D3Q19, (nx, ny, nz), storage=storage,
+                          rollers=[(c, sg * om, 2, rr) for c, sg in zip(cs, signs)], **dp.phys())
+        L = F.Lattice(p, phi0, None, None, mask, stream=torch.cuda.Stream())
+        L.autotune(5)
+        ms, _ = time_steps(L, steps, 20, 3)
+        mlups = n_fluid / (ms * 1e-3) / 1e6
+        b = bytes_per_lu(19, storage)
+        out[key] = {"value": round(mlups, 1), "unit": "MLUPS", "ms_per_step": round(ms, 5), "bytes_per_lu": b,
+                    "step_frac": round(mlups * 1e6 * b / 1e9 / PEAK_HBM_GBS, 4)}
+        L.close()
+    return out
+
+
+def shard(steps: int = 1000) -> dict:
+    """One GPU's share of the 256x128x128 shear lattice split eight ways
+    along z (its slowest axis in memory): 256x128x16 cells, the drop's
+    central planes, at its real shape.  The slab's faces are periodic here;
+    the exchange with the neighbouring slabs is not part of this path."""
+    import torch
+    from paper_2212_01617_amd import frelbm as F
+    p0, phi0, u0, meta = workload(0)
+    z0 = 56
+    phi_s = np.ascontiguousarray(phi0[z0:z0 + 16])
+    u_s = np.ascontiguousarray(u0[:, z0:z0 + 16])
+    out = {"workload": "256x128x16 slab (planes 56-71) of the D3Q19 shear droplet 256x128x128, periodic faces"}
+    for storage, key in ((0, "fp32"), (1, "fp16")):
+        p = F.make_params(F.FRE_D3Q19, (256, 128, 16), storage=storage, **meta["phys"])
+        L = F.Lattice(p, phi_s, None, u_s, stream=torch.cuda.Stream())
+        L.autotune(5)
+        ms, _ = time_steps(L, steps, 50, 3)
+        n = 256 * 128 * 16
+        mlups = n / (ms * 1e-3) / 1e6
+        b = bytes_per_lu(19, storage)
+        out[key] = {"value": round(mlups, 1), "unit": "MLUPS", "ms_per_step": round(ms, 5),
+                    "step_frac": round(mlups * 1e6 * b / 1e9 / PEAK_HBM_GBS, 4)}
+        L.close()
+    return out
+
+
+def cpu_table() -> dict:
+    """The FP64 oracle's rate on the host cores at one thread and at all
+    threads, each measurement in a child process of its own (the OpenMP
+    thread count is fixed when the oracle library loads): the 100x100 D2Q9
+    static drop, the 400x200 D2Q9 shear, the 64x32x32 D3Q19 copy and the full
+    256x128x128 lattice (fewer steps at one thread)."""
+    import subprocess
+    allc = os.cpu_count() or 1
+    try:
+        allc = len(os.sched_getaffinity(0))
+    except AttributeError:
+        pass
+    allc = int(os.environ.get("OMP_NUM_THREADS", allc))
+    cases = (("static_drop_100x100_d2q9", 200, 200), ("shear_400x200_d2q9", 200, 200),
+             ("copy_64x32x32_d3q19", 200, 200), ("shear_256x128x128_d3q19", 4, 20))
+    rows = {}
+    for name, st1, stn in cases:
+        for th, st in ((1, st1), (allc, stn)):
+            env = dict(os.environ, OMP_NUM_THREADS=str(th))
+            r = subprocess.run([sys.executable, os.path.abspath(__file__), "--cpu-case", name, "--steps", str(st)],
+                               env=env, capture_output=True, text=True, check=True)
+            rows.setdefault(name, {})[f"{th}t"] = json.loads(r.stdout.strip().splitlines()[-1])
+            print(f"[cpu] {name} {th} threads: {rows[name][f'{th}t']}", file=sys.stderr, flush=True)
+    return {"threads_all": allc, "cases": rows}
+
+
+def cpu_case(name: str, steps: int) -> dict:
+    """One oracle timing (see cpu_table)."""
+    from oracle import oracle as O
+    from paper_2212_01617_amd import synth
+    from paper_2212_01617_amd.params import derive_params
+    if name == "static_drop_100x100_d2q9":
+        phi0 = synth.droplet_phi((1, 100, 100), 20.0, 1.5, center=(49.5, 49.5, 0), noise=1e-4, seed=0, dims=2)
+        L = O.Lattice(O.make_params(0, (100, 100, 1), A=0.04, kappa=0.09, tau_f=1.0, tau_g=1.0, M=0.1), phi0)
+        n = 100 * 100
+    elif name == "shear_400x200_d2q9":
+        dp = derive_params(Re=0.5, Ca=0.1, radius=40.0, xi=2.0, H=200, Pe=0.43)
+        wu = np.zeros((3, 2, 3)); wu[1, 0, 0] = -dp.wall_u; wu[1, 1, 0] = dp.wall_u
+        sh = (1, 200, 400)
+        L = O.Lattice(O.make_params(0, (400, 200, 1), bc=(0, 1, 0), wall_u=wu, **dp.phys()),
+                      synth.droplet_phi(sh, 40.0, 2.0, noise=1e-4, seed=0, dims=2), None,
+                      synth.shear_velocity(sh, dp.rate, axis_normal=1))
+        n = 400 * 200
+    else:
+        shape, R = ((64, 32, 32), 6.25) if name == "copy_64x32x32_d3q19" else ((256, 128, 128), 25.0)
+        dp = derive_params(Re=1.0, Ca=0.1, radius=25.0, xi=2.0, H=128, Pe=0.43)
+        nx, ny, nz = shape
+        uw = dp.rate * nz / 2.0
+        wu = np.zeros((3, 2, 3)); wu[2, 0, 0] = -uw; wu[2, 1, 0] = uw
+        sh = (nz, ny, nx)
+        L = O.Lattice(O.make_params(1, shape, bc=(0, 0, 1), wall_u=wu, **dp.phys()),
+                      synth.droplet_phi(sh, R, 2.0, noise=1e-4, seed=0), None,
+                      synth.shear_velocity(sh, dp.rate, axis_normal=2))
+        n = nx * ny * nz
+    L.step(1)
+    t0 = time.perf_counter()
+    L.step(steps)
+    dt = time.perf_counter() - t0
+    return {"MLUPS": round(n * steps / dt / 1e6, 3), "steps": steps, "seconds": round(dt, 2)}
+
+
 def cpu_baseline(p_gpu, phi0, u0, meta, steps=60):
     from oracle import oracle as O
     nx, ny, nz = meta["shape"]
@@ -184,10 +304,20 @@ def main():
     ap.add_argument("--shape", default="", help="with --kernels-only: rows,xcd for k_moments, "
                     "k_potential, k_collide, e.g. 4,1,4,1,4,1 (default shapes if empty)")
     ap.add_argument("--copy-probe", action="store_true")
+    ap.add_argument("--no-extra", action="store_true", help="skip the four-roller and shard legs")
+    ap.add_argument("--cpu-table", action="store_true",
+                    help="only time the FP64 oracle at 1 and all threads on four cases (no GPU)")
+    ap.add_argument("--cpu-case", default="", help=argparse.SUPPRESS)
     args = ap.parse_args()
+    if args.cpu_case:
+        print(json.dumps(cpu_case(args.cpu_case, args.steps)), flush=True)
+        return
+    if args.cpu_table:
+        print(json.dumps({"mode": "cpu-table", **cpu_table()}), flush=True)
+        return
     if args.gpus != 1:
         print("bench.py runs on one GPU only: this build has no multi-GPU path "
-              "(one lattice per GPU; see the sharding notes in DESIGN.md)", file=sys.stderr)
+              "(one lattice per GPU)", file=sys.stderr)
         sys.exit(2)
     import torch
     from paper_2212_01617_amd import frelbm as F
@@ -267,6 +397,9 @@ def main():
     if not args.no_large:
         out["large_lattice"] = large_lattice()
     out["consistent_init"] = consistent_init_rate()
+    if not args.no_extra:
+        out["four_roller"] = four_roller()
+        out["shard"] = shard()
     if args.serve:
         out["serving"] = serving(args.serve)
     if not args.no_cpu_baseline:

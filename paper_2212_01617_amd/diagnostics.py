@@ -36,17 +36,25 @@ from scipy import ndimage
 AXES = {"x": 2, "y": 1, "z": 0}  # array axis of each spatial direction
 
 
-def indicator(phi: np.ndarray) -> np.ndarray:
+def indicator(phi: np.ndarray, solid: np.ndarray | None = None) -> np.ndarray:
     """Phase indicator, 1 in the droplet's bulk and 0 in the matrix's:
     C = clamp((phi - phi_out) / (phi_in - phi_out), 0, 1) with phi_in,
-    phi_out the medians of phi over phi > 0 and phi <= 0."""
+    phi_out the medians of phi over the fluid cells with phi > 0 and
+    phi <= 0.  Cells flagged in ``solid`` (obstacles, whose phi reads 0) get
+    C = 0: they belong to neither phase."""
     phi = np.asarray(phi, dtype=np.float64)
-    inside = phi > 0.0
-    if not inside.any() or inside.all():
-        return np.clip(0.5 * (1.0 + phi), 0.0, 1.0)
-    hi = float(np.median(phi[inside]))
-    lo = float(np.median(phi[~inside]))
-    return np.clip((phi - lo) / (hi - lo), 0.0, 1.0)
+    fluid = np.ones(phi.shape, dtype=bool) if solid is None else ~np.asarray(solid, dtype=bool)
+    inside = (phi > 0.0) & fluid
+    outside = (phi <= 0.0) & fluid
+    if not inside.any() or not outside.any():
+        C = np.clip(0.5 * (1.0 + phi), 0.0, 1.0)
+    else:
+        hi = float(np.median(phi[inside]))
+        lo = float(np.median(phi[outside]))
+        C = np.clip((phi - lo) / (hi - lo), 0.0, 1.0)
+    if solid is not None:
+        C[~fluid] = 0.0
+    return C
 
 
 def _periodic_centre(w: np.ndarray, axis: int) -> float:
@@ -102,14 +110,16 @@ class Deformation:
     centre: tuple     # centroid (x, y, z) in the rolled frame
 
 
-def deformation(phi: np.ndarray, plane: str = "xz", periodic=(True, True, True)) -> Deformation:
+def deformation(phi: np.ndarray, plane: str = "xz", periodic=(True, True, True),
+                solid: np.ndarray | None = None) -> Deformation:
     """Taylor deformation and orientation of the droplet in ``plane``.
 
     ``plane`` names the flow axis first and the second in-plane axis next,
     e.g. "xz" for shear along x with walls normal to z, "xy" for a 2D
     lattice or a four-roller cell.  theta > 0 means the long axis tilts
-    from the flow axis towards the positive second axis."""
-    C, _ = centred(indicator(phi), periodic)
+    from the flow axis towards the positive second axis.  ``solid`` flags
+    obstacle cells, which are left out of the droplet."""
+    C, _ = centred(indicator(phi, solid), periodic)
     cen, T = second_moments(C)
     a, b = "xyz".index(plane[0]), "xyz".index(plane[1])
     S = np.array([[T[a, a], T[a, b]], [T[b, a], T[b, b]]])

@@ -191,7 +191,8 @@ class Server:
         if not comps:
             return "dissolved"
         plane = "xz" if (req.flow == "shear" and req.kind == 1) else "xy"
-        m.D = Dg.deformation(phi, plane=plane, periodic=per).D
+        solid = self.engine.solid(m.handle) if hasattr(self.engine, "solid") else None
+        m.D = Dg.deformation(phi, plane=plane, periodic=per, solid=solid).D
         strain = m.t * m.rate
         if m.tracker.add(strain, m.D):
             return "steady"
@@ -353,7 +354,9 @@ def lattice_inputs(req: Request):
     om = dp.rate / k if k else dp.rate * (math.hypot(nx / 4.0, ny / 4.0) - rr) / rr
     mask = synth.roller_mask(sh, cs, rr)
     rollers = [(c, s * om, 2, rr) for c, s in zip(cs, signs)]
-    phi0 = synth.droplet_phi(sh, R, req.xi, noise=1e-4, seed=req.rid, dims=2 if req.kind == 0 else 3)
+    # the drop sits on the stagnation point, the rollers' centre of symmetry
+    phi0 = synth.droplet_phi(sh, R, req.xi, center=(nx / 2.0, ny / 2.0, (nz - 1) / 2.0), noise=1e-4,
+                             seed=req.rid, dims=2 if req.kind == 0 else 3)
     p = F.make_params(req.kind, (nx, ny, nz), storage=req.storage, rollers=rollers, **dp.phys())
     return p, phi0, None, mask, dp.rate
 
@@ -373,6 +376,7 @@ class GpuEngine:
         self.keep_final = keep_final
         self.final = {}
         self._fp = {}
+        self.masks = {}
         self.calibrate = calibrate_rollers
 
     def footprint(self, req: Request) -> int:
@@ -411,6 +415,8 @@ class GpuEngine:
         self.work += w
         self.fill += f
         self.slots[id(L)] = (slot, w, f, req.rid)
+        if mask is not None:
+            self.masks[id(L)] = mask != 0
         return L, rate
 
     def step(self, n: int):
@@ -425,8 +431,13 @@ class GpuEngine:
             raise
         return L.read(("phi",))["phi"]
 
+    def solid(self, L):
+        """Obstacle cells of a lattice (None without obstacles)."""
+        return self.masks.get(id(L))
+
     def retire(self, L):
         slot, w, f, rid = self.slots.pop(id(L))
+        self.masks.pop(id(L), None)
         if self.keep_final:
             self.final[rid] = (L.info()[0], L.populations())
         self.batch.remove(slot)

@@ -66,6 +66,26 @@ def test_ellipse_across_periodic_boundary():
     assert abs(wrapped.D - ref.D) < 1e-3 and abs(wrapped.theta - ref.theta) < 2e-3
 
 
+def test_obstacles_are_left_out_of_the_droplet():
+    # an ellipse (D = 1/3) among four solid discs whose phi reads 0, as the
+    # readback gives for obstacle cells: with the solid mask D is the
+    # ellipse's; without it the discs (indicator 0.5) swamp the moments
+    n = 160
+    phi = _ellipse((1, n, n), (80.0, 80.0, 0.0), 24.0, 12.0, 0.0)
+    z, y, x = np.meshgrid(np.arange(1), np.arange(n), np.arange(n), indexing="ij")
+    solid = np.zeros(phi.shape, dtype=bool)
+    for cx, cy in ((40, 40), (120, 40), (40, 120), (120, 120)):
+        solid |= (x - cx) ** 2 + (y - cy) ** 2 <= 19.0 ** 2
+    assert not (solid & (phi > -1.0)).any()
+    ref = Dg.deformation(phi, plane="xy")
+    with_obstacles = np.where(solid, 0.0, phi)
+    d = Dg.deformation(with_obstacles, plane="xy", periodic=(True, True, True), solid=solid)
+    assert abs(d.D - ref.D) < 1e-12 and abs(d.theta - ref.theta) < 1e-12
+    assert abs(d.D - 1.0 / 3.0) < 2e-3
+    assert Dg.deformation(with_obstacles, plane="xy").D < 0.5 * ref.D
+    assert Dg.components(with_obstacles) == Dg.components(phi)
+
+
 def test_ellipsoid_in_shear_plane():
     # semi-axes 20 (tilted in xz), 12 (along y), 10 (in xz): D in xz = 1/3
     shape = (48, 40, 72)
