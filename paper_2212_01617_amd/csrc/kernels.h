@@ -55,6 +55,33 @@ template <> inline Pops<19, 1> make_pops<19, 1>(const LaunchArgs &a) { return Po
 
 // Device view of one lattice for the kernels of one (velocity set, storage)
 // class.
+// n / d for 0 <= n < 2^31 and a divisor d >= 1 fixed at launch, as a
+// multiply-high and a shift (Granlund and Montgomery, 1994): with
+// s = ceil(log2 d) and m = floor(2^32 (2^s - d) / d) + 1, n / d equals
+// (mulhi(n, m) + n) >> s.  The tile decode divides block indices, which are
+// the same across a wave, so it runs on the scalar unit instead of as a
+// per-lane reciprocal sequence.
+struct UDiv {
+  uint32_t d = 1, m = 1, s = 0;
+  UDiv() = default;
+  explicit UDiv(uint32_t dv) : d(dv) {
+    while ((1ull << s) < dv) ++s;
+    m = (uint32_t)(((1ull << 32) * ((1ull << s) - dv)) / dv + 1u);
+  }
+};
+
+// Order of the 64 x rows tiles in a 1D grid of `blocks` blocks: gx tiles per
+// row of tiles, gy rows of tiles per plane; with xcd set, the first `full`
+// blocks follow the XCD-aware order (whole rounds of 8 rows of tiles).
+struct TileMap {
+  int gx = 1, gy = 1, xcd = 0, full = 0;
+  UDiv dgx, dgy;
+  TileMap() = default;
+  TileMap(int ex, int ey, int rows, int blocks, int xcd_order)
+      : gx((ex + 63) / 64), gy((ey + rows - 1) / rows), xcd(xcd_order),
+        full(xcd_order ? blocks / (8 * gx) * (8 * gx) : 0), dgx((uint32_t)gx), dgy((uint32_t)gy) {}
+};
+
 template <int Q, int S> struct LatView {
   Pops<Q, S> P;
   const uint32_t *nbm;
@@ -68,7 +95,7 @@ template <int Q, int S> struct LatView {
   Phys ph;
   const int *fill;
   int n_fill;
-  int xcd;  // XCD-aware block order (single-lattice kernels)
+  TileMap tm;  // block order of the single-lattice tile kernels
 };
 
 // One slot of a batch, as stored in device memory.  Arrays are given as

@@ -47,23 +47,33 @@ __device__ __forceinline__ bool cell_of_thread(const Geom &G, int &x, int &y, in
 // once per XCD.  Here consecutive runs of `ch` tiles (one grid row in x) go
 // to one XCD, while the 8 XCDs still work on neighbouring rows at any time.
 constexpr int NXCD = 8;
-__device__ __forceinline__ int xcd_tile(int b, int nb, int ch) {
-  const int full = nb / (NXCD * ch) * (NXCD * ch);
-  if (b >= full) return b;
-  const int k = b % NXCD, j = b / NXCD;
-  return ((j / ch) * NXCD + k) * ch + j % ch;
+__device__ __forceinline__ uint32_t udiv(uint32_t n, const UDiv &u) { return (__umulhi(n, u.m) + n) >> u.s; }
+
+// Tile of block b: (tile column bx, row of tiles r counted over all planes).
+__device__ __forceinline__ void tile_of_block(const TileMap &T, uint32_t b, uint32_t &bx, uint32_t &r) {
+  const uint32_t gx = (uint32_t)T.gx;
+  uint32_t t = b;
+  if (T.xcd && b < (uint32_t)T.full) {
+    const uint32_t k = b % NXCD, j = b / NXCD, jq = udiv(j, T.dgx);
+    t = (jq * NXCD + k) * gx + (j - jq * gx);
+  }
+  r = udiv(t, T.dgx);
+  bx = t - r * gx;
 }
 
 // Cell of this thread in a 1D grid of 64 x blockDim.y tiles (x fastest,
-// then y, then z), in XCD-aware order when `xcd` is set.
-__device__ __forceinline__ bool cell_of_tile(const Geom &G, int xcd, int &x, int &y, int &z, long long &c) {
+// then y, then z).  A wave is one 64-cell row of its tile, so y and z are
+// the same in every lane; saying so lets the row and plane arithmetic run
+// on the scalar unit.
+__device__ __forceinline__ bool cell_of_tile(const Geom &G, const TileMap &T, int &x, int &y, int &z,
+                                             long long &c) {
   const int rows = (int)blockDim.y;
-  const int gx = (G.ex + BX - 1) / BX, gy = (G.ey + rows - 1) / rows;
-  const int t = xcd ? xcd_tile((int)blockIdx.x, (int)gridDim.x, gx) : (int)blockIdx.x;
-  const int bx = t % gx, r = t / gx;
-  x = bx * BX + threadIdx.x;
-  y = (r % gy) * rows + threadIdx.y;
-  z = r / gy;
+  uint32_t bx, r;
+  tile_of_block(T, blockIdx.x, bx, r);
+  const uint32_t rq = udiv(r, T.dgy);
+  x = (int)bx * BX + threadIdx.x;
+  y = __builtin_amdgcn_readfirstlane((int)(r - rq * (uint32_t)T.gy) * rows + (int)threadIdx.y);
+  z = (int)rq;
   if (x >= G.ex || y >= G.ey) return false;
   c = (long long)x + (long long)G.px * ((long long)y + (long long)G.ey * z);
   return true;
@@ -744,7 +754,7 @@ template <int Q, int S, int STAGE, int ODD>
 __global__ __launch_bounds__(BX *MAX_ROWS) __attribute__((amdgpu_waves_per_eu(S == 1 ? 4 : 1))) void k_cells(LatView<Q, S> L) {
   int x, y, z;
   long long c;
-  const bool in = cell_of_tile(L.G, L.xcd, x, y, z, c);
+  const bool in = cell_of_tile(L.G, L.tm, x, y, z, c);
   if (STAGE == ST_COLLIDE) {
     stage_collide<Q, S, ODD>(L, x, y, z, in);
     return;
@@ -772,9 +782,10 @@ __global__ __launch_bounds__(BX *MAX_ROWS) void k_potential_zm(LatView<Q, S> L, 
   __shared__ float2 ring[3][MAX_ROWS + 2][HW];
   const Geom &G = L.G;
   const int rows = (int)blockDim.y;
-  const int gx = (G.ex + BX - 1) / BX, gy = (G.ey + rows - 1) / rows;
-  const int t = L.xcd ? xcd_tile((int)blockIdx.x, (int)gridDim.x, gx) : (int)blockIdx.x;
-  const int bx = t % gx, r = t / gx, by = r % gy, ch = r / gy;
+  uint32_t ubx, ur;
+  tile_of_block(L.tm, blockIdx.x, ubx, ur);
+  const uint32_t uch = udiv(ur, L.tm.dgy);
+  const int bx = (int)ubx, by = (int)(ur - uch * (uint32_t)L.tm.gy), ch = (int)uch;
   const int xlo = bx * BX, ylo = by * rows;
   const int z0 = ch * tz, z1 = min(z0 + tz, G.ez);
   const int w = min(BX, G.ex - xlo), h = min(rows, G.ey - ylo);  // cells of the tile on the lattice
@@ -839,7 +850,6 @@ __device__ __forceinline__ LatView<Q, S> view_of(char *base, const Inst &I) {
   L.XE = (float2 *)(base + I.XE);
   L.AUX = nullptr;
   L.G = I.G; L.ph = I.ph; L.fill = (const int *)(base + I.fill); L.n_fill = I.n_fill;
-  L.xcd = 0;
   return L;
 }
 
@@ -1053,7 +1063,6 @@ static LatView<Q, S> view_of_args(const LaunchArgs &a) {
   L.nbm = a.nbm; L.mask = a.mask; L.M = a.M; L.C = a.C;
   L.P0 = a.P0; L.PU = a.PU; L.PD = a.PD; L.XE = a.XE; L.AUX = a.AUX;
   L.G = a.G; L.ph = a.ph; L.fill = a.fill_list; L.n_fill = a.n_fill;
-  L.xcd = 1;
   return L;
 }
 
@@ -1065,8 +1074,8 @@ static void cells_launch(const LaunchArgs &a, int odd) {
   LatView<Q, S> L = view_of_args<Q, S>(a);
   const Shape sh = a.shape[STAGE <= ST_COLLIDE ? STAGE : SHAPE_MOMENTS];
   const int rows = (STAGE == ST_COLLIDE && ByProduct<S>::on) ? COLLIDE_ROWS : sh.rows;
-  L.xcd = sh.xcd;
   const dim3 grid = tile_grid(a.G, rows), block(BX, rows, 1);
+  L.tm = TileMap(a.G.ex, a.G.ey, rows, (int)grid.x, sh.xcd);
   if (odd) k_cells<Q, S, STAGE, 1><<<grid, block, 0, a.stream>>>(L);
   else k_cells<Q, S, STAGE, 0><<<grid, block, 0, a.stream>>>(L);
 }
@@ -1085,12 +1094,12 @@ template <int Q, int S>
 static void potential_launch(const LaunchArgs &a) {
   LatView<Q, S> L = view_of_args<Q, S>(a);
   const Shape sh = a.shape[SHAPE_POTENTIAL];
-  L.xcd = sh.xcd;
   const int tiles = ((a.G.ex + BX - 1) / BX) * ((a.G.ey + sh.rows - 1) / sh.rows);
   int nch = (2048 + tiles - 1) / tiles;
   nch = nch < 1 ? 1 : (nch > a.G.ez ? a.G.ez : nch);
   const int tz = (a.G.ez + nch - 1) / nch;
   nch = (a.G.ez + tz - 1) / tz;
+  L.tm = TileMap(a.G.ex, a.G.ey, sh.rows, tiles * nch, sh.xcd);
   k_potential_zm<Q, S><<<dim3((unsigned)(tiles * nch)), dim3(BX, sh.rows, 1), 0, a.stream>>>(L, tz);
 }
 
