@@ -87,6 +87,13 @@ typedef struct fre_roller {
  *    use_paper_form = 1, kappa1, kappa2, alpha are used as given.
  *  tau_f, tau_g > 1/2: relaxation times; M > 0: mobility, with
  *    Gamma = M / (tau_g - 1/2) (Sec. 2.2, mobility relation).
+ *  g0_extended (0 or 1; FP32 storage only): carry the rest population g_0,
+ *    which is O(1), as its FP32 value plus the part FP32 rounds away (kept
+ *    in half precision, scaled by 2^24), so that its storage rounding does
+ *    not accumulate over long runs.  The collide then needs more registers
+ *    and the FP32 step runs about 10% slower.  Fixed at init
+ *    (fre_set_params refuses to change it); such a lattice cannot join a
+ *    batch (fre_batch_add returns FRE_EINVAL).
  * Validation: tau > 1/2, kappa1, kappa2, alpha > 0 (A, kappa > 0), M > 0,
  * |wall_u| <= 0.1 and |omega| * radius <= 0.1 (Mach guard), sizes >= 1,
  * storage/kind/bc codes in range. */
@@ -102,7 +109,7 @@ typedef struct fre_params {
   double A, kappa;
   double kappa1, kappa2, alpha;
   int32_t use_paper_form;
-  int32_t reserved1;
+  int32_t g0_extended;
   double tau_f, tau_g, M;
 } fre_params;
 

@@ -61,6 +61,8 @@ fre_status validate(const fre_params *p) {
   if (!p) return fail(FRE_EINVAL, "params is NULL");
   if (p->kind != FRE_D2Q9 && p->kind != FRE_D3Q19) return fail(FRE_EINVAL, "kind %d not D2Q9/D3Q19", p->kind);
   if (p->storage != FRE_FP32 && p->storage != FRE_FP16) return fail(FRE_EINVAL, "storage %d", p->storage);
+  if (p->g0_extended != 0 && p->g0_extended != 1) return fail(FRE_EINVAL, "g0_extended %d", p->g0_extended);
+  if (p->g0_extended && p->storage != FRE_FP32) return fail(FRE_EINVAL, "g0_extended needs FP32 storage");
   if (p->nx < 1 || p->ny < 1 || p->nz < 1) return fail(FRE_EINVAL, "sizes must be >= 1");
   for (int a = 0; a < 3; ++a)
     if (p->bc[a] != FRE_PERIODIC && p->bc[a] != FRE_WALL) return fail(FRE_EINVAL, "bc[%d]=%d", a, p->bc[a]);
@@ -116,7 +118,8 @@ Plan make_plan(const fre_params *p) {
   P.o_f = take((size_t)P.q * P.ncell * es);
   if (p->storage == FRE_FP32) {
     P.o_g = take((size_t)P.q * P.ncell * 4);
-    P.o_g0 = 0;
+    // the low part of g_0, in half precision, scaled by 2^24
+    P.o_g0 = take((size_t)P.ncell * 2);
   } else {
     // plane 0 of the half array is unused (g_0 lives in an FP32 plane), so
     // f and g share every block offset
@@ -289,6 +292,7 @@ void bind_args(fre_lattice *L) {
   LaunchArgs &a = L->a;
   a.q = P.q;
   a.storage = L->p.storage;
+  a.g0x = L->p.g0_extended;
   a.G.ex = P.ext[0]; a.G.ey = P.ext[1]; a.G.ez = P.ext[2];
   for (int k = 0; k < 3; ++k) { a.G.per[k] = P.per[k]; a.G.off[k] = P.off[k]; }
   a.G.px = P.px;
@@ -296,7 +300,7 @@ void bind_args(fre_lattice *L) {
   a.ph = make_phys(&L->p);
   a.f = L->base + P.o_f;
   a.g = L->base + P.o_g;
-  a.g0 = L->p.storage == FRE_FP16 ? (float *)(L->base + P.o_g0) : nullptr;
+  a.g0 = (float *)(L->base + P.o_g0);  // FP16: the g_0 plane; FP32: the half plane of g_0's low part
   a.mask = L->base + P.o_mask;
   a.nbm = (uint32_t *)(L->base + P.o_nbm);
   a.M = (float2 *)(L->base + P.o_M);
@@ -443,8 +447,9 @@ fre_status fre_set_params(fre_lattice *L, const fre_params *p) {
   if (L->batch) return fail(FRE_ESTATE, "lattice is a batch member: remove it before changing parameters");
   const fre_params &o = L->p;
   if (p->kind != o.kind || p->nx != o.nx || p->ny != o.ny || p->nz != o.nz || p->storage != o.storage ||
-      p->bc[0] != o.bc[0] || p->bc[1] != o.bc[1] || p->bc[2] != o.bc[2] || p->n_rollers != o.n_rollers)
-    return fail(FRE_EINVAL, "shape, storage, bc and roller count cannot change");
+      p->bc[0] != o.bc[0] || p->bc[1] != o.bc[1] || p->bc[2] != o.bc[2] || p->n_rollers != o.n_rollers ||
+      p->g0_extended != o.g0_extended)
+    return fail(FRE_EINVAL, "shape, storage, bc, roller count and g0_extended cannot change");
   L->p = *p;
   L->a.ph = make_phys(p);
   reset_graph(L);
@@ -552,10 +557,11 @@ fre_status fre_read_populations(fre_lattice *L, double *f_out, double *g_out, si
   const long long N = L->n_user;
   if (n_doubles_each < (size_t)P.q * N) return fail(FRE_EINVAL, "outputs need q*N doubles each");
   float *tmp = nullptr;
-  size_t nb = (size_t)2 * P.q * P.ncell * sizeof(float);
+  // planes: f_i + w_i, g_i, then the low part of g_0 (zero with FP16 storage)
+  size_t nb = (size_t)(2 * P.q + 1) * P.ncell * sizeof(float);
   HIP_TRY(hipMalloc(&tmp, nb));
   launch_read_pops(L->a, (int)(L->t & 1), tmp);
-  std::vector<float> h((size_t)2 * P.q * P.ncell);
+  std::vector<float> h((size_t)(2 * P.q + 1) * P.ncell);
   hipError_t e = hipGetLastError();
   if (e == hipSuccess) e = hipMemcpyAsync(h.data(), tmp, nb, hipMemcpyDeviceToHost, L->a.stream);
   if (e == hipSuccess) e = hipStreamSynchronize(L->a.stream);
@@ -569,7 +575,8 @@ fre_status fre_read_populations(fre_lattice *L, double *f_out, double *g_out, si
           long long u = x + (long long)p.nx * (y + (long long)p.ny * z);
           long long ee = ext_index(P, x, y, z);
           f_out[(long long)i * N + u] = h[(size_t)i * P.ncell + ee];
-          g_out[(long long)i * N + u] = h[(size_t)(P.q + i) * P.ncell + ee];
+          g_out[(long long)i * N + u] = (double)h[(size_t)(P.q + i) * P.ncell + ee] +
+                                        (i == 0 ? (double)h[(size_t)2 * P.q * P.ncell + ee] : 0.0);
         }
   return FRE_OK;
 }
@@ -999,6 +1006,7 @@ fre_status fre_batch_add(fre_batch *B, fre_lattice *L, int32_t *slot) {
   if (!B || !L || !slot) return fail(FRE_EINVAL, "NULL argument");
   if (L->batch) return fail(FRE_EINVAL, "lattice is already a batch member");
   if (L->state) return fail(FRE_ESTATE, "lattice is in the failed state");
+  if (L->p.g0_extended) return fail(FRE_EINVAL, "a lattice with g0_extended cannot join a batch");
   int free_slot = -1, members = 0;
   for (int k = 0; k < B->max_slots; ++k) {
     if (B->slot[k]) ++members;

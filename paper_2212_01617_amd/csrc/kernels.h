@@ -33,7 +33,8 @@ struct LaunchArgs {
   Geom G;
   Phys ph;
   void *f, *g;  // population blocks (float or half)
-  float *g0;    // FP16 storage only: g_0 plane
+  float *g0;    // FP16 storage: g_0 plane; FP32 storage: the half plane of g_0's low part
+  int g0x;      // FP32 storage: g_0 carried as hi + lo (fre_params.g0_extended)
   uint8_t *mask;
   uint32_t *nbm;  // per cell: non-fluid neighbour bits, NB_SELF_SOLID
   float2 *M;    // (rho - 1, phi)
@@ -48,8 +49,8 @@ struct LaunchArgs {
 };
 
 template <int Q, int S> inline Pops<Q, S> make_pops(const LaunchArgs &a);
-template <> inline Pops<9, 0> make_pops<9, 0>(const LaunchArgs &a) { return Pops<9, 0>{(float *)a.f, (float *)a.g}; }
-template <> inline Pops<19, 0> make_pops<19, 0>(const LaunchArgs &a) { return Pops<19, 0>{(float *)a.f, (float *)a.g}; }
+template <> inline Pops<9, 0> make_pops<9, 0>(const LaunchArgs &a) { return Pops<9, 0>{(float *)a.f, (float *)a.g, (__half *)a.g0}; }
+template <> inline Pops<19, 0> make_pops<19, 0>(const LaunchArgs &a) { return Pops<19, 0>{(float *)a.f, (float *)a.g, (__half *)a.g0}; }
 template <> inline Pops<9, 1> make_pops<9, 1>(const LaunchArgs &a) { return Pops<9, 1>{(__half *)a.f, (__half *)a.g, a.g0}; }
 template <> inline Pops<19, 1> make_pops<19, 1>(const LaunchArgs &a) { return Pops<19, 1>{(__half *)a.f, (__half *)a.g, a.g0}; }
 
@@ -110,8 +111,8 @@ struct Inst {
 
 template <int Q, int S>
 __host__ __device__ inline Pops<Q, S> pops_of(void *f, void *g, float *g0);
-template <> __host__ __device__ inline Pops<9, 0> pops_of<9, 0>(void *f, void *g, float *) { return Pops<9, 0>{(float *)f, (float *)g}; }
-template <> __host__ __device__ inline Pops<19, 0> pops_of<19, 0>(void *f, void *g, float *) { return Pops<19, 0>{(float *)f, (float *)g}; }
+template <> __host__ __device__ inline Pops<9, 0> pops_of<9, 0>(void *f, void *g, float *g0) { return Pops<9, 0>{(float *)f, (float *)g, (__half *)g0}; }
+template <> __host__ __device__ inline Pops<19, 0> pops_of<19, 0>(void *f, void *g, float *g0) { return Pops<19, 0>{(float *)f, (float *)g, (__half *)g0}; }
 template <> __host__ __device__ inline Pops<9, 1> pops_of<9, 1>(void *f, void *g, float *g0) { return Pops<9, 1>{(__half *)f, (__half *)g, g0}; }
 template <> __host__ __device__ inline Pops<19, 1> pops_of<19, 1>(void *f, void *g, float *g0) { return Pops<19, 1>{(__half *)f, (__half *)g, g0}; }
 

@@ -101,21 +101,18 @@ struct Nbr {
 };
 
 // Load the q populations of fluid cell c at time parity `odd` (AA pattern).
-template <int Q, int S>
+// CACHED selects ordinary rather than non-temporal loads (the collide).
+template <int Q, int S, bool CACHED = false>
 __device__ __forceinline__ void load_pops(const Pops<Q, S> &P, const Nbr &N, long long c, int odd,
                                           float *df, float *g) {
   using V = VSet<Q>;
 #pragma unroll
   for (int i = 0; i < Q; ++i) {
-    if (!odd) {
-      df[i] = P.ldf(i, c);
-      g[i] = P.ldg(i, c);
-    } else {
-      // f_i(x) = f_i*(x - c_i), written by x - c_i into its slot opp(i)
-      long long s = i == 0 ? c : N.template back<V>(i);
-      df[i] = P.ldf(opp(i), s);
-      g[i] = P.ldg(opp(i), s);
-    }
+    // f_i(x) = f_i*(x - c_i) after an odd step, written by x - c_i into its slot opp(i)
+    const long long s = (!odd || i == 0) ? c : (long long)N.template back<V>(i);
+    const int sl = !odd ? i : opp(i);
+    df[i] = CACHED ? P.ldfc(sl, s) : P.ldf(sl, s);
+    g[i] = CACHED ? P.ldgc(sl, s) : P.ldg(sl, s);
   }
 }
 
@@ -474,7 +471,8 @@ __device__ __forceinline__ void force(const float4 *__restrict__ C, const Nbr &N
 // populations are returned in rest_out.  For a
 // link into a solid cell that slot is never read; bounce_back() then moves
 // the population to the slot the cell reads it from next step.
-template <int Q, int S, int ODD, int NT>
+// X (FP32 storage): g_0 carried as hi + lo (the extended mode).
+template <int Q, int S, int ODD, int NT, bool X = false>
 __device__ __forceinline__ void collide_cell(const Pops<Q, S> &P, const Nbr &N, long long c,
                                              const float4 *__restrict__ C,
                                              const Phys &ph, float (*post)[NT], int tid, float &rho_out,
@@ -491,9 +489,9 @@ __device__ __forceinline__ void collide_cell(const Pops<Q, S> &P, const Nbr &N, 
   float df[Q], g[Q];
   if constexpr (SPLIT) {
 #pragma unroll
-    for (int i = 0; i < Q; ++i) df[i] = (!ODD || i == 0) ? P.ldf(i, c) : P.ldf(opp(i), N.template back<V>(i));
+    for (int i = 0; i < Q; ++i) df[i] = (!ODD || i == 0) ? P.ldfc(i, c) : P.ldfc(opp(i), N.template back<V>(i));
   } else {
-    load_pops<Q, S>(P, N, c, ODD, df, g);
+    load_pops<Q, S, true>(P, N, c, ODD, df, g);
   }
   float drho = 0.0f, j[3] = {0, 0, 0};
 #pragma unroll
@@ -514,10 +512,14 @@ __device__ __forceinline__ void collide_cell(const Pops<Q, S> &P, const Nbr &N, 
     const float cu = V::cx(i) * u[0] + V::cy(i) * u[1] + V::cz(i) * u[2];
     return 3.0f * cu + 4.5f * cu * cu - 1.5f * uu;
   };
-  float phi = 0.0f;
+  float phi = 0.0f, gm = 0.0f;  // gm: sum of the moving g_i (extended g_0 only)
   if constexpr (!SPLIT) {
 #pragma unroll
     for (int i = 0; i < Q; ++i) phi += g[i];
+    if constexpr (X) {
+#pragma unroll
+      for (int i = 1; i < Q; ++i) gm += g[i];
+    }
   }
   float geq_rest = 0.0f;
   // post-collision g_i of direction i > 0, stored to the slot it streams to
@@ -551,13 +553,24 @@ __device__ __forceinline__ void collide_cell(const Pops<Q, S> &P, const Nbr &N, 
   }
   if constexpr (SPLIT) {
 #pragma unroll
-    for (int i = 0; i < Q; ++i) g[i] = (!ODD || i == 0) ? P.ldg(i, c) : P.ldg(opp(i), N.template back<V>(i));
+    for (int i = 0; i < Q; ++i) g[i] = (!ODD || i == 0) ? P.ldgc(i, c) : P.ldgc(opp(i), N.template back<V>(i));
 #pragma unroll
     for (int i = 0; i < Q; ++i) phi += g[i];
 #pragma unroll
     for (int i = 1; i < Q; ++i) collide_g(i);
   }
-  const float g0s = g[0] + ph.om_g * ((phi - geq_rest) - g[0]);  // g_0 is stored in FP32
+  float g0s;
+  if constexpr (S == 0 && X) {
+    // g_0* = g_0 + (g_0^eq - g_0) / tau_g with g_0^eq - g_0 = sum_{i>0} (g_i -
+    // g_i^eq): the increment is formed from the moving populations alone and
+    // added to hi + lo with the rounding error of the sum kept (TwoSum)
+    const float t = ph.om_g * (gm - geq_rest) + P.ldg0lo(c);
+    g0s = g[0] + t;
+    const float tb = g0s - g[0];
+    P.stg0lo(c, (g[0] - (g0s - tb)) + (t - tb));
+  } else {
+    g0s = g[0] + ph.om_g * ((phi - geq_rest) - g[0]);  // g_0 is stored in FP32
+  }
   P.stg(0, c, g0s);
   rest_out.y = g0s;
   rho_out = rho;
@@ -582,7 +595,7 @@ __device__ __forceinline__ void bounce_back(const Pops<Q, S> &P, const Nbr &N, l
     const long long n = N.template at<V>(i);
     const int sp = ODD ? i : opp(i);
     const long long sc = ODD ? n : c;
-    const float fs = P.ldf(sp, sc), gs = WITH_G ? P.ldg(sp, sc) : 0.0f;
+    const float fs = P.ldfc(sp, sc), gs = WITH_G ? P.ldgc(sp, sc) : 0.0f;
     const int xs = wrap(x + V::cx(i), G.ex), ys = wrap(y + V::cy(i), G.ey);
     const int zs = V::D == 3 ? wrap(z + V::cz(i), G.ez) : z;
     float uw[3];
@@ -602,7 +615,7 @@ __device__ __forceinline__ void bounce_back(const Pops<Q, S> &P, const Nbr &N, l
 // first pass of the moment groups of its column: S0 for this plane, UP for
 // the plane above and DN for the plane below (all their sources lie in this
 // plane), from the tile's post-collision values.
-template <int Q, int S, int ODD>
+template <int Q, int S, int ODD, bool X = false>
 __device__ __forceinline__ void stage_collide(const LatView<Q, S> &L, int x, int y, int z, bool active) {
   using V = VSet<Q>;
   constexpr int NT = BX * COLLIDE_ROWS;
@@ -614,7 +627,7 @@ __device__ __forceinline__ void stage_collide(const LatView<Q, S> &L, int x, int
     const Nbr N(L.G, x, y, z);
     float rho, phi;
     float2 rest;
-    collide_cell<Q, S, ODD, NT>(L.P, N, c, L.C, L.ph, nullptr, 0, rho, phi, rest);
+    collide_cell<Q, S, ODD, NT, X>(L.P, N, c, L.C, L.ph, nullptr, 0, rho, phi, rest);
     if (bits != 0u) bounce_back<Q, S, ODD>(L.P, N, c, bits, L.mask, L.G, L.ph, x, y, z, rho, phi);
     return;
   }
@@ -629,7 +642,7 @@ __device__ __forceinline__ void stage_collide(const LatView<Q, S> &L, int x, int
     if (fluid) {
       const Nbr N(L.G, x, y, z);
       float rho, phi;
-      collide_cell<Q, S, ODD, NT>(L.P, N, c, L.C, L.ph, post, tid, rho, phi, rest);
+      collide_cell<Q, S, ODD, NT, X>(L.P, N, c, L.C, L.ph, post, tid, rho, phi, rest);
       if (bits != 0u) bounce_back<Q, S, ODD>(L.P, N, c, bits, L.mask, L.G, L.ph, x, y, z, rho, phi);
     }
   }
@@ -748,7 +761,7 @@ __device__ __forceinline__ void run_stage(const LatView<Q, S> &L, int x, int y, 
   else stage_potential<Q, S>(L, x, y, z);
 }
 
-template <int Q, int S, int STAGE, int ODD>
+template <int Q, int S, int STAGE, int ODD, bool X = false>
 // FP16 storage: at most 128 VGPRs, 4 waves per SIMD for the collide (measured
 // faster than 3 waves without spills); FP32 keeps the compiler's choice.
 __global__ __launch_bounds__(BX *MAX_ROWS) __attribute__((amdgpu_waves_per_eu(S == 1 ? 4 : 1))) void k_cells(LatView<Q, S> L) {
@@ -756,7 +769,7 @@ __global__ __launch_bounds__(BX *MAX_ROWS) __attribute__((amdgpu_waves_per_eu(S 
   long long c;
   const bool in = cell_of_tile(L.G, L.tm, x, y, z, c);
   if (STAGE == ST_COLLIDE) {
-    stage_collide<Q, S, ODD>(L, x, y, z, in);
+    stage_collide<Q, S, ODD, X>(L, x, y, z, in);
     return;
   }
   if (in) run_stage<Q, S, STAGE, ODD>(L, x, y, z);
@@ -943,6 +956,7 @@ __global__ __launch_bounds__(BX *BY) void k_reinit_g(Pops<Q, S> P, const uint32_
     P.stg(i, c, geq);
   }
   P.stg(0, c, phi - rest);
+  if constexpr (S == 0) P.stg0lo(c, 0.0f);
 }
 
 // Observables (u with F/2, bulk pressure) at the current time; M and C must
@@ -989,7 +1003,7 @@ __global__ __launch_bounds__(BX *BY) void k_read_pops(Pops<Q, S> P, const uint32
   long long c;
   if (!cell_of_thread(G, x, y, z, c)) return;
   if (nbm[c] & NB_SELF_SOLID) {
-    for (int i = 0; i < 2 * Q; ++i) out[i * G.ncell + c] = 0.0f;
+    for (int i = 0; i <= 2 * Q; ++i) out[i * G.ncell + c] = 0.0f;
     return;
   }
   const Nbr N(G, x, y, z);
@@ -1000,6 +1014,10 @@ __global__ __launch_bounds__(BX *BY) void k_read_pops(Pops<Q, S> P, const uint32
     out[i * G.ncell + c] = df[i] + V::w(i);
     out[(Q + i) * G.ncell + c] = g[i];
   }
+  // plane 2Q: the low part of g_0 (FP32 storage), added on the host
+  float lo = 0.0f;
+  if constexpr (S == 0) lo = P.ldg0lo(c);
+  out[2 * Q * G.ncell + c] = lo;
 }
 
 // Global sums over fluid cells: compensated FP32 per thread, FP64 across the
@@ -1076,6 +1094,13 @@ static void cells_launch(const LaunchArgs &a, int odd) {
   const int rows = (STAGE == ST_COLLIDE && ByProduct<S>::on) ? COLLIDE_ROWS : sh.rows;
   const dim3 grid = tile_grid(a.G, rows), block(BX, rows, 1);
   L.tm = TileMap(a.G.ex, a.G.ey, rows, (int)grid.x, sh.xcd);
+  if constexpr (STAGE == ST_COLLIDE && S == 0) {
+    if (a.g0x) {  // extended g_0: its own instantiation, so the default keeps its registers
+      if (odd) k_cells<Q, S, STAGE, 1, true><<<grid, block, 0, a.stream>>>(L);
+      else k_cells<Q, S, STAGE, 0, true><<<grid, block, 0, a.stream>>>(L);
+      return;
+    }
+  }
   if (odd) k_cells<Q, S, STAGE, 1><<<grid, block, 0, a.stream>>>(L);
   else k_cells<Q, S, STAGE, 0><<<grid, block, 0, a.stream>>>(L);
 }

@@ -123,16 +123,24 @@ __device__ __forceinline__ uint32_t blk_offset(int planes, int i, long long c) {
   const uint32_t cc = (uint32_t)c;
   return (((cc >> 6) * (uint32_t)planes + (uint32_t)i) * 64u + (cc & 63u)) * (uint32_t)ES;
 }
-// Population loads are non-temporal: every population is read once per
-// step, so it should not displace the coupling fields, which neighbouring
-// cells re-read, from the caches (measured: about 8% less step time).
-template <class T>
+// Population loads of the moments passes are non-temporal: they read every
+// population once and should not displace the coupling fields, which the
+// potential re-reads next, from the caches (measured: ordinary loads there
+// cost 10% of the FP16 step).  The FP32 collide uses ordinary loads (the
+// ldfc/ldgc accessors): a tile's x-shifted reads at odd parity share cache
+// lines with the neighbouring tile, which then still finds them cached
+// (measured: 2% less FP32 step time).  For the FP16 collide, and for the
+// f-only collide of the consistent initialisation, ordinary loads measured
+// 2% and 5% slower, so those stay non-temporal.
+template <class T, bool NT = true>
 __device__ __forceinline__ T ld_at(const T *base, uint32_t off) {
   if constexpr (sizeof(T) == 2) {
-    const unsigned short u = __builtin_nontemporal_load((const unsigned short *)((const char *)base + off));
+    const unsigned short *p = (const unsigned short *)((const char *)base + off);
+    const unsigned short u = NT ? __builtin_nontemporal_load(p) : *p;
     return __builtin_bit_cast(T, u);
   } else {
-    return __builtin_nontemporal_load((const T *)((const char *)base + off));
+    const T *p = (const T *)((const char *)base + off);
+    return NT ? __builtin_nontemporal_load(p) : *p;
   }
 }
 template <class T>
@@ -144,10 +152,19 @@ template <int Q, int S> struct Pops;
 
 template <int Q> struct Pops<Q, 0> {
   float *f, *g;
+  // g_0 = O(1) is carried as hi + lo: hi in plane 0 of g, lo (the part of
+  // g_0 that FP32 rounds away, below 2^-24 |g_0|) scaled by 2^24 in this
+  // half-precision plane, one entry per cell.  Rounding g_0 alone to FP32
+  // each step moves long runs measurably; the other populations are small.
+  __half *g0l;
   // the value a store keeps (identity for FP32)
   __device__ __forceinline__ float round(float v) const { return v; }
+  __device__ __forceinline__ float ldg0lo(long long c) const { return __half2float(g0l[c]) * 0x1p-24f; }
+  __device__ __forceinline__ void stg0lo(long long c, float lo) const { g0l[c] = __float2half_rn(lo * 0x1p24f); }
   __device__ __forceinline__ float ldf(int i, long long c) const { return ld_at(f, blk_offset<4>(Q, i, c)); }
   __device__ __forceinline__ float ldg(int i, long long c) const { return ld_at(g, blk_offset<4>(Q, i, c)); }
+  __device__ __forceinline__ float ldfc(int i, long long c) const { return ld_at<float, false>(f, blk_offset<4>(Q, i, c)); }
+  __device__ __forceinline__ float ldgc(int i, long long c) const { return ld_at<float, false>(g, blk_offset<4>(Q, i, c)); }
   __device__ __forceinline__ void stf(int i, long long c, float v) const { st_at(f, blk_offset<4>(Q, i, c), v); }
   __device__ __forceinline__ void stg(int i, long long c, float v) const { st_at(g, blk_offset<4>(Q, i, c), v); }
 };
@@ -161,6 +178,8 @@ template <int Q> struct Pops<Q, 1> {
   __device__ __forceinline__ float ldg(int i, long long c) const {
     return i == 0 ? ld_at(g0, (uint32_t)c * 4u) : __half2float(ld_at(g, blk_offset<2>(Q, i, c)));
   }
+  __device__ __forceinline__ float ldfc(int i, long long c) const { return ldf(i, c); }
+  __device__ __forceinline__ float ldgc(int i, long long c) const { return ldg(i, c); }
   __device__ __forceinline__ void stf(int i, long long c, float v) const { st_at(f, blk_offset<2>(Q, i, c), __float2half_rn(v)); }
   __device__ __forceinline__ void stg(int i, long long c, float v) const {
     if (i == 0) st_at(g0, (uint32_t)c * 4u, v); else st_at(g, blk_offset<2>(Q, i, c), __float2half_rn(v));
