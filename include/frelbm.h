@@ -90,8 +90,8 @@ typedef struct fre_roller {
  *  g0_extended (0 or 1; FP32 storage only): carry the rest population g_0,
  *    which is O(1), as its FP32 value plus the part FP32 rounds away (kept
  *    in half precision, scaled by 2^24), so that its storage rounding does
- *    not accumulate over long runs.  The collide then needs more registers
- *    and the FP32 step runs about 10% slower.  Fixed at init
+ *    not accumulate over long runs.  The FP32 step runs about 2% slower.
+ *    Fixed at init
  *    (fre_set_params refuses to change it); such a lattice cannot join a
  *    batch (fre_batch_add returns FRE_EINVAL).
  * Validation: tau > 1/2, kappa1, kappa2, alpha > 0 (A, kappa > 0), M > 0,

@@ -514,11 +514,14 @@ __device__ __forceinline__ void collide_cell(const Pops<Q, S> &P, const Nbr &N, 
   };
   float phi = 0.0f, gm = 0.0f;  // gm: sum of the moving g_i (extended g_0 only)
   if constexpr (!SPLIT) {
-#pragma unroll
-    for (int i = 0; i < Q; ++i) phi += g[i];
     if constexpr (X) {
+      // phi = g_0 + sum of the moving g_i, the latter also used for g_0 below
 #pragma unroll
       for (int i = 1; i < Q; ++i) gm += g[i];
+      phi = g[0] + gm;
+    } else {
+#pragma unroll
+      for (int i = 0; i < Q; ++i) phi += g[i];
     }
   }
   float geq_rest = 0.0f;
