@@ -8,8 +8,9 @@ inputs, already resident in HBM when timing starts.  A step is one full
 time step of the method (all kernels).  Prints one JSON line.
 
 Modes for profiling (each prints its own JSON line):
-  --kernels-only N   N individually launched steps of the FP32 workload
-                     (for rocprofv3 kernel traces and counter runs)
+  --kernels-only N   N individually launched steps of the workload, FP32 or
+                     with --storage 1 FP16 (for rocprofv3 kernel traces and
+                     counter runs)
   --copy-probe       a plain device-to-device copy of known size, the
                      reference for scaling the FETCH_SIZE / WRITE_SIZE counters
 """
@@ -319,6 +320,7 @@ def main():
     ap.add_argument("--no-large", action="store_true", help="skip the 512x256x256 leg")
     ap.add_argument("--serve", type=int, default=24, help="requests in the serving leg (0: skip)")
     ap.add_argument("--kernels-only", type=int, default=0)
+    ap.add_argument("--storage", type=int, default=0, help="with --kernels-only: 0 FP32, 1 FP16")
     ap.add_argument("--no-tune", action="store_true", help="keep the default launch shapes")
     ap.add_argument("--shape", default="", help="with --kernels-only: rows,xcd for k_moments, "
                     "k_potential, k_collide, e.g. 4,1,4,1,4,1 (default shapes if empty)")
@@ -349,7 +351,7 @@ def main():
         copy_probe()
         return
     if args.kernels_only:
-        p, phi0, u0, meta = workload(0)
+        p, phi0, u0, meta = workload(args.storage)
         L = F.Lattice(p, phi0, None, u0, stream=stream)
         if args.shape:
             v = [int(t) for t in args.shape.split(",")]
