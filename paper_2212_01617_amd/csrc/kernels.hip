@@ -44,7 +44,7 @@ __device__ __forceinline__ bool cell_of_thread(const Geom &G, int &x, int &y, in
 // L2.  With the plain order, the tiles left and right of a tile run on other
 // XCDs, and the partial cache lines that an x-shifted access (odd-parity
 // streaming, the stencils) reads across the tile edge are fetched from HBM
-// once per XCD.  Here consecutive runs of `ch` tiles (one grid row in x) go
+// once per XCD.  Here consecutive runs of gx tiles (one grid row in x) go
 // to one XCD, while the 8 XCDs still work on neighbouring rows at any time.
 constexpr int NXCD = 8;
 __device__ __forceinline__ uint32_t udiv(uint32_t n, const UDiv &u) { return (__umulhi(n, u.m) + n) >> u.s; }

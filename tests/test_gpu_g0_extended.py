@@ -52,6 +52,26 @@ def test_shear_2d_300_steps_closer_than_default():
     assert errs[True]["phi"] < 0.5 * errs[False]["phi"]
 
 
+def test_consistent_init_resets_the_low_part():
+    # pre-iterations reset g to equilibrium, the low part of g_0 with it;
+    # then normal steps, field by field against the oracle
+    shape = (64, 48, 1)
+    phi0, _, _ = case_inputs(0, shape, radius=12, xi=1.5, noise=1e-4, seed=0)
+    kw = dict(A=0.04, kappa=0.09, tau_f=1.0, tau_g=1.0, M=0.1)
+    ref = O.Lattice(O.make_params(0, shape, **kw), phi0).consistent_init(phi0, None, 300)
+    gpu = F.Lattice(F.make_params(0, shape, g0_extended=True, **kw), phi0,
+                    stream=torch.cuda.Stream()).consistent_init(phi0, None, 300)
+    for n in (0, 101):
+        ref.step(n)
+        gpu.step(n)
+        err = field_errors(ref, gpu)
+        pf, pg = pop_errors(ref, gpu)
+        log(f"[parity] g0_extended consistent_init_drop_d2q9_{n}: " +
+            " ".join(f"{k}={v:.2e}" for k, v in err.items()) + f" f={pf:.2e} g={pg:.2e}")
+        assert err["phi"] < 1e-5 and err["u"] < 1e-5 and err["rho"] < 1e-5 and pf < 1e-5 and pg < 1e-5
+    gpu.close()
+
+
 def test_checkpoint_holds_the_low_part():
     shape = (70, 9, 12)
     phi0, rho0, u0 = case_inputs(1, shape, radius=4, xi=2.0, noise=1e-3, seed=5, rho_amp=0.01, u_amp=0.01,
