@@ -325,6 +325,7 @@ def main():
     ap.add_argument("--shape", default="", help="with --kernels-only: rows,xcd for k_moments, "
                     "k_potential, k_collide, e.g. 4,1,4,1,4,1 (default shapes if empty)")
     ap.add_argument("--copy-probe", action="store_true")
+    ap.add_argument("--serve-steady-only", action="store_true", help=argparse.SUPPRESS)
     ap.add_argument("--no-extra", action="store_true", help="skip the four-roller and shard legs")
     ap.add_argument("--cpu-table", action="store_true",
                     help="only time the FP64 oracle at 1 and all threads on four cases (no GPU)")
@@ -349,6 +350,9 @@ def main():
     stream = torch.cuda.Stream()
     if args.copy_probe:
         copy_probe()
+        return
+    if args.serve_steady_only:
+        print(json.dumps({"mode": "serving-steady", **serving_steady()}), flush=True)
         return
     if args.kernels_only:
         p, phi0, u0, meta = workload(args.storage)
@@ -425,6 +429,8 @@ def main():
         out["shard"] = shard()
     if args.serve:
         out["serving"] = serving(args.serve)
+        if not args.no_extra:
+            out["serving_steady"] = serving_steady()
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(r["p"], r["phi0"], r["u0"], r["meta"])
     print(json.dumps(out), flush=True)
@@ -446,6 +452,28 @@ def serving(n_requests: int) -> dict:
     s = {k: (round(v, 4) if isinstance(v, float) else v) for k, v in s.items()}
     s["workload"] = (f"{n_requests} requests, Poisson 20/s, D2Q9 N 64-256 / D3Q19 N 48-96, shear/rollers, "
                      "FP32/FP16, caps 10 strain units or 20000 steps, 16 GiB budget")
+    eng.batch.close()
+    return s
+
+
+def serving_steady(n_requests: int = 16) -> dict:
+    """Continuous batching of 2D shear drops that settle within the caps, so
+    that time-to-steady is measured: D2Q9, N in {64, 80, 96} (2N x N boxes,
+    R = 0.2 N), Ca in [0.05, 0.2], Re in [0.5, 1], FP32 and FP16, Poisson
+    arrivals at 20/s; caps of 40 strain units or 200,000 steps."""
+    import dataclasses
+    from paper_2212_01617_amd import serve
+    base = serve.make_requests(n_requests, rate=20.0, seed=1, d2_sizes=(64, 80, 96), d3_sizes=(64,),
+                               Ca=(0.05, 0.2), Re=(0.5, 1.0))
+    rs = [dataclasses.replace(r, kind=0, flow="shear") for r in base]
+    budget = 16 << 30
+    eng = serve.GpuEngine(budget_bytes=budget, max_members=n_requests)
+    srv = serve.Server(eng, budget, max_members=n_requests, chunk=200, strain_cap=40.0, step_cap=200_000)
+    rep = srv.run(rs)
+    s = rep.summary()
+    s = {k: (round(v, 4) if isinstance(v, float) else v) for k, v in s.items()}
+    s["workload"] = (f"{n_requests} requests, Poisson 20/s, D2Q9 shear N 64-96, Ca 0.05-0.2, Re 0.5-1, FP32/FP16, "
+                     "caps 40 strain units or 200000 steps, 16 GiB budget")
     eng.batch.close()
     return s
 
