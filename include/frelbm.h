@@ -92,8 +92,8 @@ typedef struct fre_roller {
  *    in half precision, scaled by 2^24), so that its storage rounding does
  *    not accumulate over long runs.  The FP32 step runs about 2% slower.
  *    Fixed at init
- *    (fre_set_params refuses to change it); such a lattice cannot join a
- *    batch (fre_batch_add returns FRE_EINVAL).
+ *    (fre_set_params refuses to change it).  In a batch such lattices form
+ *    classes of their own.
  * Validation: tau > 1/2, kappa1, kappa2, alpha > 0 (A, kappa > 0), M > 0,
  * |wall_u| <= 0.1 and |omega| * radius <= 0.1 (Mach guard), sizes >= 1,
  * storage/kind/bc codes in range. */

@@ -197,7 +197,7 @@ struct fre_batch {
   Inst *d_inst;
   int4 *d_work;
   int2 *d_fill;
-  int *d_range;  // [4 classes][cells start, n, fills start, n]
+  int *d_range;  // [N_BATCH_CLASSES][cells start, n, fills start, n]
   std::vector<fre_lattice *> slot;
   std::vector<Inst> h_inst;
   std::vector<int4> h_work;
@@ -842,7 +842,7 @@ BatchPlan batch_plan(int max_slots, int64_t max_work, int64_t max_fill) {
   P.o_inst = take((size_t)max_slots * sizeof(Inst));
   P.o_work = take((size_t)max_work * sizeof(int4));
   P.o_fill = take((size_t)max_fill * sizeof(int2));
-  P.o_range = take(16 * sizeof(int));
+  P.o_range = take(4 * N_BATCH_CLASSES * sizeof(int));
   P.total = o;
   return P;
 }
@@ -891,14 +891,14 @@ fre_status batch_rebuild(fre_batch *B) {
   B->h_inst.assign(B->slot.size(), Inst{});
   B->h_work.clear();
   B->h_fill.clear();
-  B->h_range.assign(16, 0);
+  B->h_range.assign(4 * N_BATCH_CLASSES, 0);
   unsigned classes = 0;
-  for (int cls = 0; cls < 4; ++cls) {
+  for (int cls = 0; cls < N_BATCH_CLASSES; ++cls) {
     B->h_range[4 * cls + 0] = (int)B->h_work.size();
     B->h_range[4 * cls + 2] = (int)B->h_fill.size();
     for (size_t k = 0; k < B->slot.size(); ++k) {
       fre_lattice *L = B->slot[k];
-      if (!L || batch_class(L->a.q, L->a.storage) != cls) continue;
+      if (!L || batch_class(L->a.q, L->a.storage, L->a.g0x) != cls) continue;
       classes |= 1u << cls;
       B->h_inst[k] = inst_of(L, B->base);
       const Geom &G = L->a.G;
@@ -919,7 +919,7 @@ fre_status batch_rebuild(fre_batch *B) {
     HIP_TRY(hipMemcpyAsync(B->d_work, B->h_work.data(), B->h_work.size() * sizeof(int4), hipMemcpyHostToDevice, B->stream));
   if (!B->h_fill.empty())
     HIP_TRY(hipMemcpyAsync(B->d_fill, B->h_fill.data(), B->h_fill.size() * sizeof(int2), hipMemcpyHostToDevice, B->stream));
-  HIP_TRY(hipMemcpyAsync(B->d_range, B->h_range.data(), 16 * sizeof(int), hipMemcpyHostToDevice, B->stream));
+  HIP_TRY(hipMemcpyAsync(B->d_range, B->h_range.data(), 4 * N_BATCH_CLASSES * sizeof(int), hipMemcpyHostToDevice, B->stream));
   HIP_TRY(hipStreamSynchronize(B->stream));
   if (classes != B->classes) batch_reset_graph(B);  // the graph launches one sequence per class
   B->classes = classes;
@@ -942,7 +942,7 @@ BatchArgs batch_args(const fre_batch *B) {
 
 void batch_launch_step(const fre_batch *B, int odd) {
   const BatchArgs b = batch_args(B);
-  for (int cls = 0; cls < 4; ++cls)
+  for (int cls = 0; cls < N_BATCH_CLASSES; ++cls)
     if (B->classes & (1u << cls)) launch_batch_step(b, cls, odd);
 }
 
@@ -1006,7 +1006,6 @@ fre_status fre_batch_add(fre_batch *B, fre_lattice *L, int32_t *slot) {
   if (!B || !L || !slot) return fail(FRE_EINVAL, "NULL argument");
   if (L->batch) return fail(FRE_EINVAL, "lattice is already a batch member");
   if (L->state) return fail(FRE_ESTATE, "lattice is in the failed state");
-  if (L->p.g0_extended) return fail(FRE_EINVAL, "a lattice with g0_extended cannot join a batch");
   int free_slot = -1, members = 0;
   for (int k = 0; k < B->max_slots; ++k) {
     if (B->slot[k]) ++members;

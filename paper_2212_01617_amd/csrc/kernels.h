@@ -129,8 +129,13 @@ struct BatchArgs {
   hipStream_t stream;
 };
 
-// class index of a (velocity set, storage) pair
-inline int batch_class(int q, int storage) { return (q == 19 ? 2 : 0) + storage; }
+// Batch classes: (velocity set, storage) pairs 0..3, and 4, 5 for D2Q9 and
+// D3Q19 in FP32 with the extended g_0 (their collide is its own kernel).
+constexpr int N_BATCH_CLASSES = 6;
+inline int batch_class(int q, int storage, int g0x) {
+  if (g0x) return q == 19 ? 5 : 4;
+  return (q == 19 ? 2 : 0) + storage;
+}
 
 void launch_batch_step(const BatchArgs &b, int cls, int odd);
 void launch_step(const LaunchArgs &a, int odd);

@@ -869,7 +869,7 @@ __device__ __forceinline__ LatView<Q, S> view_of(char *base, const Inst &I) {
   return L;
 }
 
-template <int Q, int S, int STAGE, int ODD>
+template <int Q, int S, int STAGE, int ODD, bool X = false>
 __global__ __launch_bounds__(BX *MAX_ROWS) void k_batch_cells(char *base, const Inst *__restrict__ inst, const int4 *__restrict__ work,
                                                         const int *__restrict__ range) {
   const int start = range[0], n = range[1];
@@ -879,7 +879,7 @@ __global__ __launch_bounds__(BX *MAX_ROWS) void k_batch_cells(char *base, const 
     const int x = it.y * BX + threadIdx.x, y = it.z * (int)blockDim.y + threadIdx.y, z = it.w;
     const bool in = x < L.G.ex && y < L.G.ey;
     if (STAGE == ST_COLLIDE) {
-      stage_collide<Q, S, ODD>(L, x, y, z, in);
+      stage_collide<Q, S, ODD, X>(L, x, y, z, in);
       if (ByProduct<S>::on) __syncthreads();  // the tile buffer is reused by the next item
     } else if (in) {
       run_stage<Q, S, STAGE, ODD>(L, x, y, z);
@@ -1239,7 +1239,7 @@ void launch_read_pops(const LaunchArgs &a, int odd, float *out) { FRE_DISPATCH(r
 // One batched step of one class: the same five stages over every lattice of
 // the class listed in the work lists (ranges: cells [start, n], fills
 // [start, n]).
-template <int Q, int S>
+template <int Q, int S, bool X = false>
 static void batch_step_impl(const BatchArgs &b, int cls, int odd) {
   const int *rc = b.range + 4 * cls, *rf = rc + 2;
   const dim3 bl(BX, b.rows, 1);
@@ -1250,8 +1250,8 @@ static void batch_step_impl(const BatchArgs &b, int cls, int odd) {
   k_batch_fill<Q, S, 0><<<b.grid_fill, 256, 0, b.stream>>>(b.base, b.inst, b.fill, rf);
   k_batch_cells<Q, S, ST_POTENTIAL, 0><<<b.grid_cells, bl, 0, b.stream>>>(b.base, b.inst, b.work, rc);
   k_batch_fill<Q, S, 1><<<b.grid_fill, 256, 0, b.stream>>>(b.base, b.inst, b.fill, rf);
-  if (odd) k_batch_cells<Q, S, ST_COLLIDE, 1><<<b.grid_cells, bl, 0, b.stream>>>(b.base, b.inst, b.work, rc);
-  else k_batch_cells<Q, S, ST_COLLIDE, 0><<<b.grid_cells, bl, 0, b.stream>>>(b.base, b.inst, b.work, rc);
+  if (odd) k_batch_cells<Q, S, ST_COLLIDE, 1, X><<<b.grid_cells, bl, 0, b.stream>>>(b.base, b.inst, b.work, rc);
+  else k_batch_cells<Q, S, ST_COLLIDE, 0, X><<<b.grid_cells, bl, 0, b.stream>>>(b.base, b.inst, b.work, rc);
   if (ByProduct<S>::on) {
     if (odd) k_batch_cells<Q, S, ST_COMBINE, 0><<<b.grid_cells, bl, 0, b.stream>>>(b.base, b.inst, b.work, rc);
     else k_batch_cells<Q, S, ST_COMBINE, 1><<<b.grid_cells, bl, 0, b.stream>>>(b.base, b.inst, b.work, rc);
@@ -1263,7 +1263,9 @@ void launch_batch_step(const BatchArgs &b, int cls, int odd) {
     case 0: batch_step_impl<9, 0>(b, cls, odd); break;
     case 1: batch_step_impl<9, 1>(b, cls, odd); break;
     case 2: batch_step_impl<19, 0>(b, cls, odd); break;
-    default: batch_step_impl<19, 1>(b, cls, odd); break;
+    case 3: batch_step_impl<19, 1>(b, cls, odd); break;
+    case 4: batch_step_impl<9, 0, true>(b, cls, odd); break;
+    default: batch_step_impl<19, 0, true>(b, cls, odd); break;
   }
 }
 

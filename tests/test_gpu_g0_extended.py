@@ -2,8 +2,9 @@
 which is O(1), carried as its FP32 value plus the part FP32 rounds away.
 Parity with the FP64 oracle closer than the default FP32 state on the
 cases where the rounding of g_0 dominates; a checkpoint holds the low part
-(save, load and step is bitwise equal to stepping through); the refusals:
-FP16 storage, a change through fre_set_params, a batch."""
+(save, load and step is bitwise equal to stepping through); extended
+lattices in a mixed batch step bitwise as they do alone; the refusals: FP16
+storage, a change through fre_set_params."""
 import numpy as np
 import pytest
 import torch
@@ -92,6 +93,41 @@ def test_checkpoint_holds_the_low_part():
     assert np.any(g0 != g0.astype(np.float32).astype(np.float64))
 
 
+def test_mixed_batch_equals_solo_bitwise():
+    wu = np.zeros((3, 2, 3)); wu[2, 0, 0] = -0.01; wu[2, 1, 0] = 0.01
+    phi3, _, u3 = case_inputs(1, (40, 20, 12), radius=5, xi=1.5, u_amp=0.005, seed=1)
+    phi2, _, _ = case_inputs(0, (70, 33, 1), radius=8, xi=1.5, seed=2)
+    specs = [
+        (F.make_params(1, (40, 20, 12), bc=(0, 0, 1), wall_u=wu, A=0.04, kappa=0.09, g0_extended=True), phi3, u3),
+        (F.make_params(1, (40, 20, 12), bc=(0, 0, 1), wall_u=wu, A=0.04, kappa=0.09), phi3, u3),
+        (F.make_params(0, (70, 33, 1), A=0.04, kappa=0.09, g0_extended=True), phi2, None),
+        (F.make_params(0, (70, 33, 1), storage=F.FRE_FP16, A=0.04, kappa=0.09), phi2, None),
+    ]
+    steps = 11
+    solo = []
+    for p, phi0, u0 in specs:
+        L = F.Lattice(p, phi0, None, u0)
+        L.step(steps)
+        solo.append(L.populations())
+        L.close()
+    lats = [F.Lattice(p, phi0, None, u0) for p, phi0, u0 in specs]
+    w = f = 0
+    for L in lats:
+        a, b = F.Batch.needs(L)
+        w += a
+        f += b
+    B = F.Batch(max_slots=4, max_work=w, max_fill=f)
+    for L in lats:
+        B.add(L)
+    B.step(steps)          # graph replay on the batch's stream
+    for k, L in enumerate(lats):
+        fb, gb = L.populations()
+        assert np.array_equal(fb, solo[k][0]) and np.array_equal(gb, solo[k][1]), k
+    # the two D3Q19 FP32 members differ only in g0_extended, and their states do
+    assert not np.array_equal(lats[0].populations()[1], lats[1].populations()[1])
+    B.close()
+
+
 def test_refusals():
     shape = (16, 8, 1)
     phi0, _, _ = case_inputs(0, shape, radius=3, xi=1.5)
@@ -103,10 +139,4 @@ def test_refusals():
     with pytest.raises(F.FreError) as e:
         L.set_params(F.make_params(0, shape, A=0.04, kappa=0.09, g0_extended=False))
     assert e.value.status == F.FRE_EINVAL
-    w, f = F.Batch.needs(L)
-    B = F.Batch(max_slots=2, max_work=w, max_fill=f)
-    with pytest.raises(F.FreError) as e:
-        B.add(L)
-    assert e.value.status == F.FRE_EINVAL
-    B.close()
     L.close()
