@@ -8,6 +8,8 @@
   R=6.25) after 2000 steps: every field, and the Taylor deformation D
   computed the same way from both phi fields, within 1%.
 * FP16 storage on the copy: the deviation of phi, u and D is stated.
+* FP16 storage on the full lattice, stepped as the benchmark steps it: the
+  deviation after 20 steps is stated.
 """
 import sys
 import os
@@ -44,19 +46,39 @@ def _oracle(p_meta, phi0, u0):
     return O.Lattice(po, phi0, None, u0)
 
 
-def test_full_size_c3_in_bench_launch_configuration():
+@pytest.fixture(scope="module")
+def full_oracle():
+    p, phi0, u0, meta = bench.workload(0)
+    ref = _oracle(meta, phi0, u0)
+    ref.step(20)
+    return ref
+
+
+def test_full_size_c3_in_bench_launch_configuration(full_oracle):
     p, phi0, u0, meta = bench.workload(0)
     stream = torch.cuda.Stream()
     gpu = F.Lattice(p, phi0, None, u0, stream=stream)
+    gpu.autotune(3)
     gpu.step(20)
-    ref = _oracle(meta, phi0, u0)
-    ref.step(20)
+    ref = full_oracle
     err = field_errors(ref, gpu)
     pf, pg = pop_errors(ref, gpu)
     log("[parity] c3_full_20: " + " ".join(f"{k}={v:.2e}" for k, v in err.items()) + f" f={pf:.2e} g={pg:.2e}")
     for k, v in TOL.items():
         assert err[k] < v, (k, err[k])
     assert pf < 1e-5 and pg < 1e-5
+
+
+def test_full_size_c3_fp16_storage_error_stated(full_oracle):
+    p, phi0, u0, meta = bench.workload(1)
+    gpu = F.Lattice(p, phi0, None, u0, stream=torch.cuda.Stream())
+    gpu.autotune(3)
+    gpu.step(20)
+    err = field_errors(full_oracle, gpu)
+    log("[parity] c3_full_fp16_20: " + " ".join(f"{k}={v:.2e}" for k, v in err.items()))
+    # stated error of FP16 storage after 20 steps on the full lattice
+    assert err["phi"] < 5e-5 and err["u"] < 2e-5 and err["rho"] < 2e-5
+    gpu.close()
 
 
 def _copy_case(storage):
