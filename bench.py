@@ -256,7 +256,7 @@ def cpu_table() -> dict:
                                env=env, capture_output=True, text=True, check=True)
             rows.setdefault(name, {})[f"{th}t"] = json.loads(r.stdout.strip().splitlines()[-1])
             print(f"[cpu] {name} {th} threads: {rows[name][f'{th}t']}", file=sys.stderr, flush=True)
-    return {"threads_all": allc, "cases": rows}
+    return {"threads_all": allc, "cpu_model": cpu_model(), "nproc": os.cpu_count(), "cases": rows}
 
 
 def cpu_case(name: str, steps: int) -> dict:
@@ -294,6 +294,18 @@ def cpu_case(name: str, steps: int) -> dict:
     return {"MLUPS": round(n * steps / dt / 1e6, 3), "steps": steps, "seconds": round(dt, 2)}
 
 
+def cpu_model() -> str:
+    """The host CPU's model name, as the kernel reports it."""
+    try:
+        with open("/proc/cpuinfo") as fh:
+            for line in fh:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
 def cpu_baseline(p_gpu, phi0, u0, meta, steps=60):
     from oracle import oracle as O
     nx, ny, nz = meta["shape"]
@@ -305,7 +317,7 @@ def cpu_baseline(p_gpu, phi0, u0, meta, steps=60):
     dt = time.perf_counter() - t0
     cores = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
     return {"value": round(nx * ny * nz * steps / dt / 1e6, 3), "unit": "MLUPS", "cores": cores,
-            "kind": "oracle",
+            "kind": "oracle", "cpu_model": cpu_model(), "nproc": os.cpu_count(),
             "sample": f"{steps} steps of the full 256x128x128 D3Q19 lattice (FP64 oracle, OpenMP, {dt:.1f} s)"}
 
 
@@ -393,6 +405,7 @@ def main():
         "steps": args.steps,
         "warmup": args.warmup,
         "ms_per_step": round(r["ms"], 5),
+        "ms_per_step_min_max": [round(min(r["all_ms"]), 5), round(max(r["all_ms"]), 5)],
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
@@ -413,6 +426,7 @@ def main():
         m16 = r16["n"] / (r16["ms"] * 1e-3) / 1e6
         b16 = bytes_per_lu(19, 1)
         out["fp16_store"] = {"value": round(m16, 1), "unit": "MLUPS", "ms_per_step": round(r16["ms"], 5),
+                             "ms_per_step_min_max": [round(min(r16["all_ms"]), 5), round(max(r16["all_ms"]), 5)],
                              "bytes_per_lu": b16, "step_frac": round(m16 * 1e6 * b16 / 1e9 / PEAK_HBM_GBS, 4),
                              "kernels_ms": {k: round(v, 5) for k, v in r16["prof"].items()},
                              "launch_shape": {k: {"rows": v[0], "xcd": v[1]} for k, v in r16["shape"].items()}}
