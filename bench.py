@@ -178,7 +178,10 @@ def four_roller(steps: int = 200) -> dict:
     """The four-roller cell: D3Q19 256x256x64, all axes periodic, four
     staircase cylinders of radius 30 along z at the quarter points spinning in
     alternation, a drop of radius 24 in the centre (xi = 2, Re = 0.5,
-    Ca = 0.1).  17% of the cells are solid; MLUPS count fluid cells only."""
+    Ca = 0.1).  17% of the cells are solid; MLUPS count fluid cells only.
+    The roller speed is the stagnation-flow estimate (tip speed eps times
+    the gap from the centre to the rollers); the rate does not depend on it,
+    and the calibrated speed is used by campaign.four_roller_run."""
     import torch
     from paper_2212_01617_amd import frelbm as F
     from paper_2212_01617_amd import synth
