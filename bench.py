@@ -174,15 +174,8 @@ def g0_extended_rate(steps: int, warmup: int) -> dict:
             "kernels_ms": {k: round(v, 5) for k, v in prof.items()}}
 
 
-def four_roller(steps: int = 200) -> dict:
-    """The four-roller cell: D3Q19 256x256x64, all axes periodic, four
-    staircase cylinders of radius 30 along z at the quarter points spinning in
-    alternation, a drop of radius 24 in the centre (xi = 2, Re = 0.5,
-    Ca = 0.1).  17% of the cells are solid; MLUPS count fluid cells only.
-    The roller speed is the stagnation-flow estimate (tip speed eps times
-    the gap from the centre to the rollers); the rate does not depend on it,
-    and the calibrated speed is used by campaign.four_roller_run."""
-    import torch
+def four_roller_lattice(storage: int):
+    """Parameters, phi0 and mask of the four-roller workload (see four_roller)."""
     from paper_2212_01617_amd import frelbm as F
     from paper_2212_01617_amd import synth
     from paper_2212_01617_amd.params import derive_params
@@ -193,12 +186,27 @@ def four_roller(steps: int = 200) -> dict:
     sh = (nz, ny, nx)
     mask = synth.roller_mask(sh, cs, rr)
     phi0 = synth.droplet_phi(sh, 24.0, 2.0, noise=1e-4, seed=0)
+    p = F.make_params(F.FRE_D3Q19, (nx, ny, nz), storage=storage,
+                      rollers=[(c, sg * om, 2, rr) for c, sg in zip(cs, signs)], **dp.phys())
+    return p, phi0, mask
+
+
+def four_roller(steps: int = 200) -> dict:
+    """The four-roller cell: D3Q19 256x256x64, all axes periodic, four
+    staircase cylinders of radius 30 along z at the quarter points spinning in
+    alternation, a drop of radius 24 in the centre (xi = 2, Re = 0.5,
+    Ca = 0.1).  17% of the cells are solid; MLUPS count fluid cells only.
+    The roller speed is the stagnation-flow estimate (tip speed eps times
+    the gap from the centre to the rollers); the rate does not depend on it,
+    and the calibrated speed is used by campaign.four_roller_run."""
+    import torch
+    from paper_2212_01617_amd import frelbm as F
+    _, _, mask = four_roller_lattice(0)
     n_fluid = int((mask == 0).sum())
     out = {"workload": "D3Q19 four-roller cell 256x256x64, rollers r=30 along z, drop R=24, xi=2, Re=0.5, Ca=0.1",
            "fluid_cells": n_fluid}
     for storage, key in ((0, "fp32"), (1, "fp16")):
-        p = F.make_params(F.FRE_D3Q19, (nx, ny, nz), storage=storage,
-                          rollers=[(c, sg * om, 2, rr) for c, sg in zip(cs, signs)], **dp.phys())
+        p, phi0, mask = four_roller_lattice(storage)
         L = F.Lattice(p, phi0, None, None, mask, stream=torch.cuda.Stream())
         L.autotune(5)
         ms, _ = time_steps(L, steps, 20, 3)
@@ -336,6 +344,7 @@ def main():
     ap.add_argument("--serve", type=int, default=24, help="requests in the serving leg (0: skip)")
     ap.add_argument("--kernels-only", type=int, default=0)
     ap.add_argument("--storage", type=int, default=0, help="with --kernels-only: 0 FP32, 1 FP16")
+    ap.add_argument("--four-roller", action="store_true", help="with --kernels-only: the four-roller cell")
     ap.add_argument("--no-tune", action="store_true", help="keep the default launch shapes")
     ap.add_argument("--shape", default="", help="with --kernels-only: rows,xcd for k_moments, "
                     "k_potential, k_collide, e.g. 4,1,4,1,4,1 (default shapes if empty)")
@@ -370,8 +379,12 @@ def main():
         print(json.dumps({"mode": "serving-steady", **serving_steady()}), flush=True)
         return
     if args.kernels_only:
-        p, phi0, u0, meta = workload(args.storage)
-        L = F.Lattice(p, phi0, None, u0, stream=stream)
+        if args.four_roller:
+            p, phi0, mask = four_roller_lattice(args.storage)
+            L = F.Lattice(p, phi0, None, None, mask, stream=stream)
+        else:
+            p, phi0, u0, meta = workload(args.storage)
+            L = F.Lattice(p, phi0, None, u0, stream=stream)
         if args.shape:
             v = [int(t) for t in args.shape.split(",")]
             L.set_launch_shape({k: (v[2 * i], v[2 * i + 1]) for i, k in enumerate(L.STAGES)})
