@@ -16,7 +16,9 @@ Inputs are the seeded synthetic fields of ``synth`` and the parameter rule of
 sigma and xi, M from the Peclet number); the stored metadata records the
 parameters used, so a test can check that it rebuilds the same case.
 
-    python tests/golden/long_runs.py          # about 10 minutes on 8 cores
+    python tests/golden/long_runs.py          # about 25 minutes: the 3D case takes
+                                              # about 10 on 8 cores, the 2D one runs
+                                              # on one (the oracle threads over planes)
 """
 from __future__ import annotations
 
