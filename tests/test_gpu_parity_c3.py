@@ -10,6 +10,7 @@
 * FP16 storage on the copy: the deviation of phi, u and D is stated.
 * FP16 storage on the full lattice, stepped as the benchmark steps it: the
   deviation after 20 steps is stated.
+* The extended g_0 (FP32) on the full lattice after 20 steps, at the bar.
 """
 import sys
 import os
@@ -78,6 +79,21 @@ def test_full_size_c3_fp16_storage_error_stated(full_oracle):
     log("[parity] c3_full_fp16_20: " + " ".join(f"{k}={v:.2e}" for k, v in err.items()))
     # stated error of FP16 storage after 20 steps on the full lattice
     assert err["phi"] < 5e-5 and err["u"] < 2e-5 and err["rho"] < 2e-5
+    gpu.close()
+
+
+def test_full_size_c3_extended_g0(full_oracle):
+    p, phi0, u0, meta = bench.workload(0)
+    p.g0_extended = 1
+    gpu = F.Lattice(p, phi0, None, u0, stream=torch.cuda.Stream())
+    gpu.autotune(3)
+    gpu.step(20)
+    err = field_errors(full_oracle, gpu)
+    pf, pg = pop_errors(full_oracle, gpu)
+    log("[parity] c3_full_20_g0ext: " + " ".join(f"{k}={v:.2e}" for k, v in err.items()) + f" f={pf:.2e} g={pg:.2e}")
+    for k, v in TOL.items():
+        assert err[k] < v, (k, err[k])
+    assert pf < 1e-5 and pg < 1e-5
     gpu.close()
 
 
