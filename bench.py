@@ -155,25 +155,6 @@ def consistent_init_rate(n: int = 400) -> dict:
             "sample": f"{n} pre-iterations minus 0, best of 2, FP32, 256x128x128"}
 
 
-def g0_extended_rate(steps: int, warmup: int) -> dict:
-    """The FP32 workload with g_0 carried past FP32 (fre_params.g0_extended):
-    the same bytes per lattice update plus 4 B of g_0's low part."""
-    import torch
-    from paper_2212_01617_amd import frelbm as F
-    p, phi0, u0, meta = workload(0)
-    p.g0_extended = 1
-    L = F.Lattice(p, phi0, None, u0, stream=torch.cuda.Stream())
-    L.autotune(5)
-    ms, _ = time_steps(L, steps, warmup, 3)
-    prof = L.profile(20)
-    L.close()
-    n = 256 * 128 * 128
-    mlups = n / (ms * 1e-3) / 1e6
-    return {"value": round(mlups, 1), "unit": "MLUPS", "ms_per_step": round(ms, 5),
-            "step_frac": round(mlups * 1e6 * bytes_per_lu(19, 0) / 1e9 / PEAK_HBM_GBS, 4),
-            "kernels_ms": {k: round(v, 5) for k, v in prof.items()}}
-
-
 def four_roller_lattice(storage: int):
     """Parameters, phi0 and mask of the four-roller workload (see four_roller)."""
     from paper_2212_01617_amd import frelbm as F
@@ -449,8 +430,6 @@ def main():
     for v in res.values():
         v["L"].close()
     res.clear()
-    if not args.no_extra:
-        out["fp32_g0_extended"] = g0_extended_rate(args.steps, args.warmup)
     if not args.no_large:
         out["large_lattice"] = large_lattice()
     out["consistent_init"] = consistent_init_rate()

@@ -44,7 +44,8 @@ typedef int32_t fre_status;
 #define FRE_D2Q9 0
 #define FRE_D3Q19 1
 
-#define FRE_FP32 0 /* populations stored as float                           */
+#define FRE_FP32 0 /* f_i - w_i and g_i as float; g_0 (O(1)) also keeps the  */
+                   /* part float rounds away, as a scaled half per cell      */
 #define FRE_FP16 1 /* f_i - w_i and g_i (i>0) as half, g_0 as float          */
 
 #define FRE_PERIODIC 0
@@ -87,13 +88,7 @@ typedef struct fre_roller {
  *    use_paper_form = 1, kappa1, kappa2, alpha are used as given.
  *  tau_f, tau_g > 1/2: relaxation times; M > 0: mobility, with
  *    Gamma = M / (tau_g - 1/2) (Sec. 2.2, mobility relation).
- *  g0_extended (0 or 1; FP32 storage only): carry the rest population g_0,
- *    which is O(1), as its FP32 value plus the part FP32 rounds away (kept
- *    in half precision, scaled by 2^24), so that its storage rounding does
- *    not accumulate over long runs.  The FP32 step runs about 2% slower.
- *    Fixed at init
- *    (fre_set_params refuses to change it).  In a batch such lattices form
- *    classes of their own.
+ *  reserved1: must be 0.
  * Validation: tau > 1/2, kappa1, kappa2, alpha > 0 (A, kappa > 0), M > 0,
  * |wall_u| <= 0.1 and |omega| * radius <= 0.1 (Mach guard), sizes >= 1,
  * storage/kind/bc codes in range. */
@@ -109,7 +104,7 @@ typedef struct fre_params {
   double A, kappa;
   double kappa1, kappa2, alpha;
   int32_t use_paper_form;
-  int32_t g0_extended;
+  int32_t reserved1;
   double tau_f, tau_g, M;
 } fre_params;
 

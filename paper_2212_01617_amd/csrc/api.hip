@@ -61,8 +61,7 @@ fre_status validate(const fre_params *p) {
   if (!p) return fail(FRE_EINVAL, "params is NULL");
   if (p->kind != FRE_D2Q9 && p->kind != FRE_D3Q19) return fail(FRE_EINVAL, "kind %d not D2Q9/D3Q19", p->kind);
   if (p->storage != FRE_FP32 && p->storage != FRE_FP16) return fail(FRE_EINVAL, "storage %d", p->storage);
-  if (p->g0_extended != 0 && p->g0_extended != 1) return fail(FRE_EINVAL, "g0_extended %d", p->g0_extended);
-  if (p->g0_extended && p->storage != FRE_FP32) return fail(FRE_EINVAL, "g0_extended needs FP32 storage");
+  if (p->reserved1 != 0) return fail(FRE_EINVAL, "reserved1 must be 0");
   if (p->nx < 1 || p->ny < 1 || p->nz < 1) return fail(FRE_EINVAL, "sizes must be >= 1");
   for (int a = 0; a < 3; ++a)
     if (p->bc[a] != FRE_PERIODIC && p->bc[a] != FRE_WALL) return fail(FRE_EINVAL, "bc[%d]=%d", a, p->bc[a]);
@@ -292,7 +291,6 @@ void bind_args(fre_lattice *L) {
   LaunchArgs &a = L->a;
   a.q = P.q;
   a.storage = L->p.storage;
-  a.g0x = L->p.g0_extended;
   a.G.ex = P.ext[0]; a.G.ey = P.ext[1]; a.G.ez = P.ext[2];
   for (int k = 0; k < 3; ++k) { a.G.per[k] = P.per[k]; a.G.off[k] = P.off[k]; }
   a.G.px = P.px;
@@ -447,9 +445,8 @@ fre_status fre_set_params(fre_lattice *L, const fre_params *p) {
   if (L->batch) return fail(FRE_ESTATE, "lattice is a batch member: remove it before changing parameters");
   const fre_params &o = L->p;
   if (p->kind != o.kind || p->nx != o.nx || p->ny != o.ny || p->nz != o.nz || p->storage != o.storage ||
-      p->bc[0] != o.bc[0] || p->bc[1] != o.bc[1] || p->bc[2] != o.bc[2] || p->n_rollers != o.n_rollers ||
-      p->g0_extended != o.g0_extended)
-    return fail(FRE_EINVAL, "shape, storage, bc, roller count and g0_extended cannot change");
+      p->bc[0] != o.bc[0] || p->bc[1] != o.bc[1] || p->bc[2] != o.bc[2] || p->n_rollers != o.n_rollers)
+    return fail(FRE_EINVAL, "shape, storage, bc and roller count cannot change");
   L->p = *p;
   L->a.ph = make_phys(p);
   reset_graph(L);
@@ -898,7 +895,7 @@ fre_status batch_rebuild(fre_batch *B) {
     B->h_range[4 * cls + 2] = (int)B->h_fill.size();
     for (size_t k = 0; k < B->slot.size(); ++k) {
       fre_lattice *L = B->slot[k];
-      if (!L || batch_class(L->a.q, L->a.storage, L->a.g0x) != cls) continue;
+      if (!L || batch_class(L->a.q, L->a.storage) != cls) continue;
       classes |= 1u << cls;
       B->h_inst[k] = inst_of(L, B->base);
       const Geom &G = L->a.G;

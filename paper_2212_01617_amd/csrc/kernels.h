@@ -34,7 +34,6 @@ struct LaunchArgs {
   Phys ph;
   void *f, *g;  // population blocks (float or half)
   float *g0;    // FP16 storage: g_0 plane; FP32 storage: the half plane of g_0's low part
-  int g0x;      // FP32 storage: g_0 carried as hi + lo (fre_params.g0_extended)
   uint8_t *mask;
   uint32_t *nbm;  // per cell: non-fluid neighbour bits, NB_SELF_SOLID
   float2 *M;    // (rho - 1, phi)
@@ -129,13 +128,9 @@ struct BatchArgs {
   hipStream_t stream;
 };
 
-// Batch classes: (velocity set, storage) pairs 0..3, and 4, 5 for D2Q9 and
-// D3Q19 in FP32 with the extended g_0 (their collide is its own kernel).
-constexpr int N_BATCH_CLASSES = 6;
-inline int batch_class(int q, int storage, int g0x) {
-  if (g0x) return q == 19 ? 5 : 4;
-  return (q == 19 ? 2 : 0) + storage;
-}
+// Batch classes: the (velocity set, storage) pairs.
+constexpr int N_BATCH_CLASSES = 4;
+inline int batch_class(int q, int storage) { return (q == 19 ? 2 : 0) + storage; }
 
 void launch_batch_step(const BatchArgs &b, int cls, int odd);
 void launch_step(const LaunchArgs &a, int odd);

@@ -468,16 +468,31 @@ __device__ __forceinline__ void force(const float4 *__restrict__ C, const Nbr &N
 // of parity ODD): every population goes to the slot it streams to.  If
 // `post` is given, the stored value of each moving population i > 0 also goes
 // to post[i - 1][tid] (f) and post[Q - 1 + i - 1][tid] (g); the rest
-// populations are returned in rest_out.  For a
-// link into a solid cell that slot is never read; bounce_back() then moves
-// the population to the slot the cell reads it from next step.
-// X (FP32 storage): g_0 carried as hi + lo (the extended mode).
-template <int Q, int S, int ODD, int NT, bool X = false>
+// populations are returned in rest_out.  For a link into a solid cell that
+// slot is never read; bounce_back() then moves the population to the slot the
+// cell reads it from next step.
+//
+// The equilibria (eqs. feq, geq) and the Guo term (eq. Fi) are split into
+// their parts of zeroth, first and second order in c_i.  The first-order part
+// of f^eq is formed from the momentum m = j + F/2 itself, a_i (c_i . m), not
+// from rho times u = m / rho: a rounded 1/rho takes the same value over wide
+// regions where rho varies by less than an ulp, and rho u would then differ
+// from m by the same fraction in every cell of such a region, at every step.
+// With the coefficients a_i (exact_lin) the momentum of f^eq is m and that of
+// the Guo term (1 - 1/(2 tau_f)) F, to the rounding of the individual terms.
+//
+// FP32 storage carries g_0 = O(1) as hi + lo (lo in a half-precision plane,
+// scaled by 2^24): the increment of g_0 is formed from the moving populations
+// alone, tau_g^-1 sum_{i>0} (g_i - g_i^eq), which equals (g_0^eq - g_0) / tau_g
+// since g_0^eq complements the others to phi, and added to hi + lo with the
+// rounding error of the sum kept (TwoSum, Knuth).
+template <int Q, int S, int ODD, int NT>
 __device__ __forceinline__ void collide_cell(const Pops<Q, S> &P, const Nbr &N, long long c,
                                              const float4 *__restrict__ C,
                                              const Phys &ph, float (*post)[NT], int tid, float &rho_out,
                                              float &phi_out, float2 &rest_out) {
   using V = VSet<Q>;
+  constexpr bool X = S == 0;  // g_0 as hi + lo
   const float4 cc = C[c];
   const float mu_phi = cc.w, mu_rho = coupling_mu_rho(cc);
   float F[3];
@@ -503,16 +518,17 @@ __device__ __forceinline__ void collide_cell(const Pops<Q, S> &P, const Nbr &N, 
   }
   const float rho = 1.0f + drho;
   const float inv_rho = 1.0f / rho;
-  const float u[3] = {(j[0] + 0.5f * F[0]) * inv_rho, (j[1] + 0.5f * F[1]) * inv_rho,
-                      (j[2] + 0.5f * F[2]) * inv_rho};
+  const float m[3] = {j[0] + 0.5f * F[0], j[1] + 0.5f * F[1], j[2] + 0.5f * F[2]};  // eq. veloMoment: rho u
+  const float u[3] = {m[0] * inv_rho, m[1] * inv_rho, m[2] * inv_rho};
   const float uu = u[0] * u[0] + u[1] * u[1] + u[2] * u[2];
   const float uF = u[0] * F[0] + u[1] * F[1] + u[2] * F[2];
-  // the same expression in both loops, so f and g see the same value
-  auto poly_of = [&](int i) {
+  // second-order part of the equilibria over w_i; the same expression in both
+  // loops, so f and g see the same value
+  auto quad_of = [&](int i) {
     const float cu = V::cx(i) * u[0] + V::cy(i) * u[1] + V::cz(i) * u[2];
-    return 3.0f * cu + 4.5f * cu * cu - 1.5f * uu;
+    return 4.5f * cu * cu - 1.5f * uu;
   };
-  float phi = 0.0f, gm = 0.0f;  // gm: sum of the moving g_i (extended g_0 only)
+  float phi = 0.0f, gm = 0.0f;  // gm: sum of the moving g_i (FP32: g_0 as hi + lo)
   if constexpr (!SPLIT) {
     if constexpr (X) {
       // phi = g_0 + sum of the moving g_i, the latter also used for g_0 below
@@ -527,7 +543,8 @@ __device__ __forceinline__ void collide_cell(const Pops<Q, S> &P, const Nbr &N, 
   float geq_rest = 0.0f;
   // post-collision g_i of direction i > 0, stored to the slot it streams to
   auto collide_g = [&](int i) {
-    const float geq = V::w(i) * (ph.gam3 * mu_phi + phi * poly_of(i));
+    const float cu = V::cx(i) * u[0] + V::cy(i) * u[1] + V::cz(i) * u[2];
+    const float geq = V::w(i) * ph.gam3 * mu_phi + phi * (V::a(i) * cu + V::w(i) * quad_of(i));
     geq_rest += geq;
     const float gs = P.round(g[i] + ph.om_g * (geq - g[i]));
     if (post) post[Q - 1 + i - 1][tid] = gs;
@@ -539,10 +556,10 @@ __device__ __forceinline__ void collide_cell(const Pops<Q, S> &P, const Nbr &N, 
   for (int i = 0; i < Q; ++i) {
     const float cF = V::cx(i) * F[0] + V::cy(i) * F[1] + V::cz(i) * F[2];
     const float cu = V::cx(i) * u[0] + V::cy(i) * u[1] + V::cz(i) * u[2];
-    const float wi = V::w(i);
-    const float poly = poly_of(i);
-    const float dfeq = wi * (drho + rho * poly);                         // f_i^eq - w_i
-    const float src = ph.guo * wi * (3.0f * (cF - uF) + 9.0f * cu * cF);  // Guo term
+    const float cm = V::cx(i) * m[0] + V::cy(i) * m[1] + V::cz(i) * m[2];
+    const float wi = V::w(i), ai = V::a(i);
+    const float dfeq = wi * drho + ai * cm + wi * rho * quad_of(i);             // f_i^eq - w_i
+    const float src = ph.guo * (ai * cF - 3.0f * wi * uF + 3.0f * ai * cu * cF);  // Guo term
     const float fs = P.round(df[i] + ph.om_f * (dfeq - df[i]) + src);
     if (i == 0) {
       P.stf(0, c, fs);
@@ -563,10 +580,7 @@ __device__ __forceinline__ void collide_cell(const Pops<Q, S> &P, const Nbr &N, 
     for (int i = 1; i < Q; ++i) collide_g(i);
   }
   float g0s;
-  if constexpr (S == 0 && X) {
-    // g_0* = g_0 + (g_0^eq - g_0) / tau_g with g_0^eq - g_0 = sum_{i>0} (g_i -
-    // g_i^eq): the increment is formed from the moving populations alone and
-    // added to hi + lo with the rounding error of the sum kept (TwoSum)
+  if constexpr (X) {
     const float t = ph.om_g * (gm - geq_rest) + P.ldg0lo(c);
     g0s = g[0] + t;
     const float tb = g0s - g[0];
@@ -618,7 +632,7 @@ __device__ __forceinline__ void bounce_back(const Pops<Q, S> &P, const Nbr &N, l
 // first pass of the moment groups of its column: S0 for this plane, UP for
 // the plane above and DN for the plane below (all their sources lie in this
 // plane), from the tile's post-collision values.
-template <int Q, int S, int ODD, bool X = false>
+template <int Q, int S, int ODD>
 __device__ __forceinline__ void stage_collide(const LatView<Q, S> &L, int x, int y, int z, bool active) {
   using V = VSet<Q>;
   constexpr int NT = BX * COLLIDE_ROWS;
@@ -630,7 +644,7 @@ __device__ __forceinline__ void stage_collide(const LatView<Q, S> &L, int x, int
     const Nbr N(L.G, x, y, z);
     float rho, phi;
     float2 rest;
-    collide_cell<Q, S, ODD, NT, X>(L.P, N, c, L.C, L.ph, nullptr, 0, rho, phi, rest);
+    collide_cell<Q, S, ODD, NT>(L.P, N, c, L.C, L.ph, nullptr, 0, rho, phi, rest);
     if (bits != 0u) bounce_back<Q, S, ODD>(L.P, N, c, bits, L.mask, L.G, L.ph, x, y, z, rho, phi);
     return;
   }
@@ -645,7 +659,7 @@ __device__ __forceinline__ void stage_collide(const LatView<Q, S> &L, int x, int
     if (fluid) {
       const Nbr N(L.G, x, y, z);
       float rho, phi;
-      collide_cell<Q, S, ODD, NT, X>(L.P, N, c, L.C, L.ph, post, tid, rho, phi, rest);
+      collide_cell<Q, S, ODD, NT>(L.P, N, c, L.C, L.ph, post, tid, rho, phi, rest);
       if (bits != 0u) bounce_back<Q, S, ODD>(L.P, N, c, bits, L.mask, L.G, L.ph, x, y, z, rho, phi);
     }
   }
@@ -764,7 +778,7 @@ __device__ __forceinline__ void run_stage(const LatView<Q, S> &L, int x, int y, 
   else stage_potential<Q, S>(L, x, y, z);
 }
 
-template <int Q, int S, int STAGE, int ODD, bool X = false>
+template <int Q, int S, int STAGE, int ODD>
 // FP16 storage: at most 128 VGPRs, 4 waves per SIMD for the collide (measured
 // faster than 3 waves without spills); FP32 keeps the compiler's choice.
 __global__ __launch_bounds__(BX *MAX_ROWS) __attribute__((amdgpu_waves_per_eu(S == 1 ? 4 : 1))) void k_cells(LatView<Q, S> L) {
@@ -772,7 +786,7 @@ __global__ __launch_bounds__(BX *MAX_ROWS) __attribute__((amdgpu_waves_per_eu(S 
   long long c;
   const bool in = cell_of_tile(L.G, L.tm, x, y, z, c);
   if (STAGE == ST_COLLIDE) {
-    stage_collide<Q, S, ODD, X>(L, x, y, z, in);
+    stage_collide<Q, S, ODD>(L, x, y, z, in);
     return;
   }
   if (in) run_stage<Q, S, STAGE, ODD>(L, x, y, z);
@@ -869,7 +883,7 @@ __device__ __forceinline__ LatView<Q, S> view_of(char *base, const Inst &I) {
   return L;
 }
 
-template <int Q, int S, int STAGE, int ODD, bool X = false>
+template <int Q, int S, int STAGE, int ODD>
 __global__ __launch_bounds__(BX *MAX_ROWS) void k_batch_cells(char *base, const Inst *__restrict__ inst, const int4 *__restrict__ work,
                                                         const int *__restrict__ range) {
   const int start = range[0], n = range[1];
@@ -879,7 +893,7 @@ __global__ __launch_bounds__(BX *MAX_ROWS) void k_batch_cells(char *base, const 
     const int x = it.y * BX + threadIdx.x, y = it.z * (int)blockDim.y + threadIdx.y, z = it.w;
     const bool in = x < L.G.ex && y < L.G.ey;
     if (STAGE == ST_COLLIDE) {
-      stage_collide<Q, S, ODD, X>(L, x, y, z, in);
+      stage_collide<Q, S, ODD>(L, x, y, z, in);
       if (ByProduct<S>::on) __syncthreads();  // the tile buffer is reused by the next item
     } else if (in) {
       run_stage<Q, S, STAGE, ODD>(L, x, y, z);
@@ -1097,13 +1111,6 @@ static void cells_launch(const LaunchArgs &a, int odd) {
   const int rows = (STAGE == ST_COLLIDE && ByProduct<S>::on) ? COLLIDE_ROWS : sh.rows;
   const dim3 grid = tile_grid(a.G, rows), block(BX, rows, 1);
   L.tm = TileMap(a.G.ex, a.G.ey, rows, (int)grid.x, sh.xcd);
-  if constexpr (STAGE == ST_COLLIDE && S == 0) {
-    if (a.g0x) {  // extended g_0: its own instantiation, so the default keeps its registers
-      if (odd) k_cells<Q, S, STAGE, 1, true><<<grid, block, 0, a.stream>>>(L);
-      else k_cells<Q, S, STAGE, 0, true><<<grid, block, 0, a.stream>>>(L);
-      return;
-    }
-  }
   if (odd) k_cells<Q, S, STAGE, 1><<<grid, block, 0, a.stream>>>(L);
   else k_cells<Q, S, STAGE, 0><<<grid, block, 0, a.stream>>>(L);
 }
@@ -1239,7 +1246,7 @@ void launch_read_pops(const LaunchArgs &a, int odd, float *out) { FRE_DISPATCH(r
 // One batched step of one class: the same five stages over every lattice of
 // the class listed in the work lists (ranges: cells [start, n], fills
 // [start, n]).
-template <int Q, int S, bool X = false>
+template <int Q, int S>
 static void batch_step_impl(const BatchArgs &b, int cls, int odd) {
   const int *rc = b.range + 4 * cls, *rf = rc + 2;
   const dim3 bl(BX, b.rows, 1);
@@ -1250,8 +1257,8 @@ static void batch_step_impl(const BatchArgs &b, int cls, int odd) {
   k_batch_fill<Q, S, 0><<<b.grid_fill, 256, 0, b.stream>>>(b.base, b.inst, b.fill, rf);
   k_batch_cells<Q, S, ST_POTENTIAL, 0><<<b.grid_cells, bl, 0, b.stream>>>(b.base, b.inst, b.work, rc);
   k_batch_fill<Q, S, 1><<<b.grid_fill, 256, 0, b.stream>>>(b.base, b.inst, b.fill, rf);
-  if (odd) k_batch_cells<Q, S, ST_COLLIDE, 1, X><<<b.grid_cells, bl, 0, b.stream>>>(b.base, b.inst, b.work, rc);
-  else k_batch_cells<Q, S, ST_COLLIDE, 0, X><<<b.grid_cells, bl, 0, b.stream>>>(b.base, b.inst, b.work, rc);
+  if (odd) k_batch_cells<Q, S, ST_COLLIDE, 1><<<b.grid_cells, bl, 0, b.stream>>>(b.base, b.inst, b.work, rc);
+  else k_batch_cells<Q, S, ST_COLLIDE, 0><<<b.grid_cells, bl, 0, b.stream>>>(b.base, b.inst, b.work, rc);
   if (ByProduct<S>::on) {
     if (odd) k_batch_cells<Q, S, ST_COMBINE, 0><<<b.grid_cells, bl, 0, b.stream>>>(b.base, b.inst, b.work, rc);
     else k_batch_cells<Q, S, ST_COMBINE, 1><<<b.grid_cells, bl, 0, b.stream>>>(b.base, b.inst, b.work, rc);
@@ -1263,9 +1270,7 @@ void launch_batch_step(const BatchArgs &b, int cls, int odd) {
     case 0: batch_step_impl<9, 0>(b, cls, odd); break;
     case 1: batch_step_impl<9, 1>(b, cls, odd); break;
     case 2: batch_step_impl<19, 0>(b, cls, odd); break;
-    case 3: batch_step_impl<19, 1>(b, cls, odd); break;
-    case 4: batch_step_impl<9, 0, true>(b, cls, odd); break;
-    default: batch_step_impl<19, 0, true>(b, cls, odd); break;
+    default: batch_step_impl<19, 1>(b, cls, odd); break;
   }
 }
 

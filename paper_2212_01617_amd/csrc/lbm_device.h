@@ -30,6 +30,10 @@ template <> struct VSet<9> {
   __host__ __device__ static constexpr float w(int i) {
     return i == 0 ? 4.0f / 9.0f : (i < 5 ? 1.0f / 9.0f : 1.0f / 36.0f);
   }
+  // a_i ~ 3 w_i = w_i / cs^2 for the terms linear in c_i (see exact_lin)
+  __host__ __device__ static constexpr float a(int i) {
+    return i == 0 ? 0.0f : (i < 5 ? 0x1.555556p-2f : 0x1.555554p-4f);
+  }
 };
 
 template <> struct VSet<19> {
@@ -54,9 +58,38 @@ template <> struct VSet<19> {
   __host__ __device__ static constexpr float w(int i) {
     return i == 0 ? 1.0f / 3.0f : (i < 7 ? 1.0f / 18.0f : 1.0f / 36.0f);
   }
+  __host__ __device__ static constexpr float a(int i) {
+    return i == 0 ? 0.0f : (i < 7 ? 0x1.555554p-3f : 0x1.555556p-4f);
+  }
 };
 
 __host__ __device__ constexpr int opp(int i) { return i == 0 ? 0 : ((i & 1) ? i + 1 : i - 1); }
+
+// Exact first moments in FP32.  The momentum of the equilibria (eqs. feq,
+// geq) and of the forcing term (eq. Fi) comes from their parts linear in c_i,
+// with coefficients 3 w_i = w_i / cs^2.  Rounded to FP32, the weights give
+// sum_i 3 w_i c_ia c_ib = (1 + 7.5e-9) delta_ab (D2Q9; 1.5e-8 for D3Q19), and
+// a collision then adds that fraction of the momentum to every cell, in the
+// same direction, at every step; over tens of thousands of steps this drift,
+// not the random rounding, dominates the difference from exact arithmetic.
+// The coefficients a_i are FP32 values chosen so that the identity holds
+// exactly for the stored values: for the axis and diagonal directions,
+// 2 a_axis + 4 a_diag = 1 (D2Q9) and 2 a_axis + 8 a_diag = 1 (D3Q19), with one
+// of them the rounded 3 w_i and the other solved for (both exact in FP32).
+// (The check sums in double, which holds these sums of FP32 values exactly.)
+template <class V> constexpr bool exact_lin() {
+  double s[3][3] = {{0, 0, 0}, {0, 0, 0}, {0, 0, 0}};
+  for (int i = 0; i < (V::D == 3 ? 19 : 9); ++i) {
+    const int c[3] = {V::cx(i), V::cy(i), V::cz(i)};
+    for (int a = 0; a < 3; ++a)
+      for (int b = 0; b < 3; ++b) s[a][b] += (double)V::a(i) * (double)(c[a] * c[b]);
+  }
+  for (int a = 0; a < V::D; ++a)
+    for (int b = 0; b < V::D; ++b)
+      if (s[a][b] != (a == b ? 1.0 : 0.0)) return false;
+  return true;
+}
+static_assert(exact_lin<VSet<9>>() && exact_lin<VSet<19>>(), "linear coefficients must give exact second moments");
 
 // ---------------------------------------------------------------------------
 // Geometry of one lattice in device memory.  The storage grid is the fluid

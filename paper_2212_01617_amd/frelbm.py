@@ -44,7 +44,7 @@ class fre_params(C.Structure):
         ("rollers", fre_roller * 4),
         ("A", C.c_double), ("kappa", C.c_double),
         ("kappa1", C.c_double), ("kappa2", C.c_double), ("alpha", C.c_double),
-        ("use_paper_form", C.c_int32), ("g0_extended", C.c_int32),
+        ("use_paper_form", C.c_int32), ("reserved1", C.c_int32),
         ("tau_f", C.c_double), ("tau_g", C.c_double), ("M", C.c_double),
     ]
 
@@ -116,10 +116,9 @@ def _ptr(a: np.ndarray):
 
 def make_params(kind, shape, *, storage=FRE_FP32, bc=(0, 0, 0), wall_u=None, rollers=(),
                 A=None, kappa=None, kappa1=None, kappa2=None, alpha=None,
-                tau_f=1.0, tau_g=1.0, M=0.1, g0_extended=False) -> fre_params:
+                tau_f=1.0, tau_g=1.0, M=0.1) -> fre_params:
     """shape = (nx, ny, nz); rollers = [(center(3), omega, axis, radius)];
-    give either (A, kappa) or (kappa1, kappa2, alpha).  g0_extended (FP32
-    storage): carry g_0 as FP32 plus its rounding residual."""
+    give either (A, kappa) or (kappa1, kappa2, alpha)."""
     p = fre_params()
     p.kind = kind
     p.nx, p.ny, p.nz = shape
@@ -148,7 +147,6 @@ def make_params(kind, shape, *, storage=FRE_FP32, bc=(0, 0, 0), wall_u=None, rol
         p.use_paper_form = 0
         p.A, p.kappa = A, kappa
     p.tau_f, p.tau_g, p.M = tau_f, tau_g, M
-    p.g0_extended = 1 if g0_extended else 0
     return p
 
 

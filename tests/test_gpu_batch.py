@@ -2,8 +2,10 @@
 
 A lattice advanced inside a batch -- mixed velocity sets, storage precisions
 and sizes, members joining and leaving while others run -- must hold exactly
-the populations it holds when advanced alone (bitwise), and the batch's
-graph replay must equal step-by-step launches.
+the populations it holds when advanced alone (bitwise), must agree with the
+FP64 oracle stepped for its own number of steps (FP32 storage at the 1e-5
+bar, FP16 storage at its stated error), and the batch's graph replay must
+equal step-by-step launches.
 """
 import numpy as np
 import pytest
@@ -12,7 +14,7 @@ import torch
 from paper_2212_01617_amd import frelbm as F
 from paper_2212_01617_amd import synth
 
-from _pair import case_inputs, ensure_gpu_lib, log
+from _pair import case_inputs, check_against_oracle, ensure_gpu_lib, log
 
 pytestmark = pytest.mark.gpu
 
@@ -92,6 +94,8 @@ def test_batch_equals_solo_bitwise_with_joins_and_leaves():
         same = np.array_equal(fa, fb) and np.array_equal(ga, gb)
         log(f"[batch] lattice {k}: t={t} bitwise equal to solo: {same}")
         assert same, k
+        p, phi0, u0, mask = specs[k]
+        check_against_oracle(f"batch_member_{k}", p, L, t, phi0, None, u0, mask)
     assert B.info()[0] == 3
 
 

@@ -1,21 +1,20 @@
 """Parity over the long horizons of the shear cases, against the FP64
-oracle's end states stored by ``tests/golden/long_runs.py``:
+oracle's end states stored by ``tests/golden/long_runs.py``, with the lattice
+stepped as the benchmark steps it (own stream, captured graphs):
 
-* the 64x32x32 D3Q19 copy of the 3D shear case after 20,000 steps: u at the
-  1e-5 bar and the Taylor deformation D from both phi fields within 1%
-  (observed 3.3e-8 and 1.9e-5 relative).  Its max-abs phi difference, 1.4e-5
-  at the interface, is stated and held to 3e-5: single-precision storage
-  alone moves this case that far (the FP64 oracle with only its stored g_0
-  rounded to FP32 each step ends 4.4e-5 from the exact run in phi).  With
-  g_0 carried past FP32 (g0_extended) phi, u and D all meet the bar;
-* the 400x200 D2Q9 parallel-band shear after 40,000 steps: u at the 1e-5
-  bar and D within 1% (observed 7.0e-7 and 1.0e-3 relative).  Its phi
-  difference, 1.1e-3, is stated and held to 2e-3: the FP32 collision
-  conserves momentum only to rounding, and in this 200-cell channel
-  (viscous time about 240k steps) the velocity difference grows with time,
-  so the interface position, its time integral, drifts apart faster.
+* the 64x32x32 D3Q19 copy of the 3D shear case after 20,000 steps: phi and u
+  at the 1e-5 bar and the Taylor deformation D from both phi fields within
+  1%;
+* the 400x200 D2Q9 parallel-band shear after 40,000 steps: u at the bar and
+  D within 1%; the max-abs phi difference is stated and held near what was
+  measured;
+* FP16 storage on both: the deviations are stated and held near what was
+  measured, so that a regression of the FP16 path fails.
 
-Both are stepped as the benchmark steps (own stream, captured graphs)."""
+Why the 2D case keeps a phi difference above 1e-5: this 200-cell channel's
+viscous time (about 240,000 steps) is far longer than the run, so rounding
+differences of the FP32 collision that are the same from step to step are
+not damped, and the interface position integrates them."""
 import os
 import sys
 
@@ -45,7 +44,7 @@ def golden():
     return long_runs.load()
 
 
-def _run(name, golden, g0_extended=False):
+def _run(name, golden, storage=F.FRE_FP32):
     meta, arrays = golden
     c = long_runs.case(name)
     m = meta[name]
@@ -53,7 +52,7 @@ def _run(name, golden, g0_extended=False):
     for k, v in c["phys"].items():
         assert m["phys"][k] == v, (name, k)
     assert np.array_equal(np.asarray(m["wall_u"]), np.asarray(c["wall_u"]))
-    p = F.make_params(c["kind"], c["shape"], bc=c["bc"], wall_u=c["wall_u"], g0_extended=g0_extended, **c["phys"])
+    p = F.make_params(c["kind"], c["shape"], storage=storage, bc=c["bc"], wall_u=c["wall_u"], **c["phys"])
     gpu = F.Lattice(p, c["phi0"], None, c["u0"], stream=torch.cuda.Stream())
     gpu.step(c["steps"])
     out = gpu.read(("phi", "u"))
@@ -64,7 +63,8 @@ def _run(name, golden, g0_extended=False):
     d_ref = Dg.deformation(arrays[f"{name}__phi"].astype(np.float64), plane=c["plane"], periodic=c["periodic"]).D
     d_gpu = Dg.deformation(out["phi"], plane=c["plane"], periodic=c["periodic"]).D
     rel = abs(d_gpu - d_ref) / abs(d_ref)
-    log(f"[parity] {name}_{c['steps']}{'_g0ext' if g0_extended else ''}: phi={err['phi']:.2e} u={err['u']:.2e} "
+    tag = "_fp16" if storage == F.FRE_FP16 else ""
+    log(f"[parity] {name}{tag}_{c['steps']}: phi={err['phi']:.2e} u={err['u']:.2e} "
         f"D_oracle={d_ref:.5f} D_gpu={d_gpu:.5f} rel={rel:.2e}")
     assert d_ref > 1e-2
     return err, rel
@@ -72,25 +72,26 @@ def _run(name, golden, g0_extended=False):
 
 def test_c3_copy_20000_steps(golden):
     err, rel = _run("c3_copy", golden)
-    assert err["u"] < 1e-5 and rel < 0.01
-    assert err["phi"] < 3e-5
-
-
-def test_c3_copy_20000_steps_extended_g0(golden):
-    err, rel = _run("c3_copy", golden, g0_extended=True)
     assert err["phi"] < 1e-5 and err["u"] < 1e-5 and rel < 0.01
 
 
 def test_shear_2d_40000_steps(golden):
     err, rel = _run("shear_2d", golden)
     assert err["u"] < 1e-5 and rel < 0.01
-    assert err["phi"] < 2e-3
+    # measured: phi 2.0e-5; held at 2x
+    assert err["phi"] < 4e-5
 
 
-def test_shear_2d_40000_steps_extended_g0(golden):
-    """With g_0 carried past FP32 the 2D shear's phi difference at 40,000
-    steps falls from 1.1e-3 to about 4e-4 (stated, held to 1e-3); the rest is
-    the momentum drift of the FP32 collision."""
-    err, rel = _run("shear_2d", golden, g0_extended=True)
-    assert err["u"] < 1e-5 and rel < 0.01
-    assert err["phi"] < 1e-3
+def test_c3_copy_20000_steps_fp16(golden):
+    err, rel = _run("c3_copy", golden, storage=F.FRE_FP16)
+    # measured: phi 1.1e-4, u 4.1e-6, D 3.4e-4 relative; held at about 3x
+    assert err["phi"] < 3.5e-4 and err["u"] < 1.2e-5 and rel < 1e-3
+
+
+def test_shear_2d_40000_steps_fp16(golden):
+    err, rel = _run("shear_2d", golden, storage=F.FRE_FP16)
+    # measured: phi 6.3e-2, u 3.2e-4, D 16% low.  Half-precision storage
+    # rounds every population at about 5e-4 relative each step; in this
+    # slow channel the rounding of the steady parts of the flow repeats
+    # from step to step and is not damped within the run.  Held at 2x.
+    assert err["phi"] < 0.13 and err["u"] < 6.5e-4 and rel < 0.33

@@ -215,4 +215,5 @@ def test_fp16_storage_error_stated():
                         A=5.89e-3, kappa=2.36e-2, tau_f=1.0, tau_g=1.75, M=5.26)
     err = field_errors(ref, gpu)
     log("[parity] fp16_storage: " + " ".join(f"{k}={v:.2e}" for k, v in err.items()))
-    assert err["phi"] < 5e-3 and err["u"] < 5e-4 and err["rho"] < 5e-4
+    # measured: phi 7.8e-6, u 4.5e-6, rho 5.3e-6; held at about 3x
+    assert err["phi"] < 2.5e-5 and err["u"] < 1.5e-5 and err["rho"] < 1.6e-5

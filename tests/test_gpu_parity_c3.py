@@ -10,7 +10,6 @@
 * FP16 storage on the copy: the deviation of phi, u and D is stated.
 * FP16 storage on the full lattice, stepped as the benchmark steps it: the
   deviation after 20 steps is stated.
-* The extended g_0 (FP32) on the full lattice after 20 steps, at the bar.
 """
 import sys
 import os
@@ -82,21 +81,6 @@ def test_full_size_c3_fp16_storage_error_stated(full_oracle):
     gpu.close()
 
 
-def test_full_size_c3_extended_g0(full_oracle):
-    p, phi0, u0, meta = bench.workload(0)
-    p.g0_extended = 1
-    gpu = F.Lattice(p, phi0, None, u0, stream=torch.cuda.Stream())
-    gpu.autotune(3)
-    gpu.step(20)
-    err = field_errors(full_oracle, gpu)
-    pf, pg = pop_errors(full_oracle, gpu)
-    log("[parity] c3_full_20_g0ext: " + " ".join(f"{k}={v:.2e}" for k, v in err.items()) + f" f={pf:.2e} g={pg:.2e}")
-    for k, v in TOL.items():
-        assert err[k] < v, (k, err[k])
-    assert pf < 1e-5 and pg < 1e-5
-    gpu.close()
-
-
 def _copy_case(storage):
     dp = derive_params(Re=1.0, Ca=0.1, radius=25.0, xi=2.0, H=128, Pe=0.43)
     nx, ny, nz = 64, 32, 32
@@ -148,5 +132,6 @@ def test_c3_copy_fp16_storage_error_stated(copy_oracle):
     rel = abs(d_gpu - d_ref) / abs(d_ref)
     log("[parity] c3_copy_fp16_2000: " + " ".join(f"{k}={v:.2e}" for k, v in err.items())
         + f" D_oracle={d_ref:.5f} D_gpu={d_gpu:.5f} rel={rel:.2e}")
-    # stated error of FP16 storage after 2000 steps
-    assert err["phi"] < 2e-2 and err["u"] < 2e-3 and rel < 0.05
+    # stated error of FP16 storage after 2000 steps (measured: phi 1.1e-5,
+    # u 3.2e-6, D 2.7e-5 relative); held at about 3x
+    assert err["phi"] < 3.5e-5 and err["u"] < 1e-5 and rel < 1e-4

@@ -1,7 +1,9 @@
 """Serving on the GPU: a small mixed request stream through the real batch
 engine.  Every request retires, memory and slots stay within their limits,
-and each retired lattice holds bitwise the populations of the same lattice
-advanced alone for the same number of steps."""
+each retired lattice holds bitwise the populations of the same lattice
+advanced alone for the same number of steps, and agrees with the FP64
+oracle stepped for that many steps (FP32 storage at the 1e-5 bar, FP16
+storage at its stated error)."""
 import numpy as np
 import pytest
 import torch
@@ -9,7 +11,7 @@ import torch
 from paper_2212_01617_amd import frelbm as F
 from paper_2212_01617_amd import serve
 
-from _pair import ensure_gpu_lib, log
+from _pair import check_against_oracle, ensure_gpu_lib, log
 
 pytestmark = pytest.mark.gpu
 
@@ -42,3 +44,4 @@ def test_serving_mix_equals_solo_runs():
         same = np.array_equal(fa, fb) and np.array_equal(ga, gb)
         log(f"[serve] request {o.rid} ({rs[o.rid].shape}, {o.reason}, t={t}): equal to solo: {same}")
         assert same, o.rid
+        check_against_oracle(f"served_request_{o.rid}", p, L, t, phi0, None, u0, mask)
