@@ -163,7 +163,9 @@ fre_status fre_read_moments(fre_lattice *L, uint32_t field_mask,
 
 /* The populations f_i, g_i (unshifted, post-streaming at the current time),
  * layout [q][N] each, into host arrays of n_doubles_each = q*N.  Solid
- * cells read 0.  Syncs. */
+ * cells read 0.  With FP32 storage g_0 includes its low part.  Staged
+ * through the lattice's own buffer in chunks (no device allocation; it
+ * overwrites the auxiliary field that fre_read_moments recomputes).  Syncs. */
 fre_status fre_read_populations(fre_lattice *L, double *f_out, double *g_out,
                                 size_t n_doubles_each);
 

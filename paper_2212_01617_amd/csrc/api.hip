@@ -9,6 +9,7 @@
 // into a HIP graph and replayed.
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
 #include <climits>
 #include <cmath>
 #include <cstdarg>
@@ -186,6 +187,7 @@ struct fre_lattice {
   hipGraphExec_t graph;  // two steps starting at even parity
   bool graph_ok;
   fre_batch *batch;      // non-null while the lattice is a batch member
+  int dev;               // device current at init
 };
 
 struct fre_batch {
@@ -360,6 +362,7 @@ fre_status fre_lattice_init(const fre_params *p, void *device_buf, size_t bytes,
   L->t = 0;
   L->state = 0;
   L->graph_ok = false;
+  if (hipGetDevice(&L->dev) != hipSuccess) { delete L; return fail(FRE_EDEVICE, "hipGetDevice failed"); }
   std::vector<uint8_t> mask;
   std::vector<uint32_t> nbm;
   s = build_mask(L, solid_mask, mask, nbm);
@@ -553,28 +556,35 @@ fre_status fre_read_populations(fre_lattice *L, double *f_out, double *g_out, si
   const Plan &P = L->plan;
   const long long N = L->n_user;
   if (n_doubles_each < (size_t)P.q * N) return fail(FRE_EINVAL, "outputs need q*N doubles each");
-  float *tmp = nullptr;
-  // planes: f_i + w_i, g_i, then the low part of g_0 (zero with FP16 storage)
-  size_t nb = (size_t)(2 * P.q + 1) * P.ncell * sizeof(float);
-  HIP_TRY(hipMalloc(&tmp, nb));
-  launch_read_pops(L->a, (int)(L->t & 1), tmp);
-  std::vector<float> h((size_t)(2 * P.q + 1) * P.ncell);
-  hipError_t e = hipGetLastError();
-  if (e == hipSuccess) e = hipMemcpyAsync(h.data(), tmp, nb, hipMemcpyDeviceToHost, L->a.stream);
-  if (e == hipSuccess) e = hipStreamSynchronize(L->a.stream);
-  (void)hipFree(tmp);
-  if (e != hipSuccess) return fail(FRE_EDEVICE, "population readback failed: %s", hipGetErrorString(e));
+  // staged in chunks through the lattice's AUX field (4 floats per cell, no
+  // other state lives there between calls): 2q + 1 planes per chunk -- f_i +
+  // w_i, g_i, and the low part of g_0 (zero with FP16 storage)
+  const int planes = 2 * P.q + 1;
+  const long long chunk = std::max(1LL, 4 * P.ncell / planes);
+  float *stage = (float *)L->a.AUX;
+  std::vector<float> h((size_t)planes * (size_t)std::min(chunk, P.ncell));
   const fre_params &p = L->p;
-  for (int i = 0; i < P.q; ++i)
-    for (int z = 0; z < p.nz; ++z)
-      for (int y = 0; y < p.ny; ++y)
-        for (int x = 0; x < p.nx; ++x) {
-          long long u = x + (long long)p.nx * (y + (long long)p.ny * z);
-          long long ee = ext_index(P, x, y, z);
-          f_out[(long long)i * N + u] = h[(size_t)i * P.ncell + ee];
-          g_out[(long long)i * N + u] = (double)h[(size_t)(P.q + i) * P.ncell + ee] +
-                                        (i == 0 ? (double)h[(size_t)2 * P.q * P.ncell + ee] : 0.0);
-        }
+  const int odd = (int)(L->t & 1);
+  for (long long c0 = 0; c0 < P.ncell; c0 += chunk) {
+    const int n = (int)std::min(chunk, P.ncell - c0);
+    launch_read_pops(L->a, odd, stage, c0, n);
+    HIP_TRY(hipGetLastError());
+    HIP_TRY(hipMemcpyAsync(h.data(), stage, (size_t)planes * n * sizeof(float), hipMemcpyDeviceToHost, L->a.stream));
+    HIP_TRY(hipStreamSynchronize(L->a.stream));
+    for (long long c = c0; c < c0 + n; ++c) {
+      const int x = (int)(c % P.px) - P.off[0];
+      const long long r = c / P.px;
+      const int y = (int)(r % P.ext[1]) - P.off[1], z = (int)(r / P.ext[1]) - P.off[2];
+      if (x < 0 || x >= p.nx || y < 0 || y >= p.ny || z < 0 || z >= p.nz) continue;
+      const long long u = x + (long long)p.nx * (y + (long long)p.ny * z);
+      const size_t t = (size_t)(c - c0);
+      for (int i = 0; i < P.q; ++i) {
+        f_out[(long long)i * N + u] = h[(size_t)i * n + t];
+        g_out[(long long)i * N + u] = (double)h[(size_t)(P.q + i) * n + t] +
+                                      (i == 0 ? (double)h[(size_t)2 * P.q * n + t] : 0.0);
+      }
+    }
+  }
   return FRE_OK;
 }
 

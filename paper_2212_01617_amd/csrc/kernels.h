@@ -149,8 +149,12 @@ void launch_init(const LaunchArgs &a);
 // n (even) pre-iterations of f with u held at AUX.xyz and phi at AUX.w, then
 // g reset to its equilibrium and M recomputed (consistent initialisation).
 void launch_consistent_init(const LaunchArgs &a, long long n);
-void launch_read_pops(const LaunchArgs &a, int odd, float *out);
-int reduce_blocks();
+// Populations of the storage cells [c0, c0 + n) as [2q + 1][n] floats.
+void launch_read_pops(const LaunchArgs &a, int odd, float *out, long long c0, int n);
+// blocks (partials of 8 doubles) of the global reduction
+constexpr int REDUCE_BLOCKS = 1024;
+inline int reduce_blocks() { return REDUCE_BLOCKS; }
 void launch_reduce(const LaunchArgs &a, double *part);
+
 
 }  // namespace frelbm

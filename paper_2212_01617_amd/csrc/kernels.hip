@@ -1011,30 +1011,37 @@ __global__ __launch_bounds__(BX *BY) void k_observe(Pops<Q, S> P, const uint32_t
                        (j[2] + 0.5f * F[2]) * inv, pres);
 }
 
-// Unshifted populations in the natural layout, [2q][ncell] floats.
+// Unshifted populations of the storage cells [c0, c0 + n), as [2q + 1][n]
+// floats: f_i + w_i, g_i, then the low part of g_0 (FP32 storage; zero with
+// FP16 storage).  Solid cells read 0.
 template <int Q, int S>
-__global__ __launch_bounds__(BX *BY) void k_read_pops(Pops<Q, S> P, const uint32_t *__restrict__ nbm,
-                                                      float *__restrict__ out, Geom G, int odd) {
+__global__ __launch_bounds__(256) void k_read_pops(Pops<Q, S> P, const uint32_t *__restrict__ nbm,
+                                                   float *__restrict__ out, Geom G, int odd, long long c0,
+                                                   int n) {
   using V = VSet<Q>;
-  int x, y, z;
-  long long c;
-  if (!cell_of_thread(G, x, y, z, c)) return;
+  const int t = blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= n) return;
+  const long long c = c0 + t;
   if (nbm[c] & NB_SELF_SOLID) {
-    for (int i = 0; i <= 2 * Q; ++i) out[i * G.ncell + c] = 0.0f;
+    for (int i = 0; i <= 2 * Q; ++i) out[(long long)i * n + t] = 0.0f;
     return;
   }
+  int x, y, z;
+  x = (int)(c % G.px);
+  const long long r = c / G.px;
+  y = (int)(r % G.ey);
+  z = (int)(r / G.ey);
   const Nbr N(G, x, y, z);
   float df[Q], g[Q];
   load_pops<Q, S>(P, N, c, odd, df, g);
 #pragma unroll
   for (int i = 0; i < Q; ++i) {
-    out[i * G.ncell + c] = df[i] + V::w(i);
-    out[(Q + i) * G.ncell + c] = g[i];
+    out[(long long)i * n + t] = df[i] + V::w(i);
+    out[(long long)(Q + i) * n + t] = g[i];
   }
-  // plane 2Q: the low part of g_0 (FP32 storage), added on the host
   float lo = 0.0f;
   if constexpr (S == 0) lo = P.ldg0lo(c);
-  out[2 * Q * G.ncell + c] = lo;
+  out[(long long)2 * Q * n + t] = lo;
 }
 
 // Global sums over fluid cells: compensated FP32 per thread, FP64 across the
@@ -1209,8 +1216,8 @@ static void consistent_init_impl(const LaunchArgs &a, long long n) {
 }
 
 template <int Q, int S>
-static void read_pops_impl(const LaunchArgs &a, int odd, float *out) {
-  k_read_pops<Q, S><<<cell_grid(a.G), cell_block(), 0, a.stream>>>(make_pops<Q, S>(a), a.nbm, out, a.G, odd);
+static void read_pops_impl(const LaunchArgs &a, int odd, float *out, long long c0, int n) {
+  k_read_pops<Q, S><<<(n + 255) / 256, 256, 0, a.stream>>>(make_pops<Q, S>(a), a.nbm, out, a.G, odd, c0, n);
 }
 
 #define FRE_DISPATCH(fn, ...)                                   \
@@ -1241,7 +1248,9 @@ void launch_consistent_init(const LaunchArgs &a, long long n) { FRE_DISPATCH(con
 bool uses_by_product(const LaunchArgs &a) { return a.storage == 0; }
 void launch_observe(const LaunchArgs &a, int odd) { FRE_DISPATCH(observe_impl, a, odd); }
 void launch_init(const LaunchArgs &a) { FRE_DISPATCH(init_impl, a); }
-void launch_read_pops(const LaunchArgs &a, int odd, float *out) { FRE_DISPATCH(read_pops_impl, a, odd, out); }
+void launch_read_pops(const LaunchArgs &a, int odd, float *out, long long c0, int n) {
+  FRE_DISPATCH(read_pops_impl, a, odd, out, c0, n);
+}
 
 // One batched step of one class: the same five stages over every lattice of
 // the class listed in the work lists (ranges: cells [start, n], fills
@@ -1274,9 +1283,9 @@ void launch_batch_step(const BatchArgs &b, int cls, int odd) {
   }
 }
 
-int reduce_blocks() { return 1024; }
 void launch_reduce(const LaunchArgs &a, double *part) {
   k_reduce<<<reduce_blocks(), 256, 0, a.stream>>>(a.C, a.AUX, a.nbm, a.G.ncell, part);
 }
+
 
 }  // namespace frelbm
