@@ -176,6 +176,18 @@ fre_status fre_read_populations(fre_lattice *L, double *f_out, double *g_out,
  * failed state and returns FRE_ENUMERIC.  Syncs. */
 fre_status fre_reduce(fre_lattice *L, double out[8]);
 
+/* fre_reduce for callers that cannot allocate memory (serving loops or
+ * harnesses that forbid device or host allocation): the same sums, bitwise
+ * equal to fre_reduce's, with the block partials kept in a fixed device array
+ * of the library (64 KiB per GPU, taken when the library loads and held until
+ * the process ends) instead of the lattice buffer.  It calls no hipMalloc or
+ * hipFree and allocates no host memory.  The array's size does not depend on the
+ * lattice, so every lattice fre_lattice_init accepts is accepted.  The array
+ * is shared by every call on one GPU: calls that overlap on one GPU (two
+ * streams, two threads) race and must be serialised by the caller.  Runs on
+ * the device the lattice was created on.  Same errors as fre_reduce.  Syncs. */
+fre_status fre_reduce_noalloc(fre_lattice *L, double out[8]);
+
 /* Current step count and state (0 ok, 1 failed). */
 fre_status fre_info(const fre_lattice *L, int64_t *step, int32_t *state);
 

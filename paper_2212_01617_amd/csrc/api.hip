@@ -15,6 +15,7 @@
 #include <cstdarg>
 #include <cstdio>
 #include <cstring>
+#include <mutex>
 #include <string>
 #include <vector>
 
@@ -609,6 +610,71 @@ fre_status fre_reduce(fre_lattice *L, double out[8]) {
     return fail(FRE_ENUMERIC, "%.0f fluid cells hold non-finite values at step %lld", acc[6], (long long)L->t);
   }
   return FRE_OK;
+}
+
+}  // extern "C"
+
+// ---------------------------------------------------------------------------
+// Allocation-free reduction.  Its block partials and totals live in this
+// file-scope device array (one copy per GPU, held until the process ends)
+// instead of the lattice buffer.  Host code uses the array through the
+// address hipGetSymbolAddress gives on each device, never through its name.
+// ---------------------------------------------------------------------------
+constexpr int kScratchDoubles = REDUCE_BLOCKS * 8 + 8;  // partials, then 8 totals
+static __device__ __align__(256) double scratch[kScratchDoubles];
+
+namespace {
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+double *g_scratch_ptr[kMaxDevices] = {};
+
+// The device address of `scratch` on device `dev`, which must be current;
+// looked up once per device.
+fre_status scratch_of_device(int dev, double **out) {
+  std::lock_guard<std::mutex> lock(g_scratch_mu);
+  if (dev < 0 || dev >= kMaxDevices) return fail(FRE_EDEVICE, "device %d out of range", dev);
+  if (!g_scratch_ptr[dev]) {
+    void *ptr = nullptr;
+    hipError_t e = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+    if (e != hipSuccess || !ptr)
+      return fail(FRE_EDEVICE, "hipGetSymbolAddress(scratch) on device %d failed: %s", dev, hipGetErrorString(e));
+    g_scratch_ptr[dev] = (double *)ptr;
+  }
+  *out = g_scratch_ptr[dev];
+  return FRE_OK;
+}
+}  // namespace
+
+extern "C" {
+
+fre_status fre_reduce_noalloc(fre_lattice *L, double out[8]) {
+  if (!L || !out) return fail(FRE_EINVAL, "NULL argument");
+  if (fre_status bs = sync_batch(L)) return bs;
+  int cur = 0;
+  HIP_TRY(hipGetDevice(&cur));
+  if (cur != L->dev) HIP_TRY(hipSetDevice(L->dev));
+  auto finish = [&](fre_status st) {
+    if (cur != L->dev) (void)hipSetDevice(cur);
+    return st;
+  };
+  double *ptr = nullptr;
+  fre_status s = scratch_of_device(L->dev, &ptr);
+  if (s != FRE_OK) return finish(s);
+  s = observe(L);
+  if (s != FRE_OK) return finish(s);
+  // every block writes all 8 of its partials, so nothing needs clearing
+  launch_reduce_total(L->a, ptr, ptr + (size_t)REDUCE_BLOCKS * 8);
+  hipError_t e = hipGetLastError();
+  if (e == hipSuccess)
+    e = hipMemcpyAsync(out, ptr + (size_t)REDUCE_BLOCKS * 8, 8 * sizeof(double), hipMemcpyDeviceToHost, L->a.stream);
+  if (e == hipSuccess) e = hipStreamSynchronize(L->a.stream);
+  if (e != hipSuccess) return finish(fail(FRE_EDEVICE, "reduction failed: %s", hipGetErrorString(e)));
+  out[0] = out[7] + out[0];  // sum rho = n_fluid + sum (rho - 1)
+  if (out[6] > 0) {
+    L->state = 1;
+    return finish(fail(FRE_ENUMERIC, "%.0f fluid cells hold non-finite values at step %lld", out[6], (long long)L->t));
+  }
+  return finish(FRE_OK);
 }
 
 fre_status fre_info(const fre_lattice *L, int64_t *step, int32_t *state) {

@@ -155,6 +155,8 @@ void launch_read_pops(const LaunchArgs &a, int odd, float *out, long long c0, in
 constexpr int REDUCE_BLOCKS = 1024;
 inline int reduce_blocks() { return REDUCE_BLOCKS; }
 void launch_reduce(const LaunchArgs &a, double *part);
-
+// launch_reduce, then the sum of the reduce_blocks() partials in block order
+// into total[8] on the device.
+void launch_reduce_total(const LaunchArgs &a, double *part, double *total);
 
 }  // namespace frelbm

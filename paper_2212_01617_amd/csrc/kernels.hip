@@ -1088,6 +1088,17 @@ __global__ __launch_bounds__(256) void k_reduce(const float4 *__restrict__ C, co
     for (int k = 0; k < 8; ++k) part[blockIdx.x * 8 + k] = red[k][0];
 }
 
+// Sums the nb block partials of k_reduce, for each of the 8 quantities in
+// block order (the order fre_reduce sums them on the host), into total[8].
+__global__ __launch_bounds__(64) void k_reduce_final(const double *__restrict__ part, int nb,
+                                                     double *__restrict__ total) {
+  const int k = threadIdx.x;
+  if (k >= 8) return;
+  double acc = 0.0;
+  for (int b = 0; b < nb; ++b) acc += part[b * 8 + k];
+  total[k] = acc;
+}
+
 // ---------------------------------------------------------------------------
 // host launchers
 // ---------------------------------------------------------------------------
@@ -1286,6 +1297,9 @@ void launch_batch_step(const BatchArgs &b, int cls, int odd) {
 void launch_reduce(const LaunchArgs &a, double *part) {
   k_reduce<<<reduce_blocks(), 256, 0, a.stream>>>(a.C, a.AUX, a.nbm, a.G.ncell, part);
 }
-
+void launch_reduce_total(const LaunchArgs &a, double *part, double *total) {
+  launch_reduce(a, part);
+  k_reduce_final<<<1, 64, 0, a.stream>>>(part, reduce_blocks(), total);
+}
 
 }  // namespace frelbm

@@ -63,6 +63,7 @@ _SIGS = [
     ("fre_read_moments", C.c_int32, [C.c_void_p, C.c_uint32, C.c_void_p, C.c_size_t]),
     ("fre_read_populations", C.c_int32, [C.c_void_p, C.c_void_p, C.c_void_p, C.c_size_t]),
     ("fre_reduce", C.c_int32, [C.c_void_p, C.c_void_p]),
+    ("fre_reduce_noalloc", C.c_int32, [C.c_void_p, C.c_void_p]),
     ("fre_info", C.c_int32, [C.c_void_p, C.POINTER(C.c_int64), C.POINTER(C.c_int32)]),
     ("fre_state_bytes", C.c_int32, [C.c_void_p, C.POINTER(C.c_size_t)]),
     ("fre_save", C.c_int32, [C.c_void_p, C.c_void_p, C.c_size_t]),
@@ -248,6 +249,13 @@ class Lattice:
     def reduce(self) -> np.ndarray:
         out = np.zeros(8)
         _check(lib().fre_reduce(self._h, _ptr(out)))
+        return out
+
+    def reduce_noalloc(self) -> np.ndarray:
+        """fre_reduce_noalloc: the same sums without any allocation by the
+        library (calls on one GPU must not overlap)."""
+        out = np.zeros(8)
+        _check(lib().fre_reduce_noalloc(self._h, _ptr(out)))
         return out
 
     def info(self):
