@@ -497,9 +497,9 @@ __device__ __forceinline__ void collide_cell(const Pops<Q, S> &P, const Nbr &N, 
   const float mu_phi = cc.w, mu_rho = coupling_mu_rho(cc);
   float F[3];
   force<Q>(C, N, mu_rho, mu_phi, F);
-  // FP16 storage loads g only after f is collided and stored, which holds the
-  // kernel to 128 VGPRs (4 waves per SIMD); with FP32 storage and the moment
-  // sums the split costs registers instead, so f and g are loaded together.
+  // FP16 storage loads g only after f is collided and stored (fewer live
+  // registers); with FP32 storage and the moment sums the split costs
+  // registers instead, so f and g are loaded together.
   constexpr bool SPLIT = S == 1;
   float df[Q], g[Q];
   if constexpr (SPLIT) {
@@ -519,15 +519,14 @@ __device__ __forceinline__ void collide_cell(const Pops<Q, S> &P, const Nbr &N, 
   const float rho = 1.0f + drho;
   const float inv_rho = 1.0f / rho;
   const float m[3] = {j[0] + 0.5f * F[0], j[1] + 0.5f * F[1], j[2] + 0.5f * F[2]};  // eq. veloMoment: rho u
-  const float u[3] = {m[0] * inv_rho, m[1] * inv_rho, m[2] * inv_rho};
-  const float uu = u[0] * u[0] + u[1] * u[1] + u[2] * u[2];
-  const float uF = u[0] * F[0] + u[1] * F[1] + u[2] * F[2];
-  // second-order part of the equilibria over w_i; the same expression in both
-  // loops, so f and g see the same value
-  auto quad_of = [&](int i) {
-    const float cu = V::cx(i) * u[0] + V::cy(i) * u[1] + V::cz(i) * u[2];
-    return 4.5f * cu * cu - 1.5f * uu;
-  };
+  // u = m / rho enters the terms of second order; they are written with m
+  // and 1/rho so that u itself is not kept (registers)
+  const float mmr = (m[0] * m[0] + m[1] * m[1] + m[2] * m[2]) * inv_rho;  // rho |u|^2
+  const float uF = (m[0] * F[0] + m[1] * F[1] + m[2] * F[2]) * inv_rho;   // u . F
+  // rho times the second-order part of the equilibria over w_i, from
+  // cm = c_i . m and cu = c_i . u; the same expression in both loops, so f and g
+  // see the same value
+  auto rquad = [&](float cm, float cu) { return 4.5f * cm * cu - 1.5f * mmr; };
   float phi = 0.0f, gm = 0.0f;  // gm: sum of the moving g_i (FP32: g_0 as hi + lo)
   if constexpr (!SPLIT) {
     if constexpr (X) {
@@ -543,8 +542,9 @@ __device__ __forceinline__ void collide_cell(const Pops<Q, S> &P, const Nbr &N, 
   float geq_rest = 0.0f;
   // post-collision g_i of direction i > 0, stored to the slot it streams to
   auto collide_g = [&](int i) {
-    const float cu = V::cx(i) * u[0] + V::cy(i) * u[1] + V::cz(i) * u[2];
-    const float geq = V::w(i) * ph.gam3 * mu_phi + phi * (V::a(i) * cu + V::w(i) * quad_of(i));
+    const float cm = V::cx(i) * m[0] + V::cy(i) * m[1] + V::cz(i) * m[2];
+    const float cu = cm * inv_rho;
+    const float geq = V::w(i) * ph.gam3 * mu_phi + phi * (V::a(i) * cu + V::w(i) * (rquad(cm, cu) * inv_rho));
     geq_rest += geq;
     const float gs = P.round(g[i] + ph.om_g * (geq - g[i]));
     if (post) post[Q - 1 + i - 1][tid] = gs;
@@ -555,10 +555,10 @@ __device__ __forceinline__ void collide_cell(const Pops<Q, S> &P, const Nbr &N, 
 #pragma unroll
   for (int i = 0; i < Q; ++i) {
     const float cF = V::cx(i) * F[0] + V::cy(i) * F[1] + V::cz(i) * F[2];
-    const float cu = V::cx(i) * u[0] + V::cy(i) * u[1] + V::cz(i) * u[2];
     const float cm = V::cx(i) * m[0] + V::cy(i) * m[1] + V::cz(i) * m[2];
+    const float cu = cm * inv_rho;
     const float wi = V::w(i), ai = V::a(i);
-    const float dfeq = wi * drho + ai * cm + wi * rho * quad_of(i);             // f_i^eq - w_i
+    const float dfeq = wi * drho + ai * cm + wi * rquad(cm, cu);                // f_i^eq - w_i
     const float src = ph.guo * (ai * cF - 3.0f * wi * uF + 3.0f * ai * cu * cF);  // Guo term
     const float fs = P.round(df[i] + ph.om_f * (dfeq - df[i]) + src);
     if (i == 0) {
@@ -778,10 +778,11 @@ __device__ __forceinline__ void run_stage(const LatView<Q, S> &L, int x, int y, 
   else stage_potential<Q, S>(L, x, y, z);
 }
 
+// The collide keeps the compiler's register choice (3 waves per SIMD for
+// D3Q19): capped at 128 VGPRs (4 waves) it spills 52-56 bytes per lane in FP16
+// storage and was measured 16% slower (186 against 160 us at 256x128x128).
 template <int Q, int S, int STAGE, int ODD>
-// FP16 storage: at most 128 VGPRs, 4 waves per SIMD for the collide (measured
-// faster than 3 waves without spills); FP32 keeps the compiler's choice.
-__global__ __launch_bounds__(BX *MAX_ROWS) __attribute__((amdgpu_waves_per_eu(S == 1 ? 4 : 1))) void k_cells(LatView<Q, S> L) {
+__global__ __launch_bounds__(BX *MAX_ROWS) void k_cells(LatView<Q, S> L) {
   int x, y, z;
   long long c;
   const bool in = cell_of_tile(L.G, L.tm, x, y, z, c);
