@@ -418,6 +418,9 @@ def main():
         "kernels_ms": {k: round(v, 5) for k, v in r["prof"].items()},
         "launch_shape": {k: {"rows": v[0], "xcd": v[1]} for k, v in r["shape"].items()},
     }
+    cp = copy_rate()
+    out["copy_ceiling_GBps"] = cp["GBps"]
+    out["roofline"]["frac_of_copy_ceiling"] = round(achieved / cp["GBps"], 4)
     if 1 in res:
         r16 = res[1]
         m16 = r16["n"] / (r16["ms"] * 1e-3) / 1e6
@@ -487,24 +490,34 @@ def serving_steady(n_requests: int = 16) -> dict:
     return s
 
 
-def copy_probe(nbytes: int = 1 << 30, reps: int = 5) -> None:
-    """A plain device copy of nbytes, repeated: reading the FETCH_SIZE and
-    WRITE_SIZE counters of these launches against nbytes gives the scale of
-    the counters for the kernels of the step."""
+def copy_rate(nbytes: int = 1 << 30, reps: int = 5) -> dict:
+    """A plain device-to-device copy of nbytes (read once, written once),
+    repeated after one warm-up copy: its rate is the copy ceiling of HBM on
+    this box, measured beside the 8 TB/s peak.  The same launches are the
+    reference that scales the FETCH_SIZE / WRITE_SIZE counters."""
     import torch
     src = torch.empty(nbytes, dtype=torch.uint8, device="cuda")
     src.fill_(1)
     dst = torch.empty_like(src)
+    dst.copy_(src)
     torch.cuda.synchronize()
-    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-    e0.record()
+    times = []
     for _ in range(reps):
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
         dst.copy_(src)
-    e1.record()
-    torch.cuda.synchronize()
-    ms = e0.elapsed_time(e1) / reps
-    print(json.dumps({"mode": "copy-probe", "bytes_read": nbytes, "bytes_written": nbytes, "reps": reps,
-                      "ms": round(ms, 4), "GBps": round(2 * nbytes / ms / 1e6, 1)}), flush=True)
+        e1.record()
+        torch.cuda.synchronize()
+        times.append(e0.elapsed_time(e1))
+    ms = float(np.median(times))
+    del src, dst
+    torch.cuda.empty_cache()
+    return {"bytes_read": nbytes, "bytes_written": nbytes, "reps": reps, "ms": round(ms, 4),
+            "GBps": round(2 * nbytes / ms / 1e6, 1)}
+
+
+def copy_probe(nbytes: int = 1 << 30, reps: int = 5) -> None:
+    print(json.dumps({"mode": "copy-probe", **copy_rate(nbytes, reps)}), flush=True)
 
 
 if __name__ == "__main__":

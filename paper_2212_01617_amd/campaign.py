@@ -1,6 +1,6 @@
 """Critical capillary number of drop breakup in shear, on the serving engine.
 
-Sec. 3.2 reports that a drop of radius a = 30 in shear breaks up above
+Sec. 3.1 (Breakup) reports that a drop of radius a = 30 in shear breaks up above
 Ca_c ~ 0.7 in 2D and ~ 0.42 in 3D, and shows a 2D breakup with end-pinching
 and capillary waves at Ca = 3.5 (Re = 1, a = 40).  A sweep serves one shear
 request per capillary number through the batch (all admitted at once); each

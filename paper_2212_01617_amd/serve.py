@@ -167,7 +167,8 @@ class Server:
 
     def __init__(self, engine, budget_bytes: int, max_members: int, chunk: int = 200,
                  strain_cap: float = 25.0, step_cap: int = 200_000, clock=time.monotonic,
-                 sleep=time.sleep):
+                 sleep=time.sleep, on_retire=None):
+        self.on_retire = on_retire  # called with each Outcome as it retires
         self.engine = engine
         self.budget = int(budget_bytes)
         self.max_members = int(max_members)
@@ -261,6 +262,8 @@ class Server:
                 used -= self.engine.footprint(m.req)
                 outcomes.append(Outcome(m.req.rid, reason, m.req.arrival, m.admitted, self.clock() - t0,
                                         m.t, m.t * m.rate, m.D, m.req.cells))
+                if self.on_retire:
+                    self.on_retire(outcomes[-1])
         wall = self.clock() - t0
         return Report(outcomes, wall, lu, peak_bytes, peak_members)
 
@@ -444,3 +447,49 @@ class GpuEngine:
         self.work -= w
         self.fill -= f
         L.close()
+
+
+def main(argv=None):
+    """Serve the mixed request stream on the GPU and print the summary as one
+    JSON line (each retirement is printed as it happens).  With the defaults
+    this is the full sweep: 256 requests, Poisson arrivals at 20/s, D2Q9
+    N = 64..512 and D3Q19 N = 48..160 in steps of 16, shear and four-roller,
+    FP32 and FP16, Ca in [0.05, 0.4], Re in [0.1, 1], a 32 GiB budget."""
+    import argparse
+    import json
+    ap = argparse.ArgumentParser(description=main.__doc__.split("\n\n")[0])
+    ap.add_argument("--requests", type=int, default=256)
+    ap.add_argument("--rate", type=float, default=20.0)
+    ap.add_argument("--seed", type=int, default=0)
+    ap.add_argument("--budget-gib", type=float, default=32.0)
+    ap.add_argument("--max-members", type=int, default=32)
+    ap.add_argument("--strain-cap", type=float, default=25.0)
+    ap.add_argument("--step-cap", type=int, default=200_000)
+    ap.add_argument("--chunk", type=int, default=200)
+    ap.add_argument("--out", default="", help="also write every outcome to this JSON file")
+    args = ap.parse_args(argv)
+    rs = make_requests(args.requests, rate=args.rate, seed=args.seed)
+    budget = int(args.budget_gib * (1 << 30))
+    eng = GpuEngine(budget_bytes=budget, max_members=args.max_members)
+
+    def show(o):
+        print(json.dumps({"rid": o.rid, "reason": o.reason, "steps": o.steps, "strain": round(o.strain, 3),
+                          "D": round(o.D, 4), "cells": o.cells, "latency_s": round(o.latency, 3)}), flush=True)
+
+    srv = Server(eng, budget, max_members=args.max_members, chunk=args.chunk, strain_cap=args.strain_cap,
+                 step_cap=args.step_cap, on_retire=show)
+    rep = srv.run(rs)
+    s = rep.summary()
+    s = {k: (round(v, 4) if isinstance(v, float) else v) for k, v in s.items()}
+    s["workload"] = (f"{args.requests} requests, Poisson {args.rate}/s, D2Q9 N 64-512 / D3Q19 N 48-160, "
+                     f"shear/rollers, FP32/FP16, caps {args.strain_cap} strain units or {args.step_cap} steps, "
+                     f"{args.budget_gib} GiB budget, at most {args.max_members} members")
+    if args.out:
+        with open(args.out, "w") as fh:
+            json.dump({"summary": s, "outcomes": [o.__dict__ for o in rep.outcomes]}, fh)
+    print(json.dumps({"mode": "serving", **s}), flush=True)
+    eng.batch.close()
+
+
+if __name__ == "__main__":
+    main()

@@ -1,4 +1,4 @@
-"""Breakup in shear on the GPU serving engine (qualitative, after Sec. 3.2):
+"""Breakup in shear on the GPU serving engine (qualitative, after Sec. 3.1, Breakup):
 a 2D drop of radius 16 at Re = 1 stays whole at Ca = 0.2 and breaks up at
 Ca = 2, both served together in one batch.  The 3D four-roller run on a
 small cell: the drop on the stagnation point deforms in the extensional
