@@ -240,3 +240,118 @@ class Brute:
     def populations(self):
         return (np.stack([self._user(self.f[i]) for i in range(self.q)]),
                 np.stack([self._user(self.g[i]) for i in range(self.q)]))
+
+
+class Brute3(Brute):
+    """The ternary step (Sec. 2.2, Remark after the mobility relation) in the
+    same naive form, written in the concentrations C1 = (rho + phi - psi)/2,
+    C2 = (rho - phi - psi)/2, C3 = psi of the cited ternary free energy
+    sum_m kappa_m/2 C_m^2 (1 - C_m)^2 + alpha^2 kappa_m/2 |grad C_m|^2: the
+    potential of each concentration, mu_m = kappa_m C_m (1 - C_m)(1 - 2 C_m)
+    - alpha^2 kappa_m lap C_m, and the force sum_m mu_m grad C_m - grad(sum_m
+    C_m mu_m), equal to the form in (rho, phi, psi) of the C oracle by the
+    chain rule; the third population h relaxes like g towards the equilibrium
+    with (psi, mu_psi, Gamma_psi)."""
+
+    def __init__(self, kind, shape_xyz, phi0, psi0, rho0=None, u0=None, mask=None, *, kappa3, M3, tau_h, **kw):
+        self.k3, self.th = kappa3, tau_h
+        self.G3 = M3 / (tau_h - 0.5)
+        self._psi0 = psi0
+        super().__init__(kind, shape_xyz, phi0, rho0, u0, mask, **kw)
+        # the base class set f and g from the binary potentials: redo all
+        # three from the ternary ones
+        nx, ny, nz = self.n
+        N = nx * ny * nz
+        def to_ext(v, default):
+            out = np.zeros(self.E)
+            vv = np.full(N, default) if v is None else np.asarray(v, float).reshape(-1)
+            out[self.inner_idx] = vv[self.user_of_inner]
+            return out * self.fluid
+        phi, psi, rho = to_ext(phi0, 0.0), to_ext(psi0, 0.0), to_ext(rho0, 1.0)
+        u = np.zeros((3, self.E))
+        if u0 is not None:
+            uu = np.asarray(u0, float).reshape(3, -1)
+            for a in range(3):
+                u[a] = to_ext(uu[a], 0.0)
+        mur, mup, muq = self._potentials3(rho, phi, psi)
+        self.f = self._feq(rho, u)
+        self.g = self._geq(phi, mup, u)
+        self.h = self._heq(psi, muq, u)
+
+    def _heq(self, psi, muq, u):
+        cu = self.c @ u
+        uu = (u * u).sum(0)
+        h = self.w[:, None] * (3 * self.G3 * muq + psi * (3 * cu + 4.5 * cu ** 2 - 1.5 * uu))
+        h[0] = psi - h[1:].sum(0)
+        return h * self.fluid
+
+    def _conc(self, rho, phi, psi):
+        return [0.5 * (rho + phi - psi), 0.5 * (rho - phi - psi), psi]
+
+    def _mu_conc(self, rho, phi, psi):
+        """potential of each concentration at fluid cells"""
+        Cs = self._conc(self._fill(rho), self._fill(phi), self._fill(psi))
+        Cr = self._conc(rho, phi, psi)
+        out = []
+        for k, C, Cf in zip((self.k1, self.k2, self.k3), Cr, Cs):
+            out.append((k * C * (1 - C) * (1 - 2 * C) - self.al ** 2 * k * self._lap(Cf)) * self.fluid)
+        return out
+
+    def _potentials3(self, rho, phi, psi):
+        m1, m2, m3 = self._mu_conc(rho, phi, psi)
+        return 0.5 * (m1 + m2), 0.5 * (m1 - m2), m3 - 0.5 * (m1 + m2)
+
+    def _moments3(self):
+        rho = self.f.sum(0) * self.fluid
+        phi = self.g.sum(0) * self.fluid
+        psi = self.h.sum(0) * self.fluid
+        j = (self.c.T @ self.f) * self.fluid
+        mu = self._mu_conc(rho, phi, psi)
+        Cr = self._conc(rho, phi, psi)
+        pi = sum(C * m for C, m in zip(Cr, mu))
+        F = -self._grad(self._fill(pi))
+        for C, m in zip(Cr, mu):
+            # grad of the filled concentration: the fill is linear, so this is
+            # the same combination of the filled rho, phi, psi
+            F = F + m * self._grad(self._fill(C))
+        F = F * self.fluid
+        with np.errstate(invalid="ignore", divide="ignore"):
+            u = np.where(self.fluid, (j + 0.5 * F) / np.where(self.fluid, rho, 1.0), 0.0)
+        mur, mup, muq = 0.5 * (mu[0] + mu[1]), 0.5 * (mu[0] - mu[1]), mu[2] - 0.5 * (mu[0] + mu[1])
+        return rho, phi, psi, j, mur, mup, muq, F, u
+
+    def _step(self):
+        rho, phi, psi, j, mur, mup, muq, F, u = self._moments3()
+        cu = self.c @ u
+        cF = self.c @ F
+        uF = (u * F).sum(0)
+        S = (1 - 0.5 / self.tf) * self.w[:, None] * (3 * (cF - uF) + 9 * cu * cF)
+        fs = self.f - (self.f - self._feq(rho, u)) / self.tf + S
+        gs = self.g - (self.g - self._geq(phi, mup, u)) / self.tg
+        hs = self.h - (self.h - self._heq(psi, muq, u)) / self.th
+        fn, gn, hn = np.zeros_like(self.f), np.zeros_like(self.g), np.zeros_like(self.h)
+        F_idx = np.nonzero(self.fluid)[0]
+        for i in range(self.q):
+            io = self.opp[i]
+            src = self.nb[io, F_idx]
+            fl = self.fluid[src]
+            fn[i, F_idx[fl]] = fs[i, src[fl]]
+            gn[i, F_idx[fl]] = gs[i, src[fl]]
+            hn[i, F_idx[fl]] = hs[i, src[fl]]
+            for x, s in zip(F_idx[~fl], src[~fl]):
+                cw = self.c[io] @ self._body_u(x, s, io)
+                fn[i, x] = fs[io, x] - 6 * self.w[io] * rho[x] * cw
+                gn[i, x] = gs[io, x] - 6 * self.w[io] * phi[x] * cw
+                hn[i, x] = hs[io, x] - 6 * self.w[io] * psi[x] * cw
+        self.f, self.g, self.h = fn, gn, hn
+        self.t += 1
+
+    def observe(self):
+        rho, phi, psi, j, mur, mup, muq, F, u = self._moments3()
+        return {"rho": self._user(rho), "phi": self._user(phi), "psi": self._user(psi),
+                "ux": self._user(u[0]), "uy": self._user(u[1]), "uz": self._user(u[2]),
+                "mu_rho": self._user(mur), "mu_phi": self._user(mup), "mu_psi": self._user(muq)}
+
+    def populations(self):
+        f, g = super().populations()
+        return f, g, np.stack([self._user(self.h[i]) for i in range(self.q)])

@@ -52,6 +52,9 @@
  *     A ghost cell lying in the ghost layers of several axes moves with the
  *     mean of those walls' velocities.
  *   - Initialisation: f = f^eq(rho0,u0), g = g^eq(phi0, mu_phi(rho0,phi0), u0).
+ *   - Three components (Sec. 2.2, Remark after the mobility relation): the
+ *     free energy of the cited ternary model, see the or3_ functions at the
+ *     end of this file.
  *   - Consistent initialisation (Sec. 2.3 cites Mei, Luo, Lallemand and
  *     d'Humieres 2006, without details): pre-iterations of the f population
  *     in which the velocity of the equilibrium and of the forcing term is
@@ -230,6 +233,11 @@ typedef struct {
   double *pi;                    /* rho mu_rho + phi mu_phi */
   double *Fx, *Fy, *Fz, *ux, *uy, *uz;
   long t;
+  /* ternary extension (or3_*): third order parameter psi and its population
+   * h; NULL / 0 for a binary lattice */
+  int ternary;
+  double kappa3, M3, tau_h;
+  double *h, *hn, *psi, *lq, *muq;
 } or_state;
 
 static long or_idx(const or_state *s, int x, int y, int z) {
@@ -419,6 +427,7 @@ static void *or_zalloc(size_t n) { return calloc(n ? n : 1, 1); }
 
 void or_destroy(or_state *s) {
   if (!s) return;
+  free(s->h); free(s->hn); free(s->psi); free(s->lq); free(s->muq);
   free(s->kind); free(s->f); free(s->g); free(s->fn); free(s->gn);
   free(s->rho); free(s->phi); free(s->jx); free(s->jy); free(s->jz);
   free(s->lr); free(s->lp); free(s->mur); free(s->mup); free(s->pi);
@@ -720,4 +729,274 @@ void or_stencils(or_state *s, const double *X, double *lap_out,
     for (int a = 0; a < 3; ++a) grad_out[(long)a * N + u] = gr[a];
   }
   free(tmp);
+}
+
+/* ====================================================================== */
+/* Ternary extension (Sec. 2.2, Remark after the mobility relation): one   */
+/* more Cahn-Hilliard equation, for a third order parameter psi, and one   */
+/* more population h.  The free energy is that of the ternary model the    */
+/* Remark cites (Semprebon, Krueger and Kusumaatmaja 2016), written with   */
+/* the concentrations C1 = (rho + phi - psi)/2, C2 = (rho - phi - psi)/2,  */
+/* C3 = psi:                                                               */
+/*   Psi = int sum_m [ kappa_m/2 C_m^2 (1 - C_m)^2                         */
+/*                     + alpha^2 kappa_m/2 |grad C_m|^2 ] dV,              */
+/* which for C3 = 0 is eq. (functional) term by term.  The potentials are  */
+/* the functional derivatives, through the chain rule from                 */
+/*   mu_m = kappa_m C_m (1 - C_m)(1 - 2 C_m) - alpha^2 kappa_m lap C_m:    */
+/*   mu_rho = (mu_1 + mu_2)/2, mu_phi = (mu_1 - mu_2)/2,                   */
+/*   mu_psi = mu_3 - (mu_1 + mu_2)/2;                                      */
+/* the force generalises eq. (F) to -rho grad mu_rho - phi grad mu_phi     */
+/* - psi grad mu_psi (the divergence of the chemical pressure of this      */
+/* functional), taken in the same product-rule form as the binary step;    */
+/* h has the equilibrium of eq. (geq) with (psi, mu_psi, Gamma_psi),       */
+/* Gamma_psi = M_psi / (tau_h - 1/2), and the walls treat it as g.         */
+/* ====================================================================== */
+
+/* The three potentials at a node from rho, phi, psi and their Laplacians.
+ * out[0] = mu_rho, out[1] = mu_phi, out[2] = mu_psi. */
+void or3_mu(double kappa1, double kappa2, double kappa3, double alpha, double rho,
+            double phi, double psi, double lap_rho, double lap_phi, double lap_psi,
+            double *out) {
+  double C[3] = {0.5 * (rho + phi - psi), 0.5 * (rho - phi - psi), psi};
+  double L[3] = {0.5 * (lap_rho + lap_phi - lap_psi),
+                 0.5 * (lap_rho - lap_phi - lap_psi), lap_psi};
+  double k[3] = {kappa1, kappa2, kappa3};
+  double m[3];
+  for (int a = 0; a < 3; ++a)
+    m[a] = k[a] * C[a] * (1.0 - C[a]) * (1.0 - 2.0 * C[a]) -
+           alpha * alpha * k[a] * L[a];
+  out[0] = 0.5 * (m[0] + m[1]);
+  out[1] = 0.5 * (m[0] - m[1]);
+  out[2] = m[2] - 0.5 * (m[0] + m[1]);
+}
+
+/* Bulk free-energy density of the ternary functional. */
+double or3_psi_bulk(double kappa1, double kappa2, double kappa3, double rho,
+                    double phi, double psi) {
+  double C[3] = {0.5 * (rho + phi - psi), 0.5 * (rho - phi - psi), psi};
+  double k[3] = {kappa1, kappa2, kappa3};
+  double e = 0.0;
+  for (int a = 0; a < 3; ++a)
+    e += 0.5 * k[a] * C[a] * C[a] * (1.0 - C[a]) * (1.0 - C[a]);
+  return e;
+}
+
+static double or3_gamma(const or_state *s) { return s->M3 / (s->tau_h - 0.5); }
+
+static void or3_moments(or_state *s) {
+  const int(*c)[3] = or_c(s->p.kind);
+  int q = s->q;
+#pragma omp parallel for schedule(static)
+  for (long x = 0; x < s->ncell; ++x) {
+    if (s->kind[x] != OR_FLUID) {
+      s->rho[x] = s->phi[x] = s->psi[x] = s->jx[x] = s->jy[x] = s->jz[x] = 0.0;
+      continue;
+    }
+    double r = 0.0, p = 0.0, z = 0.0, j[3] = {0.0, 0.0, 0.0};
+    for (int i = 0; i < q; ++i) {
+      double fi = s->f[x * q + i];
+      r += fi;
+      p += s->g[x * q + i];
+      z += s->h[x * q + i];
+      for (int a = 0; a < 3; ++a) j[a] += c[i][a] * fi;
+    }
+    s->rho[x] = r;
+    s->phi[x] = p;
+    s->psi[x] = z;
+    s->jx[x] = j[0];
+    s->jy[x] = j[1];
+    s->jz[x] = j[2];
+  }
+}
+
+/* The three potentials and Pi = rho mu_rho + phi mu_phi + psi mu_psi at fluid
+ * cells; solid cells filled for rho, phi, psi and Pi (reading R5). */
+static void or3_potentials(or_state *s) {
+  or_fill_solid(s, s->rho);
+  or_fill_solid(s, s->phi);
+  or_fill_solid(s, s->psi);
+#pragma omp parallel for schedule(static)
+  for (long x = 0; x < s->ncell; ++x) {
+    if (s->kind[x] != OR_FLUID) continue;
+    s->lr[x] = or_lap_at(s, s->rho, x);
+    s->lp[x] = or_lap_at(s, s->phi, x);
+    s->lq[x] = or_lap_at(s, s->psi, x);
+    double mu[3];
+    or3_mu(s->p.kappa1, s->p.kappa2, s->kappa3, s->p.alpha, s->rho[x], s->phi[x],
+           s->psi[x], s->lr[x], s->lp[x], s->lq[x], mu);
+    s->mur[x] = mu[0];
+    s->mup[x] = mu[1];
+    s->muq[x] = mu[2];
+    s->pi[x] = s->rho[x] * mu[0] + s->phi[x] * mu[1] + s->psi[x] * mu[2];
+  }
+  or_fill_solid(s, s->pi);
+}
+
+/* F = mu_rho grad rho + mu_phi grad phi + mu_psi grad psi - grad Pi (equal in
+ * the continuum to -rho grad mu_rho - phi grad mu_phi - psi grad mu_psi) and
+ * u = (j + F/2)/rho at fluid cells. */
+static void or3_force_velocity(or_state *s) {
+#pragma omp parallel for schedule(static)
+  for (long x = 0; x < s->ncell; ++x) {
+    if (s->kind[x] != OR_FLUID) {
+      s->Fx[x] = s->Fy[x] = s->Fz[x] = 0.0;
+      s->ux[x] = s->uy[x] = s->uz[x] = 0.0;
+      continue;
+    }
+    double gr[3], gp[3], gq[3], gpi[3];
+    or_grad_at(s, s->rho, x, gr);
+    or_grad_at(s, s->phi, x, gp);
+    or_grad_at(s, s->psi, x, gq);
+    or_grad_at(s, s->pi, x, gpi);
+    double F[3];
+    for (int a = 0; a < 3; ++a)
+      F[a] = s->mur[x] * gr[a] + s->mup[x] * gp[a] + s->muq[x] * gq[a] - gpi[a];
+    s->Fx[x] = F[0];
+    s->Fy[x] = F[1];
+    s->Fz[x] = F[2];
+    s->ux[x] = (s->jx[x] + 0.5 * F[0]) / s->rho[x];
+    s->uy[x] = (s->jy[x] + 0.5 * F[1]) / s->rho[x];
+    s->uz[x] = (s->jz[x] + 0.5 * F[2]) / s->rho[x];
+  }
+}
+
+/* A ternary lattice: the binary parameters (kappa1, kappa2, alpha, tau_f,
+ * tau_g, M for phi) plus kappa3, the mobility M3 and relaxation time tau_h
+ * of psi.  Initialisation at equilibrium as in Sec. 2.3:
+ * f = f^eq(rho0, u0), g = g^eq(phi0, mu_phi, u0), h = g^eq(psi0, mu_psi, u0)
+ * with the potentials of the initial fields.  psi0 on the fluid domain. */
+or_state *or3_create(const or_params *p, double kappa3, double M3, double tau_h,
+                     const uint8_t *mask, const double *phi0, const double *psi0,
+                     const double *rho0, const double *u0) {
+  or_state *s = or_create_geometry(p, mask);
+  if (!s) return NULL;
+  s->ternary = 1;
+  s->kappa3 = kappa3;
+  s->M3 = M3;
+  s->tau_h = tau_h;
+  size_t nc = (size_t)s->ncell, d = sizeof(double);
+  s->h = (double *)or_zalloc(nc * s->q * d);
+  s->hn = (double *)or_zalloc(nc * s->q * d);
+  s->psi = (double *)or_zalloc(nc * d);
+  s->lq = (double *)or_zalloc(nc * d);
+  s->muq = (double *)or_zalloc(nc * d);
+  long N = (long)p->nx * p->ny * p->nz;
+  double *U[3];
+  for (int a = 0; a < 3; ++a) U[a] = (double *)or_zalloc(nc * d);
+  for (long u = 0; u < N; ++u) {
+    long e = or_user_to_ext(s, u);
+    if (s->kind[e] != OR_FLUID) continue;
+    s->phi[e] = phi0[u];
+    s->psi[e] = psi0[u];
+    s->rho[e] = rho0 ? rho0[u] : 1.0;
+    if (u0)
+      for (int a = 0; a < 3; ++a) U[a][e] = u0[(long)a * N + u];
+  }
+  or3_potentials(s);
+  double G = or_gamma(s), G3 = or3_gamma(s);
+  for (long e = 0; e < s->ncell; ++e) {
+    if (s->kind[e] != OR_FLUID) continue;
+    double uu[3] = {U[0][e], U[1][e], U[2][e]};
+    or_feq(p->kind, s->rho[e], uu, &s->f[e * s->q]);
+    or_geq(p->kind, s->phi[e], s->mup[e], G, uu, &s->g[e * s->q]);
+    or_geq(p->kind, s->psi[e], s->muq[e], G3, uu, &s->h[e * s->q]);
+  }
+  for (int a = 0; a < 3; ++a) free(U[a]);
+  s->t = 0;
+  return s;
+}
+
+/* One ternary time step: the binary step with the third order parameter. */
+static void or3_step1(or_state *s) {
+  int q = s->q, kind = s->p.kind;
+  const int(*c)[3] = or_c(kind);
+  const double *w = or_w(kind);
+  double G = or_gamma(s), G3 = or3_gamma(s);
+  double tf = s->p.tau_f, tg = s->p.tau_g, th = s->tau_h;
+  or3_moments(s);
+  or3_potentials(s);
+  or3_force_velocity(s);
+#pragma omp parallel for schedule(static)
+  for (long x = 0; x < s->ncell; ++x) {
+    if (s->kind[x] != OR_FLUID) continue;
+    double u[3] = {s->ux[x], s->uy[x], s->uz[x]};
+    double F[3] = {s->Fx[x], s->Fy[x], s->Fz[x]};
+    double feq[OR_MAXQ], geq[OR_MAXQ], heq[OR_MAXQ], S[OR_MAXQ];
+    or_feq(kind, s->rho[x], u, feq);
+    or_guo(kind, tf, u, F, S);
+    or_geq(kind, s->phi[x], s->mup[x], G, u, geq);
+    or_geq(kind, s->psi[x], s->muq[x], G3, u, heq);
+    for (int i = 0; i < q; ++i) {
+      double fs = s->f[x * q + i] - (s->f[x * q + i] - feq[i]) / tf + S[i];
+      double gs = s->g[x * q + i] - (s->g[x * q + i] - geq[i]) / tg;
+      double hs = s->h[x * q + i] - (s->h[x * q + i] - heq[i]) / th;
+      long y = or_nb(s, x, i);
+      if (y >= 0 && s->kind[y] == OR_FLUID) {
+        s->fn[y * q + i] = fs;
+        s->gn[y * q + i] = gs;
+        s->hn[y * q + i] = hs;
+      } else {
+        double uw[3];
+        or_body_velocity(s, x, y, i, uw);
+        double cu = c[i][0] * uw[0] + c[i][1] * uw[1] + c[i][2] * uw[2];
+        int ib = or_opp(i);
+        s->fn[x * q + ib] = fs - 2.0 * w[i] * s->rho[x] * cu / CS2;
+        s->gn[x * q + ib] = gs - 2.0 * w[i] * s->phi[x] * cu / CS2;
+        s->hn[x * q + ib] = hs - 2.0 * w[i] * s->psi[x] * cu / CS2;
+      }
+    }
+  }
+  double *t1 = s->f; s->f = s->fn; s->fn = t1;
+  double *t2 = s->g; s->g = s->gn; s->gn = t2;
+  double *t3 = s->h; s->h = s->hn; s->hn = t3;
+  s->t += 1;
+}
+
+void or3_step(or_state *s, long n) {
+  for (long k = 0; k < n; ++k) or3_step1(s);
+}
+
+/* Ternary observables on the fluid domain: out has 11*N entries: rho, phi,
+ * psi, ux, uy, uz, mu_rho, mu_phi, mu_psi, P, solid flag, with P = cs^2 rho
+ * + Pi - psi_b. */
+void or3_observe(or_state *s, double *out) {
+  or3_moments(s);
+  or3_potentials(s);
+  or3_force_velocity(s);
+  long N = (long)s->p.nx * s->p.ny * s->p.nz;
+  for (long u = 0; u < N; ++u) {
+    long e = or_user_to_ext(s, u);
+    double *o[11];
+    for (int k = 0; k < 11; ++k) o[k] = out + (long)k * N + u;
+    if (s->kind[e] != OR_FLUID) {
+      for (int k = 0; k < 10; ++k) *o[k] = 0.0;
+      *o[10] = 1.0;
+      continue;
+    }
+    double r = s->rho[e], ph = s->phi[e], ps = s->psi[e];
+    *o[0] = r;
+    *o[1] = ph;
+    *o[2] = ps;
+    *o[3] = s->ux[e];
+    *o[4] = s->uy[e];
+    *o[5] = s->uz[e];
+    *o[6] = s->mur[e];
+    *o[7] = s->mup[e];
+    *o[8] = s->muq[e];
+    *o[9] = CS2 * r + r * s->mur[e] + ph * s->mup[e] + ps * s->muq[e] -
+            or3_psi_bulk(s->p.kappa1, s->p.kappa2, s->kappa3, r, ph, ps);
+    *o[10] = 0.0;
+  }
+}
+
+/* Ternary populations on the fluid domain, layout [q][N] each. */
+void or3_get_populations(const or_state *s, double *f_out, double *g_out,
+                         double *h_out) {
+  or_get_populations(s, f_out, g_out);
+  long N = (long)s->p.nx * s->p.ny * s->p.nz;
+  for (long u = 0; u < N; ++u) {
+    long e = or_user_to_ext(s, u);
+    for (int i = 0; i < s->q; ++i)
+      h_out[(long)i * N + u] = s->kind[e] == OR_FLUID ? s->h[e * s->q + i] : 0.0;
+  }
 }

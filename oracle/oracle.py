@@ -85,6 +85,14 @@ def lib():
         L.or_get_populations.argtypes = [C.c_void_p, dp, dp]
         L.or_set_populations.argtypes = [C.c_void_p, dp, dp]
         L.or_stencils.argtypes = [C.c_void_p, dp, dp, dp]
+        L.or3_mu.argtypes = [C.c_double] * 10 + [dp]
+        L.or3_psi_bulk.argtypes = [C.c_double] * 6
+        L.or3_psi_bulk.restype = C.c_double
+        L.or3_create.restype = C.c_void_p
+        L.or3_create.argtypes = [C.POINTER(Params), C.c_double, C.c_double, C.c_double, C.c_void_p, dp, dp, dp, dp]
+        L.or3_step.argtypes = [C.c_void_p, C.c_long]
+        L.or3_observe.argtypes = [C.c_void_p, dp]
+        L.or3_get_populations.argtypes = [C.c_void_p, dp, dp, dp]
         _lib = L
     return _lib
 
@@ -244,3 +252,73 @@ class Lattice:
         grad = np.zeros(3 * self.N)
         lib().or_stencils(self._h, _dp(X), _dp(lap), _dp(grad))
         return lap.reshape(self.shape), grad.reshape(3, *self.shape)
+
+
+# --------------------------------------------------------------------------
+# ternary extension (Sec. 2.2, Remark after the mobility relation)
+# --------------------------------------------------------------------------
+def mu3(kappa1, kappa2, kappa3, alpha, rho, phi, psi, lap_rho, lap_phi, lap_psi):
+    """(mu_rho, mu_phi, mu_psi) of the ternary free energy at a node."""
+    out = np.zeros(3)
+    lib().or3_mu(kappa1, kappa2, kappa3, alpha, rho, phi, psi, lap_rho, lap_phi, lap_psi, _dp(out))
+    return tuple(out)
+
+
+def psi_bulk3(kappa1, kappa2, kappa3, rho, phi, psi):
+    """Bulk free-energy density of the ternary functional."""
+    return lib().or3_psi_bulk(kappa1, kappa2, kappa3, rho, phi, psi)
+
+
+OBS3_FIELDS = ("rho", "phi", "psi", "ux", "uy", "uz", "mu_rho", "mu_phi", "mu_psi", "P", "solid")
+
+
+class Lattice3:
+    """A ternary oracle lattice: the binary parameters (phi's mobility M,
+    tau_g) plus kappa3 and psi's mobility M3 and relaxation time tau_h.
+    Fields are numpy arrays shaped (nz, ny, nx)."""
+
+    def __init__(self, params: Params, kappa3, M3, tau_h, phi0, psi0, rho0=None, u0=None, mask=None):
+        self.params = params
+        self.shape = (params.nz, params.ny, params.nx)
+        self.N = params.nx * params.ny * params.nz
+        self.q = 9 if params.kind == 0 else 19
+        phi0 = np.ascontiguousarray(np.asarray(phi0, dtype=np.float64).reshape(-1))
+        psi0 = np.ascontiguousarray(np.asarray(psi0, dtype=np.float64).reshape(-1))
+        rho0 = None if rho0 is None else np.ascontiguousarray(np.asarray(rho0, np.float64).reshape(-1))
+        u0 = None if u0 is None else np.ascontiguousarray(np.asarray(u0, np.float64).reshape(3, -1))
+        self._mask = None if mask is None else np.ascontiguousarray(np.asarray(mask, np.uint8).reshape(-1))
+        self._keep = (phi0, psi0, rho0, u0)
+        self._h = lib().or3_create(C.byref(params), float(kappa3), float(M3), float(tau_h),
+                                   None if self._mask is None else self._mask.ctypes.data,
+                                   _dp(phi0), _dp(psi0),
+                                   None if rho0 is None else _dp(rho0),
+                                   None if u0 is None else _dp(u0))
+        if not self._h:
+            raise ValueError("oracle rejected the lattice parameters")
+
+    def __del__(self):
+        h = getattr(self, "_h", None)
+        if h and lib is not None:
+            lib().or_destroy(h)
+            self._h = None
+
+    @property
+    def t(self) -> int:
+        return lib().or_time(self._h)
+
+    def step(self, n: int = 1):
+        lib().or3_step(self._h, int(n))
+        return self
+
+    def observe(self) -> dict:
+        out = np.zeros(11 * self.N)
+        lib().or3_observe(self._h, _dp(out))
+        out = out.reshape(11, *self.shape)
+        return {k: out[i] for i, k in enumerate(OBS3_FIELDS)}
+
+    def populations(self):
+        f = np.zeros(self.q * self.N)
+        g = np.zeros(self.q * self.N)
+        h = np.zeros(self.q * self.N)
+        lib().or3_get_populations(self._h, _dp(f), _dp(g), _dp(h))
+        return tuple(a.reshape(self.q, *self.shape) for a in (f, g, h))
