@@ -64,6 +64,8 @@ typedef int32_t fre_status;
 #define FRE_F_MU_RHO 8u
 #define FRE_F_MU_PHI 16u
 #define FRE_F_P 32u
+#define FRE_F_PSI 64u     /* ternary lattices only */
+#define FRE_F_MU_PSI 128u /* ternary lattices only */
 
 /* A staircase cylinder (rotating roller): the cells whose mask code is 2+k
  * move rigidly with angular velocity omega about the line through `center`
@@ -88,7 +90,17 @@ typedef struct fre_roller {
  *    use_paper_form = 1, kappa1, kappa2, alpha are used as given.
  *  tau_f, tau_g > 1/2: relaxation times; M > 0: mobility, with
  *    Gamma = M / (tau_g - 1/2) (Sec. 2.2, mobility relation).
- *  reserved1: must be 0.
+ *  ternary (0 or 1): a third component (Sec. 2.2, Remark after the mobility
+ *    relation): a third order parameter psi with its own Cahn-Hilliard
+ *    population h, the free energy of the cited ternary model (in the
+ *    concentrations C1 = (rho + phi - psi)/2, C2 = (rho - phi - psi)/2,
+ *    C3 = psi: sum_m kappa_m/2 C_m^2 (1 - C_m)^2 + alpha^2 kappa_m/2
+ *    |grad C_m|^2, which is eq. (functional) for C3 = 0), kappa3 > 0, and
+ *    psi's mobility M3 >= 0 with relaxation time tau_h > 1/2
+ *    (Gamma_psi = M3 / (tau_h - 1/2)).  FP32 storage only; created with
+ *    fre_lattice_init3, stepped alone (not in batches), no consistent
+ *    initialisation or launch-shape tuning.  kappa3, M3, tau_h are ignored
+ *    when ternary = 0.
  * Validation: tau > 1/2, kappa1, kappa2, alpha > 0 (A, kappa > 0), M > 0,
  * |wall_u| <= 0.1 and |omega| * radius <= 0.1 (Mach guard), sizes >= 1,
  * storage/kind/bc codes in range. */
@@ -104,8 +116,9 @@ typedef struct fre_params {
   double A, kappa;
   double kappa1, kappa2, alpha;
   int32_t use_paper_form;
-  int32_t reserved1;
+  int32_t ternary;
   double tau_f, tau_g, M;
+  double kappa3, M3, tau_h;
 } fre_params;
 
 typedef struct fre_lattice fre_lattice;
@@ -127,6 +140,15 @@ fre_status fre_lattice_init(const fre_params *p, void *device_buf, size_t bytes,
                             void *hip_stream, const double *phi0,
                             const double *rho0, const double *u0,
                             const uint8_t *solid_mask, fre_lattice **out);
+
+/* A ternary lattice (params->ternary = 1): as fre_lattice_init with the
+ * third order parameter psi0 (N values, host, required; C3 = psi).  The
+ * populations start at their equilibria f^eq(rho0, u0), g^eq(phi0, mu_phi,
+ * u0), h^eq(psi0, mu_psi, u0) with the potentials of the initial fields.
+ * fre_lattice_init refuses ternary parameters. */
+fre_status fre_lattice_init3(const fre_params *p, void *device_buf, size_t bytes, void *hip_stream,
+                             const double *phi0, const double *psi0, const double *rho0, const double *u0,
+                             const uint8_t *solid_mask, fre_lattice **out);
 
 /* Consistent initialisation (Sec. 2.3, which starts from equilibrium and
  * aligns the kinetic moments by collisions, citing Mei, Luo, Lallemand and
@@ -157,7 +179,9 @@ fre_status fre_step(fre_lattice *L, int64_t n);
 /* Observables at the current time, without stepping: the fields selected by
  * field_mask (FRE_F_*) in bit order, each N doubles (U: 3N), into host_out
  * of n_doubles.  u includes F/2 (eq. veloMoment); P is the bulk pressure
- * cs^2 rho + rho mu_rho + phi mu_phi - psi_b.  Solid cells read 0.  Syncs. */
+ * cs^2 rho + rho mu_rho + phi mu_phi - psi_b (ternary: + psi mu_psi, and the
+ * ternary bulk density).  Ternary lattices also take FRE_F_PSI and
+ * FRE_F_MU_PSI.  Solid cells read 0.  Syncs. */
 fre_status fre_read_moments(fre_lattice *L, uint32_t field_mask,
                             double *host_out, size_t n_doubles);
 
@@ -168,6 +192,12 @@ fre_status fre_read_moments(fre_lattice *L, uint32_t field_mask,
  * overwrites the auxiliary field that fre_read_moments recomputes).  Syncs. */
 fre_status fre_read_populations(fre_lattice *L, double *f_out, double *g_out,
                                 size_t n_doubles_each);
+
+/* The three populations f_i, g_i, h_i of a ternary lattice, as
+ * fre_read_populations (g_0 and h_0 with their low parts).
+ * fre_read_populations refuses ternary lattices. */
+fre_status fre_read_populations3(fre_lattice *L, double *f_out, double *g_out, double *h_out,
+                                 size_t n_doubles_each);
 
 /* Global sums over fluid cells, accumulated in FP64 on the device from
  * compensated FP32 partials: out[0] sum rho, [1] sum phi, [2] sum |phi|,

@@ -56,14 +56,20 @@ struct Plan {
   int off[3];
   int px;          // row pitch: ext[0] rounded up to a multiple of 64
   long long ncell;  // px * ext[1] * ext[2]
-  size_t o_f, o_g, o_g0, o_mask, o_nbm, o_M, o_C, o_P0, o_PU, o_PD, o_XE, o_AUX, o_fill, o_part, total;
+  size_t o_f, o_g, o_g0, o_h, o_h0, o_mask, o_nbm, o_M, o_C, o_CM, o_P0, o_PU, o_PD, o_XE, o_AUX, o_fill, o_part, total;
 };
 
 fre_status validate(const fre_params *p) {
   if (!p) return fail(FRE_EINVAL, "params is NULL");
   if (p->kind != FRE_D2Q9 && p->kind != FRE_D3Q19) return fail(FRE_EINVAL, "kind %d not D2Q9/D3Q19", p->kind);
   if (p->storage != FRE_FP32 && p->storage != FRE_FP16) return fail(FRE_EINVAL, "storage %d", p->storage);
-  if (p->reserved1 != 0) return fail(FRE_EINVAL, "reserved1 must be 0");
+  if (p->ternary != 0 && p->ternary != 1) return fail(FRE_EINVAL, "ternary must be 0 or 1 (got %d)", p->ternary);
+  if (p->ternary) {
+    if (p->storage != FRE_FP32) return fail(FRE_EINVAL, "ternary lattices need FP32 storage");
+    if (!(p->kappa3 > 0) || !std::isfinite(p->kappa3)) return fail(FRE_EINVAL, "kappa3 must be > 0");
+    if (!(p->tau_h > 0.5) || !std::isfinite(p->tau_h)) return fail(FRE_EINVAL, "tau_h must exceed 1/2");
+    if (!(p->M3 >= 0.0) || !std::isfinite(p->M3)) return fail(FRE_EINVAL, "mobility M3 must be >= 0");
+  }
   if (p->nx < 1 || p->ny < 1 || p->nz < 1) return fail(FRE_EINVAL, "sizes must be >= 1");
   for (int a = 0; a < 3; ++a)
     if (p->bc[a] != FRE_PERIODIC && p->bc[a] != FRE_WALL) return fail(FRE_EINVAL, "bc[%d]=%d", a, p->bc[a]);
@@ -127,12 +133,21 @@ Plan make_plan(const fre_params *p) {
     P.o_g = take((size_t)P.q * P.ncell * 2);
     P.o_g0 = take((size_t)P.ncell * 4);
   }
+  const bool t3 = p->ternary != 0;
+  if (t3) {
+    // the third population and the low part of its rest population, inside
+    // the population range (checkpoints carry them)
+    P.o_h = take((size_t)P.q * P.ncell * 4);
+    P.o_h0 = take((size_t)P.ncell * 2);
+  }
   P.o_mask = take((size_t)P.ncell);
   P.o_nbm = take((size_t)P.ncell * 4);
-  P.o_M = take((size_t)P.ncell * 8);
+  P.o_M = take((size_t)P.ncell * (t3 ? 16 : 8));
   P.o_C = take((size_t)P.ncell * 16);
-  // FP32: first-pass moment sums of the collide (same plane; below and above in 3D)
-  const bool bp = p->storage == FRE_FP32;
+  P.o_CM = t3 ? take((size_t)P.ncell * 8) : 0;
+  // FP32: first-pass moment sums of the collide (same plane; below and above
+  // in 3D); the ternary step has no by-product moments
+  const bool bp = p->storage == FRE_FP32 && !t3;
   P.o_P0 = bp ? take((size_t)P.ncell * 8) : 0;
   P.o_PU = bp && P.q == 19 ? take((size_t)P.ncell * 8) : 0;
   P.o_PD = bp && P.q == 19 ? take((size_t)P.ncell * 8) : 0;
@@ -165,6 +180,11 @@ Phys make_phys(const fre_params *p) {
   for (int a = 0; a < 3; ++a)
     for (int s = 0; s < 2; ++s)
       for (int b = 0; b < 3; ++b) ph.wall_u[a][s][b] = (float)p->wall_u[a][s][b];
+  if (p->ternary) {
+    ph.k3 = (float)p->kappa3;
+    ph.om_h = (float)(1.0 / p->tau_h);
+    ph.gam3h = (float)(3.0 * p->M3 / (p->tau_h - 0.5));
+  }
   ph.n_rollers = p->n_rollers;
   for (int k = 0; k < p->n_rollers; ++k) {
     for (int a = 0; a < 3; ++a) ph.rc[k][a] = (float)p->rollers[k].center[a];
@@ -311,14 +331,25 @@ void bind_args(fre_lattice *L) {
   a.PD = P.o_PD ? (float2 *)(L->base + P.o_PD) : nullptr;
   a.XE = P.o_XE ? (float2 *)(L->base + P.o_XE) : nullptr;
   a.AUX = (float4 *)(L->base + P.o_AUX);
+  a.ternary = L->p.ternary;
+  a.h = P.o_h ? L->base + P.o_h : nullptr;
+  a.h0l = P.o_h0 ? (__half *)(L->base + P.o_h0) : nullptr;
+  a.CM = P.o_CM ? (float2 *)(L->base + P.o_CM) : nullptr;
   a.fill_list = (int *)(L->base + P.o_fill);
   a.n_fill = (int)L->fill_host.size();
 }
 
 size_t pops_bytes(const Plan &P, int storage) { return P.o_mask - P.o_f; }
 
+// one step of either kind of lattice
+void launch_lattice_step(const LaunchArgs &a, int odd) {
+  if (a.ternary) launch_step3(a, odd);
+  else launch_step(a, odd);
+}
+
 fre_status observe(fre_lattice *L) {
-  launch_observe(L->a, (int)(L->t & 1));
+  if (L->a.ternary) launch_observe3(L->a, (int)(L->t & 1));
+  else launch_observe(L->a, (int)(L->t & 1));
   HIP_TRY(hipGetLastError());
   return FRE_OK;
 }
@@ -337,13 +368,21 @@ fre_status fre_footprint(const fre_params *p, size_t *device_bytes) {
   return FRE_OK;
 }
 
-fre_status fre_lattice_init(const fre_params *p, void *device_buf, size_t bytes, void *hip_stream,
-                            const double *phi0, const double *rho0, const double *u0,
-                            const uint8_t *solid_mask, fre_lattice **out) {
+}  // extern "C"
+
+namespace {
+
+// fre_lattice_init and fre_lattice_init3: psi0 is NULL for a binary lattice
+fre_status lattice_init(const fre_params *p, void *device_buf, size_t bytes, void *hip_stream,
+                        const double *phi0, const double *psi0, const double *rho0, const double *u0,
+                        const uint8_t *solid_mask, fre_lattice **out) {
   if (!out) return fail(FRE_EINVAL, "out is NULL");
   *out = nullptr;
   fre_status s = validate(p);
   if (s != FRE_OK) return s;
+  const bool t3 = p->ternary != 0;
+  if (t3 && !psi0) return fail(FRE_EINVAL, "a ternary lattice needs psi0 (use fre_lattice_init3)");
+  if (!t3 && psi0) return fail(FRE_EINVAL, "psi0 given for a binary lattice (set ternary = 1)");
   if (!phi0) return fail(FRE_EINVAL, "phi0 is NULL");
   if (!device_buf) return fail(FRE_EINVAL, "device_buf is NULL");
   if ((uintptr_t)device_buf % kAlign) return fail(FRE_EINVAL, "device_buf must be 256-byte aligned");
@@ -351,7 +390,8 @@ fre_status fre_lattice_init(const fre_params *p, void *device_buf, size_t bytes,
   if (bytes < P.total) return fail(FRE_ENOMEM, "buffer of %zu bytes < footprint %zu", bytes, P.total);
   long long N = (long long)p->nx * p->ny * p->nz;
   for (long long u = 0; u < N; ++u) {
-    if (!std::isfinite(phi0[u]) || (rho0 && !(std::isfinite(rho0[u]) && rho0[u] > 0)) ||
+    if (!std::isfinite(phi0[u]) || (psi0 && !std::isfinite(psi0[u])) ||
+        (rho0 && !(std::isfinite(rho0[u]) && rho0[u] > 0)) ||
         (u0 && !(std::isfinite(u0[u]) && std::isfinite(u0[N + u]) && std::isfinite(u0[2 * N + u]))))
       return fail(FRE_EINVAL, "non-finite or non-positive initial value at cell %lld", u);
   }
@@ -372,15 +412,18 @@ fre_status fre_lattice_init(const fre_params *p, void *device_buf, size_t bytes,
   for (int k = 0; k < N_SHAPES; ++k) L->a.shape[k] = Shape{4, 1};
   L->a.stream = (hipStream_t)hip_stream;
   // initial fields in storage layout
-  std::vector<float> M((size_t)P.ncell * 2, 0.0f), U((size_t)P.ncell * 4, 0.0f);
+  // M: (rho - 1, phi), or (rho - 1, phi, psi, 0) on a ternary lattice
+  const int mw = t3 ? 4 : 2;
+  std::vector<float> M((size_t)P.ncell * mw, 0.0f), U((size_t)P.ncell * 4, 0.0f);
   for (int z = 0; z < p->nz; ++z)
     for (int y = 0; y < p->ny; ++y)
       for (int x = 0; x < p->nx; ++x) {
         long long u = x + (long long)p->nx * (y + (long long)p->ny * z);
         long long e = ext_index(P, x, y, z);
         if (mask[e] != CELL_FLUID) continue;
-        M[2 * e] = rho0 ? (float)(rho0[u] - 1.0) : 0.0f;
-        M[2 * e + 1] = (float)phi0[u];
+        M[mw * e] = rho0 ? (float)(rho0[u] - 1.0) : 0.0f;
+        M[mw * e + 1] = (float)phi0[u];
+        if (t3) M[mw * e + 2] = (float)psi0[u];
         if (u0)
           for (int k = 0; k < 3; ++k) U[4 * e + k] = (float)u0[(long long)k * N + u];
       }
@@ -400,12 +443,45 @@ fre_status fre_lattice_init(const fre_params *p, void *device_buf, size_t bytes,
     INIT_TRY(hipMemcpyAsync(L->a.fill_list, L->fill_host.data(), L->fill_host.size() * 4, hipMemcpyHostToDevice, st));
   INIT_TRY(hipMemcpyAsync(L->a.nbm, nbm.data(), nbm.size() * 4, hipMemcpyHostToDevice, st));
   INIT_TRY(hipMemsetAsync(L->a.C, 0, (size_t)P.ncell * 16, st));
-  launch_init(L->a);
+  if (t3) {
+    INIT_TRY(hipMemsetAsync(L->a.CM, 0, (size_t)P.ncell * 8, st));
+    launch_init3(L->a);
+  } else {
+    launch_init(L->a);
+  }
   INIT_TRY(hipGetLastError());
   INIT_TRY(hipStreamSynchronize(st));
 #undef INIT_TRY
   *out = L;
   return FRE_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+fre_status fre_lattice_init(const fre_params *p, void *device_buf, size_t bytes, void *hip_stream,
+                            const double *phi0, const double *rho0, const double *u0,
+                            const uint8_t *solid_mask, fre_lattice **out) {
+  if (p && p->ternary) {
+    if (out) *out = nullptr;
+    return fail(FRE_EINVAL, "ternary lattices are created with fre_lattice_init3");
+  }
+  return lattice_init(p, device_buf, bytes, hip_stream, phi0, nullptr, rho0, u0, solid_mask, out);
+}
+
+fre_status fre_lattice_init3(const fre_params *p, void *device_buf, size_t bytes, void *hip_stream,
+                             const double *phi0, const double *psi0, const double *rho0, const double *u0,
+                             const uint8_t *solid_mask, fre_lattice **out) {
+  if (p && !p->ternary) {
+    if (out) *out = nullptr;
+    return fail(FRE_EINVAL, "fre_lattice_init3 needs ternary = 1");
+  }
+  if (!psi0) {
+    if (out) *out = nullptr;
+    return fail(FRE_EINVAL, "psi0 is NULL");
+  }
+  return lattice_init(p, device_buf, bytes, hip_stream, phi0, psi0, rho0, u0, solid_mask, out);
 }
 
 fre_status fre_consistent_init(fre_lattice *L, const double *phi0, const double *u0, int64_t n) {
@@ -416,6 +492,7 @@ fre_status fre_consistent_init(fre_lattice *L, const double *phi0, const double 
   if (L->state) return fail(FRE_ESTATE, "lattice is in the failed state");
   if (L->batch) return fail(FRE_ESTATE, "lattice is a batch member: remove it first");
   if (L->t != 0) return fail(FRE_ESTATE, "consistent initialisation is only possible before the first step");
+  if (L->p.ternary) return fail(FRE_EINVAL, "consistent initialisation is not available for ternary lattices");
   const fre_params *p = &L->p;
   const Plan &P = L->plan;
   const long long N = L->n_user;
@@ -449,8 +526,9 @@ fre_status fre_set_params(fre_lattice *L, const fre_params *p) {
   if (L->batch) return fail(FRE_ESTATE, "lattice is a batch member: remove it before changing parameters");
   const fre_params &o = L->p;
   if (p->kind != o.kind || p->nx != o.nx || p->ny != o.ny || p->nz != o.nz || p->storage != o.storage ||
-      p->bc[0] != o.bc[0] || p->bc[1] != o.bc[1] || p->bc[2] != o.bc[2] || p->n_rollers != o.n_rollers)
-    return fail(FRE_EINVAL, "shape, storage, bc and roller count cannot change");
+      p->bc[0] != o.bc[0] || p->bc[1] != o.bc[1] || p->bc[2] != o.bc[2] || p->n_rollers != o.n_rollers ||
+      p->ternary != o.ternary)
+    return fail(FRE_EINVAL, "shape, storage, bc, roller count and the ternary flag cannot change");
   L->p = *p;
   L->a.ph = make_phys(p);
   reset_graph(L);
@@ -464,7 +542,7 @@ fre_status fre_step(fre_lattice *L, int64_t n) {
   if (L->batch) return fail(FRE_ESTATE, "lattice is a batch member: step the batch");
   hipStream_t st = L->a.stream;
   auto one = [&]() -> fre_status {
-    launch_step(L->a, (int)(L->t & 1));
+    launch_lattice_step(L->a, (int)(L->t & 1));
     HIP_TRY(hipGetLastError());
     L->t += 1;
     return FRE_OK;
@@ -484,8 +562,8 @@ fre_status fre_step(fre_lattice *L, int64_t n) {
   if (!L->graph_ok) {
     hipGraph_t g;
     HIP_TRY(hipStreamBeginCapture(st, hipStreamCaptureModeThreadLocal));
-    launch_step(L->a, 0);
-    launch_step(L->a, 1);
+    launch_lattice_step(L->a, 0);
+    launch_lattice_step(L->a, 1);
     hipError_t e = hipStreamEndCapture(st, &g);
     if (e != hipSuccess) return fail(FRE_EDEVICE, "graph capture failed: %s", hipGetErrorString(e));
     e = hipGraphInstantiate(&L->graph, g, nullptr, nullptr, 0);
@@ -504,25 +582,30 @@ fre_status fre_step(fre_lattice *L, int64_t n) {
 fre_status fre_read_moments(fre_lattice *L, uint32_t field_mask, double *host_out, size_t n_doubles) {
   if (!L || !host_out) return fail(FRE_EINVAL, "NULL argument");
   if (fre_status bs = sync_batch(L)) return bs;
-  if (field_mask == 0 || (field_mask & ~63u)) return fail(FRE_EINVAL, "bad field mask 0x%x", field_mask);
+  const bool t3 = L->p.ternary != 0;
+  const int nfield = t3 ? 8 : 6;
+  if (field_mask == 0 || (field_mask & ~((1u << nfield) - 1u)))
+    return fail(FRE_EINVAL, "bad field mask 0x%x%s", field_mask,
+                (!t3 && (field_mask & (FRE_F_PSI | FRE_F_MU_PSI))) ? " (psi fields need a ternary lattice)" : "");
   size_t need = 0;
   const long long N = L->n_user;
-  for (int b = 0; b < 6; ++b)
+  for (int b = 0; b < nfield; ++b)
     if (field_mask & (1u << b)) need += (b == 2 ? 3 : 1) * (size_t)N;
   if (n_doubles < need) return fail(FRE_EINVAL, "output holds %zu doubles, need %zu", n_doubles, need);
   const Plan &P = L->plan;
   fre_status s = observe(L);
   if (s != FRE_OK) return s;
-  std::vector<float> Cv((size_t)P.ncell * 4), AUX((size_t)P.ncell * 4);
+  std::vector<float> Cv((size_t)P.ncell * 4), AUX((size_t)P.ncell * 4), CM(t3 ? (size_t)P.ncell * 2 : 0);
   std::vector<uint8_t> mask((size_t)P.ncell);
   hipStream_t st = L->a.stream;
   HIP_TRY(hipMemcpyAsync(Cv.data(), L->a.C, Cv.size() * 4, hipMemcpyDeviceToHost, st));
+  if (t3) HIP_TRY(hipMemcpyAsync(CM.data(), L->a.CM, CM.size() * 4, hipMemcpyDeviceToHost, st));
   HIP_TRY(hipMemcpyAsync(AUX.data(), L->a.AUX, AUX.size() * 4, hipMemcpyDeviceToHost, st));
   HIP_TRY(hipMemcpyAsync(mask.data(), L->a.mask, mask.size(), hipMemcpyDeviceToHost, st));
   HIP_TRY(hipStreamSynchronize(st));
   const fre_params &p = L->p;
   double *o = host_out;
-  for (int b = 0; b < 6; ++b) {
+  for (int b = 0; b < nfield; ++b) {
     if (!(field_mask & (1u << b))) continue;
     int ncomp = b == 2 ? 3 : 1;
     for (int k = 0; k < ncomp; ++k) {
@@ -532,7 +615,22 @@ fre_status fre_read_moments(fre_lattice *L, uint32_t field_mask, double *host_ou
             long long u = x + (long long)p.nx * (y + (long long)p.ny * z);
             long long e = ext_index(P, x, y, z);
             double v = 0.0;
-            if (mask[e] == CELL_FLUID) {
+            if (mask[e] == CELL_FLUID && t3) {
+              // C = (rho - 1, phi, psi, Pi), CM = (mu_phi, mu_psi):
+              // mu_rho = (Pi - phi mu_phi - psi mu_psi) / rho
+              const double rho = 1.0 + (double)Cv[4 * e];
+              switch (b) {
+                case 0: v = rho; break;
+                case 1: v = Cv[4 * e + 1]; break;
+                case 2: v = AUX[4 * e + k]; break;
+                case 3: v = ((double)Cv[4 * e + 3] - (double)Cv[4 * e + 1] * CM[2 * e] -
+                             (double)Cv[4 * e + 2] * CM[2 * e + 1]) / rho; break;
+                case 4: v = CM[2 * e]; break;
+                case 5: v = AUX[4 * e + 3]; break;
+                case 6: v = Cv[4 * e + 2]; break;
+                default: v = CM[2 * e + 1]; break;
+              }
+            } else if (mask[e] == CELL_FLUID) {
               switch (b) {
                 case 0: v = 1.0 + (double)Cv[4 * e]; break;
                 case 1: v = Cv[4 * e + 1]; break;
@@ -553,6 +651,7 @@ fre_status fre_read_moments(fre_lattice *L, uint32_t field_mask, double *host_ou
 
 fre_status fre_read_populations(fre_lattice *L, double *f_out, double *g_out, size_t n_doubles_each) {
   if (!L || !f_out || !g_out) return fail(FRE_EINVAL, "NULL argument");
+  if (L->p.ternary) return fail(FRE_EINVAL, "ternary lattices are read with fre_read_populations3");
   if (fre_status bs = sync_batch(L)) return bs;
   const Plan &P = L->plan;
   const long long N = L->n_user;
@@ -583,6 +682,46 @@ fre_status fre_read_populations(fre_lattice *L, double *f_out, double *g_out, si
         f_out[(long long)i * N + u] = h[(size_t)i * n + t];
         g_out[(long long)i * N + u] = (double)h[(size_t)(P.q + i) * n + t] +
                                       (i == 0 ? (double)h[(size_t)2 * P.q * n + t] : 0.0);
+      }
+    }
+  }
+  return FRE_OK;
+}
+
+fre_status fre_read_populations3(fre_lattice *L, double *f_out, double *g_out, double *h_out,
+                                 size_t n_doubles_each) {
+  if (!L || !f_out || !g_out || !h_out) return fail(FRE_EINVAL, "NULL argument");
+  if (!L->p.ternary) return fail(FRE_EINVAL, "fre_read_populations3 needs a ternary lattice");
+  const Plan &P = L->plan;
+  const long long N = L->n_user;
+  if (n_doubles_each < (size_t)P.q * N) return fail(FRE_EINVAL, "outputs need q*N doubles each");
+  // staged in chunks through AUX as fre_read_populations: 3q + 2 planes --
+  // f_i + w_i, g_i, h_i, and the low parts of g_0 and h_0
+  const int planes = 3 * P.q + 2;
+  const long long chunk = std::max(1LL, 4 * P.ncell / planes);
+  float *stage = (float *)L->a.AUX;
+  std::vector<float> hb((size_t)planes * (size_t)std::min(chunk, P.ncell));
+  const fre_params &p = L->p;
+  const int odd = (int)(L->t & 1);
+  for (long long c0 = 0; c0 < P.ncell; c0 += chunk) {
+    const int n = (int)std::min(chunk, P.ncell - c0);
+    launch_read_pops3(L->a, odd, stage, c0, n);
+    HIP_TRY(hipGetLastError());
+    HIP_TRY(hipMemcpyAsync(hb.data(), stage, (size_t)planes * n * sizeof(float), hipMemcpyDeviceToHost, L->a.stream));
+    HIP_TRY(hipStreamSynchronize(L->a.stream));
+    for (long long c = c0; c < c0 + n; ++c) {
+      const int x = (int)(c % P.px) - P.off[0];
+      const long long r = c / P.px;
+      const int y = (int)(r % P.ext[1]) - P.off[1], z = (int)(r / P.ext[1]) - P.off[2];
+      if (x < 0 || x >= p.nx || y < 0 || y >= p.ny || z < 0 || z >= p.nz) continue;
+      const long long u = x + (long long)p.nx * (y + (long long)p.ny * z);
+      const size_t t = (size_t)(c - c0);
+      for (int i = 0; i < P.q; ++i) {
+        f_out[(long long)i * N + u] = hb[(size_t)i * n + t];
+        g_out[(long long)i * N + u] = (double)hb[(size_t)(P.q + i) * n + t] +
+                                      (i == 0 ? (double)hb[(size_t)3 * P.q * n + t] : 0.0);
+        h_out[(long long)i * N + u] = (double)hb[(size_t)(2 * P.q + i) * n + t] +
+                                      (i == 0 ? (double)hb[(size_t)(3 * P.q + 1) * n + t] : 0.0);
       }
     }
   }
@@ -732,7 +871,8 @@ fre_status fre_load(fre_lattice *L, const void *host, size_t bytes) {
   if (s != FRE_OK) return s;
   HIP_TRY(hipMemcpyAsync(L->base + L->plan.o_f, (const uint8_t *)host + sizeof h, h.pops_bytes, hipMemcpyHostToDevice, L->a.stream));
   L->t = h.step;
-  launch_moments(L->a, (int)(L->t & 1));  // M of the restored populations
+  if (!L->p.ternary) launch_moments(L->a, (int)(L->t & 1));  // M of the restored populations
+                                                            // (the ternary step makes its own)
   HIP_TRY(hipGetLastError());
   HIP_TRY(hipStreamSynchronize(L->a.stream));
   L->state = 0;
@@ -818,6 +958,7 @@ fre_status fre_profile_step(fre_lattice *L, int64_t n, double *kernel_ms, int32_
   if (L->state) return fail(FRE_ESTATE, "lattice is in the failed state");
   int slot[8];
   const int K = step_kernel_slots(L->a, slot);
+  if (L->p.ternary) return fail(FRE_EINVAL, "per-kernel profiling is not available for ternary lattices");
   if (max_kernels < K) return fail(FRE_EINVAL, "kernel_ms needs %d entries", K);
   if (L->batch) return fail(FRE_ESTATE, "lattice is a batch member: profile it alone");
   fre_status st = time_kernels(L, n, kernel_ms);
@@ -827,6 +968,7 @@ fre_status fre_profile_step(fre_lattice *L, int64_t n, double *kernel_ms, int32_
 
 fre_status fre_set_launch_shape(fre_lattice *L, const int32_t cfg[6]) {
   if (!L || !cfg) return fail(FRE_EINVAL, "NULL argument");
+  if (L->p.ternary) return fail(FRE_EINVAL, "ternary lattices have one launch shape");
   Shape sh[N_SHAPES];
   for (int k = 0; k < N_SHAPES; ++k) {
     sh[k] = Shape{cfg[2 * k], cfg[2 * k + 1]};
@@ -853,6 +995,7 @@ fre_status fre_get_launch_shape(const fre_lattice *L, int32_t cfg[6]) {
 fre_status fre_autotune(fre_lattice *L, int64_t n, int32_t cfg_out[6], double stage_ms[3]) {
   if (!L) return fail(FRE_EINVAL, "lattice is NULL");
   if (n < 2 || n > 10000) return fail(FRE_EINVAL, "n must be in [2, 10000]");
+  if (L->p.ternary) return fail(FRE_EINVAL, "ternary lattices have one launch shape");
   if (L->state) return fail(FRE_ESTATE, "lattice is in the failed state");
   if (L->batch) return fail(FRE_ESTATE, "lattice is a batch member: tune the batch");
   n += n & 1;  // both parities equally
@@ -1078,6 +1221,7 @@ fre_status fre_batch_create(void *device_buf, size_t bytes, void *hip_stream, in
 fre_status fre_batch_add(fre_batch *B, fre_lattice *L, int32_t *slot) {
   if (!B || !L || !slot) return fail(FRE_EINVAL, "NULL argument");
   if (L->batch) return fail(FRE_EINVAL, "lattice is already a batch member");
+  if (L->p.ternary) return fail(FRE_EINVAL, "ternary lattices are stepped on their own");
   if (L->state) return fail(FRE_ESTATE, "lattice is in the failed state");
   int free_slot = -1, members = 0;
   for (int k = 0; k < B->max_slots; ++k) {

@@ -45,6 +45,13 @@ struct LaunchArgs {
   int n_fill;
   Shape shape[N_SHAPES];
   hipStream_t stream;
+  // ternary lattices (FP32): M holds (rho - 1, phi, psi, 0) as float4 and C
+  // (rho - 1, phi, psi, Pi); h is the third population with the half plane
+  // of h_0's low part, CM holds (mu_phi, mu_psi)
+  int ternary;
+  void *h;
+  __half *h0l;
+  float2 *CM;
 };
 
 template <int Q, int S> inline Pops<Q, S> make_pops(const LaunchArgs &a);
@@ -151,6 +158,13 @@ void launch_init(const LaunchArgs &a);
 void launch_consistent_init(const LaunchArgs &a, long long n);
 // Populations of the storage cells [c0, c0 + n) as [2q + 1][n] floats.
 void launch_read_pops(const LaunchArgs &a, int odd, float *out, long long c0, int n);
+// Ternary lattices: one step, the observables (into AUX; C, CM current), the
+// equilibrium initialisation (M filled from host fields, AUX = u0) and the
+// populations of storage cells [c0, c0 + n) as [3q + 2][n] floats.
+void launch_step3(const LaunchArgs &a, int odd);
+void launch_observe3(const LaunchArgs &a, int odd);
+void launch_init3(const LaunchArgs &a);
+void launch_read_pops3(const LaunchArgs &a, int odd, float *out, long long c0, int n);
 // blocks (partials of 8 doubles) of the global reduction
 constexpr int REDUCE_BLOCKS = 1024;
 inline int reduce_blocks() { return REDUCE_BLOCKS; }

@@ -1101,6 +1101,321 @@ __global__ __launch_bounds__(64) void k_reduce_final(const double *__restrict__ 
 }
 
 // ---------------------------------------------------------------------------
+// Ternary lattices (Sec. 2.2, Remark after the mobility relation): a third
+// order parameter psi with its own population h, FP32 storage, one thread
+// per cell in each pass.  A step is k3_moments, k3_fill (M), k3_potential,
+// k3_fill (Pi), k3_collide; the arithmetic follows the binary stages, with
+// the potentials of chem_pot3 and the force
+//   mu_rho grad rho + mu_phi grad phi + mu_psi grad psi - grad Pi,
+//   Pi = rho mu_rho + phi mu_phi + psi mu_psi,
+// the product-rule form of -rho grad mu_rho - phi grad mu_phi - psi grad mu_psi.
+// h_0 and g_0 are carried as hi + lo like g_0 of the binary FP32 state.
+// ---------------------------------------------------------------------------
+template <int Q> struct T3View {
+  float *f, *g, *h;
+  __half *g0l, *h0l;
+  const uint32_t *nbm;
+  const uint8_t *mask;
+  float4 *M4;   // (rho - 1, phi, psi, 0)
+  float4 *C4;   // (rho - 1, phi, psi, Pi)
+  float2 *CM;   // (mu_phi, mu_psi)
+  float4 *AUX;  // u0 at init; (u, P) after observe
+  Geom G;
+  Phys ph;
+  const int *fill;
+  int n_fill;
+  __device__ float ld(const float *a, int i, long long c) const { return ld_at<float, false>(a, blk_offset<4>(Q, i, c)); }
+  __device__ void st(float *a, int i, long long c, float v) const { st_at(a, blk_offset<4>(Q, i, c), v); }
+};
+
+// population i of fluid cell c at parity `odd` (AA pattern, as load_pops)
+template <int Q>
+__device__ __forceinline__ float ld3(const T3View<Q> &T, const float *a, const Nbr &N, long long c, int odd, int i) {
+  using V = VSet<Q>;
+  return (!odd || i == 0) ? T.ld(a, i, c) : T.ld(a, opp(i), N.template back<V>(i));
+}
+
+template <int Q>
+__global__ __launch_bounds__(BX *BY) void k3_moments(T3View<Q> T, int odd) {
+  int x, y, z;
+  long long c;
+  if (!cell_of_thread(T.G, x, y, z, c)) return;
+  if (T.nbm[c] & NB_SELF_SOLID) return;
+  const Nbr N(T.G, x, y, z);
+  float dr = 0.0f, ph = 0.0f, ps = 0.0f;
+#pragma unroll
+  for (int i = 0; i < Q; ++i) {
+    dr += ld3<Q>(T, T.f, N, c, odd, i);
+    ph += ld3<Q>(T, T.g, N, c, odd, i);
+    ps += ld3<Q>(T, T.h, N, c, odd, i);
+  }
+  T.M4[c] = make_float4(dr, ph, ps, 0.0f);
+}
+
+// solid cells next to fluid: (rho - 1, phi, psi) into M4 (PI = 0), or Pi into
+// C4 with (rho - 1, phi, psi) copied from M4 (PI = 1); the lattice-weighted
+// mean over fluid neighbours (reading R5)
+template <int Q, int PI>
+__global__ __launch_bounds__(256) void k3_fill(T3View<Q> T) {
+  const int k = blockIdx.x * blockDim.x + threadIdx.x;
+  if (k >= T.n_fill) return;
+  const int s = T.fill[k];
+  int x, y, z;
+  cell_coords(T.G, s, x, y, z);
+  if (PI) {
+    float pi;
+    fluid_mean<Q, 1, 4>((const float *)T.C4 + 3, T.nbm[s], T.G, x, y, z, &pi);
+    const float4 m = T.M4[s];
+    T.C4[s] = make_float4(m.x, m.y, m.z, pi);
+  } else {
+    float v[3];
+    fluid_mean<Q, 3, 4>((const float *)T.M4, T.nbm[s], T.G, x, y, z, v);
+    T.M4[s] = make_float4(v[0], v[1], v[2], 0.0f);
+  }
+}
+
+template <int Q>
+__device__ __forceinline__ void t3_potential_at(const T3View<Q> &T, const Nbr &N, long long c) {
+  using V = VSet<Q>;
+  const float4 m0 = T.M4[c];
+  float ar = 0.0f, ap = 0.0f, aq = 0.0f;
+#pragma unroll
+  for (int i = 1; i < Q; ++i) {
+    const float4 m = T.M4[N.template at<V>(i)];
+    ar += V::w(i) * (m.x - m0.x);
+    ap += V::w(i) * (m.y - m0.y);
+    aq += V::w(i) * (m.z - m0.z);
+  }
+  float mr, mp, mq;
+  chem_pot3(T.ph, m0.x, m0.y, m0.z, 6.0f * ar, 6.0f * ap, 6.0f * aq, mr, mp, mq);
+  T.C4[c] = make_float4(m0.x, m0.y, m0.z, (1.0f + m0.x) * mr + m0.y * mp + m0.z * mq);
+  T.CM[c] = make_float2(mp, mq);
+}
+
+template <int Q>
+__global__ __launch_bounds__(BX *BY) void k3_potential(T3View<Q> T) {
+  int x, y, z;
+  long long c;
+  if (!cell_of_thread(T.G, x, y, z, c)) return;
+  if (T.nbm[c] & NB_SELF_SOLID) return;
+  t3_potential_at<Q>(T, Nbr(T.G, x, y, z), c);
+}
+
+// force and mu_rho of a fluid cell from C4, CM
+template <int Q>
+__device__ __forceinline__ void t3_force(const T3View<Q> &T, const Nbr &N, long long c, float F[3], float &mu_phi,
+                                         float &mu_psi) {
+  using V = VSet<Q>;
+  const float4 cc = T.C4[c];
+  const float2 cm = T.CM[c];
+  mu_phi = cm.x;
+  mu_psi = cm.y;
+  const float mu_rho = (cc.w - cc.y * cm.x - cc.z * cm.y) / (1.0f + cc.x);
+  float gr[3] = {0, 0, 0}, gp[3] = {0, 0, 0}, gq[3] = {0, 0, 0}, gw[3] = {0, 0, 0};
+#pragma unroll
+  for (int i = 1; i < Q; ++i) {
+    const float4 m = T.C4[N.template at<V>(i)];
+    const float w = 3.0f * V::w(i);
+    const int cv[3] = {V::cx(i), V::cy(i), V::cz(i)};
+#pragma unroll
+    for (int a = 0; a < 3; ++a) {
+      if (!cv[a]) continue;
+      gr[a] += cv[a] * w * m.x;
+      gp[a] += cv[a] * w * m.y;
+      gq[a] += cv[a] * w * m.z;
+      gw[a] += cv[a] * w * m.w;
+    }
+  }
+#pragma unroll
+  for (int a = 0; a < 3; ++a) F[a] = mu_rho * gr[a] + mu_phi * gp[a] + mu_psi * gq[a] - gw[a];
+}
+
+// collision of one Cahn-Hilliard population (g or h) of a fluid cell with
+// order parameter value X, potential mu and 3 Gamma = gam3, relaxing at om;
+// rest population as hi + lo; streamed in place (AA parity ODD)
+template <int Q, int ODD>
+__device__ __forceinline__ float t3_collide_ch(const T3View<Q> &T, float *a, __half *lo, const Nbr &N, long long c,
+                                               const float m[3], float inv_rho, float mmr, float mu, float gam3,
+                                               float om) {
+  using V = VSet<Q>;
+  float v[Q];
+#pragma unroll
+  for (int i = 0; i < Q; ++i) v[i] = ld3<Q>(T, a, N, c, ODD, i);
+  float gm = 0.0f;
+#pragma unroll
+  for (int i = 1; i < Q; ++i) gm += v[i];
+  const float X = v[0] + gm;
+  float rest = 0.0f;
+#pragma unroll
+  for (int i = 1; i < Q; ++i) {
+    const float cmi = V::cx(i) * m[0] + V::cy(i) * m[1] + V::cz(i) * m[2];
+    const float cu = cmi * inv_rho;
+    const float eq = V::w(i) * gam3 * mu + X * (V::a(i) * cu + V::w(i) * ((4.5f * cmi * cu - 1.5f * mmr) * inv_rho));
+    rest += eq;
+    const float s = v[i] + om * (eq - v[i]);
+    if (!ODD) T.st(a, opp(i), c, s);
+    else T.st(a, i, N.template at<V>(i), s);
+  }
+  const float t = om * (gm - rest) + __half2float(lo[c]) * 0x1p-24f;
+  const float r0 = v[0] + t;
+  const float tb = r0 - v[0];
+  lo[c] = __float2half_rn(((v[0] - (r0 - tb)) + (t - tb)) * 0x1p24f);
+  T.st(a, 0, c, r0);
+  return X;
+}
+
+template <int Q, int ODD>
+__global__ __launch_bounds__(BX *BY) void k3_collide(T3View<Q> T) {
+  using V = VSet<Q>;
+  int x, y, z;
+  long long c;
+  if (!cell_of_thread(T.G, x, y, z, c)) return;
+  const uint32_t bits = T.nbm[c];
+  if (bits & NB_SELF_SOLID) return;
+  const Nbr N(T.G, x, y, z);
+  float F[3], mu_phi, mu_psi;
+  t3_force<Q>(T, N, c, F, mu_phi, mu_psi);
+  // f: BGK with the Guo term, first moments exact as in collide_cell
+  float df[Q];
+#pragma unroll
+  for (int i = 0; i < Q; ++i) df[i] = ld3<Q>(T, T.f, N, c, ODD, i);
+  float drho = 0.0f, j[3] = {0, 0, 0};
+#pragma unroll
+  for (int i = 0; i < Q; ++i) {
+    drho += df[i];
+    j[0] += V::cx(i) * df[i];
+    j[1] += V::cy(i) * df[i];
+    j[2] += V::cz(i) * df[i];
+  }
+  const float rho = 1.0f + drho, inv_rho = 1.0f / rho;
+  const float m[3] = {j[0] + 0.5f * F[0], j[1] + 0.5f * F[1], j[2] + 0.5f * F[2]};
+  const float mmr = (m[0] * m[0] + m[1] * m[1] + m[2] * m[2]) * inv_rho;
+  const float uF = (m[0] * F[0] + m[1] * F[1] + m[2] * F[2]) * inv_rho;
+#pragma unroll
+  for (int i = 0; i < Q; ++i) {
+    const float cF = V::cx(i) * F[0] + V::cy(i) * F[1] + V::cz(i) * F[2];
+    const float cm = V::cx(i) * m[0] + V::cy(i) * m[1] + V::cz(i) * m[2];
+    const float cu = cm * inv_rho;
+    const float wi = V::w(i), ai = V::a(i);
+    const float dfeq = wi * drho + ai * cm + wi * (4.5f * cm * cu - 1.5f * mmr);
+    const float src = T.ph.guo * (ai * cF - 3.0f * wi * uF + 3.0f * ai * cu * cF);
+    const float fs = df[i] + T.ph.om_f * (dfeq - df[i]) + src;
+    if (!ODD || i == 0) T.st(T.f, i == 0 ? 0 : opp(i), c, fs);
+    else T.st(T.f, i, N.template at<V>(i), fs);
+  }
+  const float phi = t3_collide_ch<Q, ODD>(T, T.g, T.g0l, N, c, m, inv_rho, mmr, mu_phi, T.ph.gam3, T.ph.om_g);
+  const float psi = t3_collide_ch<Q, ODD>(T, T.h, T.h0l, N, c, m, inv_rho, mmr, mu_psi, T.ph.gam3h, T.ph.om_h);
+  if (!bits) return;
+  // moving halfway bounce-back, as bounce_back() for each population
+#pragma unroll
+  for (int i = 1; i < Q; ++i) {
+    if (!((bits >> i) & 1u)) continue;
+    const long long n = N.template at<V>(i);
+    const int sp = ODD ? i : opp(i);
+    const long long sc = ODD ? n : c;
+    const int xs = wrap(x + V::cx(i), T.G.ex), ys = wrap(y + V::cy(i), T.G.ey);
+    const int zs = V::D == 3 ? wrap(z + V::cz(i), T.G.ez) : z;
+    float uw[3];
+    body_velocity<V>(T.G, T.ph, T.mask[n], x, y, z, xs, ys, zs, i, uw);
+    const float k = 6.0f * V::w(i) * (V::cx(i) * uw[0] + V::cy(i) * uw[1] + V::cz(i) * uw[2]);
+    const int bp = ODD ? opp(i) : i;
+    const long long bc = ODD ? c : n;
+    T.st(T.f, bp, bc, T.ld(T.f, sp, sc) - k * rho);
+    T.st(T.g, bp, bc, T.ld(T.g, sp, sc) - k * phi);
+    T.st(T.h, bp, bc, T.ld(T.h, sp, sc) - k * psi);
+  }
+}
+
+// equilibrium initialisation from M4 (filled) and u0 in AUX
+template <int Q>
+__global__ __launch_bounds__(BX *BY) void k3_init(T3View<Q> T) {
+  using V = VSet<Q>;
+  int x, y, z;
+  long long c;
+  if (!cell_of_thread(T.G, x, y, z, c)) return;
+  if (T.nbm[c] & NB_SELF_SOLID) return;
+  const Nbr N(T.G, x, y, z);
+  t3_potential_at<Q>(T, N, c);
+  const float4 m0 = T.M4[c];
+  const float2 mu = T.CM[c];
+  const float4 u4 = T.AUX[c];
+  const float u[3] = {u4.x, u4.y, u4.z};
+  const float uu = u[0] * u[0] + u[1] * u[1] + u[2] * u[2];
+  const float rho = 1.0f + m0.x;
+  float rg = 0.0f, rh = 0.0f;
+#pragma unroll
+  for (int i = 0; i < Q; ++i) {
+    const float cu = V::cx(i) * u[0] + V::cy(i) * u[1] + V::cz(i) * u[2];
+    const float poly = 3.0f * cu + 4.5f * cu * cu - 1.5f * uu;
+    T.st(T.f, i, c, V::w(i) * (m0.x + rho * poly));
+    if (i > 0) {
+      const float ge = V::w(i) * (T.ph.gam3 * mu.x + m0.y * poly);
+      const float he = V::w(i) * (T.ph.gam3h * mu.y + m0.z * poly);
+      rg += ge;
+      rh += he;
+      T.st(T.g, i, c, ge);
+      T.st(T.h, i, c, he);
+    }
+  }
+  T.st(T.g, 0, c, m0.y - rg);
+  T.st(T.h, 0, c, m0.z - rh);
+}
+
+// observables (u with F/2, bulk pressure) into AUX; C4, CM current
+template <int Q>
+__global__ __launch_bounds__(BX *BY) void k3_observe(T3View<Q> T, int odd) {
+  using V = VSet<Q>;
+  int x, y, z;
+  long long c;
+  if (!cell_of_thread(T.G, x, y, z, c)) return;
+  if (T.nbm[c] & NB_SELF_SOLID) {
+    T.AUX[c] = make_float4(0, 0, 0, 0);
+    return;
+  }
+  const Nbr N(T.G, x, y, z);
+  float F[3], mp, mq;
+  t3_force<Q>(T, N, c, F, mp, mq);
+  float j[3] = {0, 0, 0};
+#pragma unroll
+  for (int i = 0; i < Q; ++i) {
+    const float v = ld3<Q>(T, T.f, N, c, odd, i);
+    j[0] += V::cx(i) * v;
+    j[1] += V::cy(i) * v;
+    j[2] += V::cz(i) * v;
+  }
+  const float4 cc = T.C4[c];
+  const float rho = 1.0f + cc.x, inv = 1.0f / rho;
+  const float pres = rho / 3.0f + cc.w - psi_bulk3(T.ph, rho, cc.y, cc.z);
+  T.AUX[c] = make_float4((j[0] + 0.5f * F[0]) * inv, (j[1] + 0.5f * F[1]) * inv, (j[2] + 0.5f * F[2]) * inv, pres);
+}
+
+// populations of the storage cells [c0, c0 + n) as [3q + 2][n] floats: f_i +
+// w_i, g_i, h_i, then the low parts of g_0 and h_0; solid cells read 0
+template <int Q>
+__global__ __launch_bounds__(256) void k3_read_pops(T3View<Q> T, int odd, float *__restrict__ out, long long c0,
+                                                    int n) {
+  using V = VSet<Q>;
+  const int t = blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= n) return;
+  const long long c = c0 + t;
+  if (T.nbm[c] & NB_SELF_SOLID) {
+    for (int i = 0; i < 3 * Q + 2; ++i) out[(long long)i * n + t] = 0.0f;
+    return;
+  }
+  const int x = (int)(c % T.G.px);
+  const long long r = c / T.G.px;
+  const Nbr N(T.G, x, (int)(r % T.G.ey), (int)(r / T.G.ey));
+#pragma unroll
+  for (int i = 0; i < Q; ++i) {
+    out[(long long)i * n + t] = ld3<Q>(T, T.f, N, c, odd, i) + V::w(i);
+    out[(long long)(Q + i) * n + t] = ld3<Q>(T, T.g, N, c, odd, i);
+    out[(long long)(2 * Q + i) * n + t] = ld3<Q>(T, T.h, N, c, odd, i);
+  }
+  out[(long long)3 * Q * n + t] = __half2float(T.g0l[c]) * 0x1p-24f;
+  out[(long long)(3 * Q + 1) * n + t] = __half2float(T.h0l[c]) * 0x1p-24f;
+}
+
+// ---------------------------------------------------------------------------
 // host launchers
 // ---------------------------------------------------------------------------
 static dim3 cell_grid(const Geom &G) { return dim3((G.ex + BX - 1) / BX, (G.ey + BY - 1) / BY, G.ez); }
@@ -1301,6 +1616,69 @@ void launch_reduce(const LaunchArgs &a, double *part) {
 void launch_reduce_total(const LaunchArgs &a, double *part, double *total) {
   launch_reduce(a, part);
   k_reduce_final<<<1, 64, 0, a.stream>>>(part, reduce_blocks(), total);
+}
+
+// ---------------------------------------------------------------------------
+// ternary host launchers
+// ---------------------------------------------------------------------------
+template <int Q>
+static T3View<Q> t3_view(const LaunchArgs &a) {
+  T3View<Q> T;
+  T.f = (float *)a.f; T.g = (float *)a.g; T.h = (float *)a.h;
+  T.g0l = (__half *)a.g0; T.h0l = a.h0l;
+  T.nbm = a.nbm; T.mask = a.mask;
+  T.M4 = (float4 *)a.M; T.C4 = a.C; T.CM = a.CM; T.AUX = a.AUX;
+  T.G = a.G; T.ph = a.ph; T.fill = a.fill_list; T.n_fill = a.n_fill;
+  return T;
+}
+
+template <int Q>
+static void t3_couple(const LaunchArgs &a, int odd) {
+  const T3View<Q> T = t3_view<Q>(a);
+  k3_moments<Q><<<cell_grid(a.G), cell_block(), 0, a.stream>>>(T, odd);
+  if (a.n_fill) k3_fill<Q, 0><<<fill_blocks(a.n_fill), 256, 0, a.stream>>>(T);
+  k3_potential<Q><<<cell_grid(a.G), cell_block(), 0, a.stream>>>(T);
+  if (a.n_fill) k3_fill<Q, 1><<<fill_blocks(a.n_fill), 256, 0, a.stream>>>(T);
+}
+
+template <int Q>
+static void t3_step(const LaunchArgs &a, int odd) {
+  t3_couple<Q>(a, odd);
+  const T3View<Q> T = t3_view<Q>(a);
+  if (odd) k3_collide<Q, 1><<<cell_grid(a.G), cell_block(), 0, a.stream>>>(T);
+  else k3_collide<Q, 0><<<cell_grid(a.G), cell_block(), 0, a.stream>>>(T);
+}
+
+void launch_step3(const LaunchArgs &a, int odd) {
+  if (a.q == 9) t3_step<9>(a, odd);
+  else t3_step<19>(a, odd);
+}
+
+void launch_observe3(const LaunchArgs &a, int odd) {
+  if (a.q == 9) {
+    t3_couple<9>(a, odd);
+    k3_observe<9><<<cell_grid(a.G), cell_block(), 0, a.stream>>>(t3_view<9>(a), odd);
+  } else {
+    t3_couple<19>(a, odd);
+    k3_observe<19><<<cell_grid(a.G), cell_block(), 0, a.stream>>>(t3_view<19>(a), odd);
+  }
+}
+
+template <int Q>
+static void t3_init(const LaunchArgs &a) {
+  const T3View<Q> T = t3_view<Q>(a);
+  if (a.n_fill) k3_fill<Q, 0><<<fill_blocks(a.n_fill), 256, 0, a.stream>>>(T);
+  k3_init<Q><<<cell_grid(a.G), cell_block(), 0, a.stream>>>(T);
+}
+
+void launch_init3(const LaunchArgs &a) {
+  if (a.q == 9) t3_init<9>(a);
+  else t3_init<19>(a);
+}
+
+void launch_read_pops3(const LaunchArgs &a, int odd, float *out, long long c0, int n) {
+  if (a.q == 9) k3_read_pops<9><<<(n + 255) / 256, 256, 0, a.stream>>>(t3_view<9>(a), odd, out, c0, n);
+  else k3_read_pops<19><<<(n + 255) / 256, 256, 0, a.stream>>>(t3_view<19>(a), odd, out, c0, n);
 }
 
 }  // namespace frelbm

@@ -125,7 +125,35 @@ struct Phys {
   float rc[4][3];
   float rom[4];
   int rax[4];
+  // ternary lattices: kappa3, 1/tau_h, Gamma_psi / cs^2
+  float k3, om_h, gam3h;
 };
+
+// The three potentials of the ternary free energy (the Remark after the
+// mobility relation in Sec. 2.2 adds a coupled Cahn-Hilliard equation per
+// further component; the free energy is that of the cited ternary model):
+// concentrations C1 = (rho + phi - psi)/2, C2 = (rho - phi - psi)/2, C3 = psi,
+// mu_m = kappa_m C_m (1 - C_m)(1 - 2 C_m) - alpha^2 kappa_m lap C_m, and
+// mu_rho = (mu_1 + mu_2)/2, mu_phi = (mu_1 - mu_2)/2, mu_psi = mu_3 - mu_rho.
+__device__ __forceinline__ void chem_pot3(const Phys &P, float drho, float phi, float psi, float lr, float lp,
+                                          float lq, float &mu_rho, float &mu_phi, float &mu_psi) {
+  const float a2 = 4.0f * P.a2q;  // alpha^2
+  const float c1 = 0.5f * (1.0f + drho + phi - psi), c2 = 0.5f * (1.0f + drho - phi - psi), c3 = psi;
+  const float l1 = 0.5f * (lr + lp - lq), l2 = 0.5f * (lr - lp - lq), l3 = lq;
+  const float m1 = P.k1 * (c1 * (1.0f - c1) * (1.0f - 2.0f * c1) - a2 * l1);
+  const float m2 = P.k2 * (c2 * (1.0f - c2) * (1.0f - 2.0f * c2) - a2 * l2);
+  const float m3 = P.k3 * (c3 * (1.0f - c3) * (1.0f - 2.0f * c3) - a2 * l3);
+  mu_rho = 0.5f * (m1 + m2);
+  mu_phi = 0.5f * (m1 - m2);
+  mu_psi = m3 - mu_rho;
+}
+
+// Bulk free-energy density of the ternary functional.
+__device__ __forceinline__ float psi_bulk3(const Phys &P, float rho, float phi, float psi) {
+  const float c1 = 0.5f * (rho + phi - psi), c2 = 0.5f * (rho - phi - psi), c3 = psi;
+  return 0.5f * (P.k1 * c1 * c1 * (1.0f - c1) * (1.0f - c1) + P.k2 * c2 * c2 * (1.0f - c2) * (1.0f - c2) +
+                 P.k3 * c3 * c3 * (1.0f - c3) * (1.0f - c3));
+}
 
 __device__ __forceinline__ int wrap(int v, int n) { return v < 0 ? v + n : (v >= n ? v - n : v); }
 

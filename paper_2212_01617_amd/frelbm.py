@@ -20,8 +20,10 @@ FRE_D2Q9, FRE_D3Q19 = 0, 1
 FRE_FP32, FRE_FP16 = 0, 1
 FRE_PERIODIC, FRE_WALL = 0, 1
 FRE_F_RHO, FRE_F_PHI, FRE_F_U, FRE_F_MU_RHO, FRE_F_MU_PHI, FRE_F_P = 1, 2, 4, 8, 16, 32
+FRE_F_PSI, FRE_F_MU_PSI = 64, 128
 FIELDS = (("rho", FRE_F_RHO), ("phi", FRE_F_PHI), ("u", FRE_F_U),
-          ("mu_rho", FRE_F_MU_RHO), ("mu_phi", FRE_F_MU_PHI), ("P", FRE_F_P))
+          ("mu_rho", FRE_F_MU_RHO), ("mu_phi", FRE_F_MU_PHI), ("P", FRE_F_P),
+          ("psi", FRE_F_PSI), ("mu_psi", FRE_F_MU_PSI))
 
 
 class FreError(RuntimeError):
@@ -44,8 +46,9 @@ class fre_params(C.Structure):
         ("rollers", fre_roller * 4),
         ("A", C.c_double), ("kappa", C.c_double),
         ("kappa1", C.c_double), ("kappa2", C.c_double), ("alpha", C.c_double),
-        ("use_paper_form", C.c_int32), ("reserved1", C.c_int32),
+        ("use_paper_form", C.c_int32), ("ternary", C.c_int32),
         ("tau_f", C.c_double), ("tau_g", C.c_double), ("M", C.c_double),
+        ("kappa3", C.c_double), ("M3", C.c_double), ("tau_h", C.c_double),
     ]
 
 
@@ -57,11 +60,15 @@ _SIGS = [
     ("fre_lattice_init", C.c_int32, [C.POINTER(fre_params), C.c_void_p, C.c_size_t, C.c_void_p,
                                      C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p,
                                      C.POINTER(C.c_void_p)]),
+    ("fre_lattice_init3", C.c_int32, [C.POINTER(fre_params), C.c_void_p, C.c_size_t, C.c_void_p,
+                                      C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p,
+                                      C.POINTER(C.c_void_p)]),
     ("fre_set_params", C.c_int32, [C.c_void_p, C.POINTER(fre_params)]),
     ("fre_consistent_init", C.c_int32, [C.c_void_p, C.c_void_p, C.c_void_p, C.c_int64]),
     ("fre_step", C.c_int32, [C.c_void_p, C.c_int64]),
     ("fre_read_moments", C.c_int32, [C.c_void_p, C.c_uint32, C.c_void_p, C.c_size_t]),
     ("fre_read_populations", C.c_int32, [C.c_void_p, C.c_void_p, C.c_void_p, C.c_size_t]),
+    ("fre_read_populations3", C.c_int32, [C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p, C.c_size_t]),
     ("fre_reduce", C.c_int32, [C.c_void_p, C.c_void_p]),
     ("fre_reduce_noalloc", C.c_int32, [C.c_void_p, C.c_void_p]),
     ("fre_info", C.c_int32, [C.c_void_p, C.POINTER(C.c_int64), C.POINTER(C.c_int32)]),
@@ -117,9 +124,10 @@ def _ptr(a: np.ndarray):
 
 def make_params(kind, shape, *, storage=FRE_FP32, bc=(0, 0, 0), wall_u=None, rollers=(),
                 A=None, kappa=None, kappa1=None, kappa2=None, alpha=None,
-                tau_f=1.0, tau_g=1.0, M=0.1) -> fre_params:
+                tau_f=1.0, tau_g=1.0, M=0.1, ternary=None) -> fre_params:
     """shape = (nx, ny, nz); rollers = [(center(3), omega, axis, radius)];
-    give either (A, kappa) or (kappa1, kappa2, alpha)."""
+    give either (A, kappa) or (kappa1, kappa2, alpha).  A ternary lattice
+    takes ternary=(kappa3, M3, tau_h)."""
     p = fre_params()
     p.kind = kind
     p.nx, p.ny, p.nz = shape
@@ -148,6 +156,9 @@ def make_params(kind, shape, *, storage=FRE_FP32, bc=(0, 0, 0), wall_u=None, rol
         p.use_paper_form = 0
         p.A, p.kappa = A, kappa
     p.tau_f, p.tau_g, p.M = tau_f, tau_g, M
+    if ternary is not None:
+        p.ternary = 1
+        p.kappa3, p.M3, p.tau_h = ternary
     return p
 
 
@@ -162,9 +173,15 @@ class Lattice:
     Host fields are numpy arrays shaped (nz, ny, nx)."""
 
     def __init__(self, params: fre_params, phi0, rho0=None, u0=None, mask=None,
-                 device="cuda:0", stream=None):
+                 device="cuda:0", stream=None, psi0=None):
+        """psi0 (ternary lattices, params.ternary = 1) is the third order
+        parameter's initial field; the lattice is then made by
+        fre_lattice_init3."""
         import torch  # device memory and streams only
         self.params = params
+        self.ternary = bool(params.ternary)
+        if self.ternary != (psi0 is not None):
+            raise ValueError("psi0 is given exactly for ternary parameters")
         self.shape = (params.nz, params.ny, params.nx)
         self.N = params.nx * params.ny * params.nz
         self.q = 9 if params.kind == FRE_D2Q9 else 19
@@ -179,11 +196,15 @@ class Lattice:
         u0 = None if u0 is None else np.ascontiguousarray(np.asarray(u0, np.float64).reshape(-1))
         mask = None if mask is None else np.ascontiguousarray(np.asarray(mask, np.uint8).reshape(-1))
         h = C.c_void_p()
-        _check(lib().fre_lattice_init(C.byref(params), C.c_void_p(self._base), nbytes,
-                                      C.c_void_p(self.stream.cuda_stream), _ptr(phi0),
-                                      None if rho0 is None else _ptr(rho0),
-                                      None if u0 is None else _ptr(u0),
-                                      None if mask is None else _ptr(mask), C.byref(h)))
+        rest = (None if rho0 is None else _ptr(rho0), None if u0 is None else _ptr(u0),
+                None if mask is None else _ptr(mask), C.byref(h))
+        if self.ternary:
+            psi0 = np.ascontiguousarray(np.asarray(psi0, np.float64).reshape(-1))
+            _check(lib().fre_lattice_init3(C.byref(params), C.c_void_p(self._base), nbytes,
+                                           C.c_void_p(self.stream.cuda_stream), _ptr(phi0), _ptr(psi0), *rest))
+        else:
+            _check(lib().fre_lattice_init(C.byref(params), C.c_void_p(self._base), nbytes,
+                                          C.c_void_p(self.stream.cuda_stream), _ptr(phi0), *rest))
         self._h = h
 
     def close(self):
@@ -241,8 +262,13 @@ class Lattice:
         return res
 
     def populations(self):
+        """(f, g), or (f, g, h) on a ternary lattice, each (q, nz, ny, nx)."""
         f = np.empty(self.q * self.N)
         g = np.empty(self.q * self.N)
+        if self.ternary:
+            h = np.empty(self.q * self.N)
+            _check(lib().fre_read_populations3(self._h, _ptr(f), _ptr(g), _ptr(h), self.q * self.N))
+            return tuple(a.reshape((self.q,) + self.shape) for a in (f, g, h))
         _check(lib().fre_read_populations(self._h, _ptr(f), _ptr(g), self.q * self.N))
         return f.reshape((self.q,) + self.shape), g.reshape((self.q,) + self.shape)
 

@@ -178,6 +178,10 @@ class Server:
         self.clock = clock
         self.sleep = sleep
 
+    def _due(self, m: _Member) -> int:
+        """Step count at which member m is next sampled."""
+        return min(m.next_sample, self.step_cap)
+
     def _sample(self, m: _Member, now: float):
         """Sample D (and breakup); return the retirement reason or None."""
         try:
@@ -243,16 +247,18 @@ class Server:
                 if pending:
                     self.sleep(max(0.0, pending[0].arrival - (self.clock() - t0)))
                 continue
-            # step up to the next sample that falls due, at most one chunk
-            n = min(self.chunk, min(m.next_sample - m.t for m in active))
+            # step up to the next sample that falls due (or the step cap, which
+            # a slow request may reach before its first sample), at most one chunk
+            n = min(self.chunk, min(self._due(m) - m.t for m in active))
             n = max(n, 1)
             self.engine.step(n)
             lu += n * sum(m.req.cells for m in active)
             done = []
             for m in active:
                 m.t += n
-                if m.t >= m.next_sample:
-                    m.next_sample += m.sample_every
+                if m.t >= self._due(m):
+                    if m.t >= m.next_sample:
+                        m.next_sample += m.sample_every
                     reason = self._sample(m, self.clock() - t0)
                     if reason:
                         done.append((m, reason))

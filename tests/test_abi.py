@@ -61,6 +61,41 @@ def test_validation_errors(lib, bad, msg):
     assert msg in str(ei.value)
 
 
+@pytest.mark.parametrize("bad,msg", [
+    (dict(ternary=(0.0, 0.05, 1.0)), "kappa3"),
+    (dict(ternary=(0.1, -0.1, 1.0)), "M3"),
+    (dict(ternary=(0.1, 0.05, 0.5)), "tau_h"),
+    (dict(ternary=(0.1, 0.05, 1.0), storage=F.FRE_FP16), "FP32"),
+])
+def test_ternary_validation_errors(lib, bad, msg):
+    with pytest.raises(F.FreError) as ei:
+        F.footprint(_ok_params(**bad))
+    assert ei.value.status == F.FRE_EINVAL
+    assert msg in str(ei.value)
+
+
+def test_ternary_flag_is_0_or_1(lib):
+    p = _ok_params()
+    p.ternary = 2
+    with pytest.raises(F.FreError) as ei:
+        F.footprint(p)
+    assert ei.value.status == F.FRE_EINVAL
+
+
+def test_ternary_footprint_holds_the_third_population(lib):
+    q, n = 19, 16 * 8 * 8
+    assert F.footprint(_ok_params(ternary=(0.1, 0.05, 1.0))) >= F.footprint(_ok_params()) + q * n * 4 - 64 * n
+    p = _ok_params(ternary=(0.1, 0.05, 1.0))
+    out = C.c_void_p(1)
+    # the binary entry point refuses ternary parameters before touching memory
+    assert lib.fre_lattice_init(C.byref(p), None, 0, None, None, None, None, None, C.byref(out)) == F.FRE_EINVAL
+    assert out.value is None and b"fre_lattice_init3" in lib.fre_last_error()
+    b = _ok_params()
+    assert lib.fre_lattice_init3(C.byref(b), None, 0, None, None, None, None, None, None,
+                                 C.byref(out)) == F.FRE_EINVAL
+    assert out.value is None
+
+
 def test_d2q9_shape_rules(lib):
     with pytest.raises(F.FreError):
         F.footprint(F.make_params(F.FRE_D2Q9, (8, 8, 2), A=0.04, kappa=0.09))

@@ -90,9 +90,12 @@ def test_checkpoint_holds_the_low_part():
     assert np.any(g0 != g0.astype(np.float32).astype(np.float64))
 
 
-def test_reserved_word_refused():
+def test_ternary_entry_points_refuse_binary_lattices():
     p = F.make_params(0, (16, 8, 1), A=0.04, kappa=0.09)
-    p.reserved1 = 1
+    a = F.Lattice(p, np.zeros((1, 8, 16)))
+    f = np.empty(9 * 128)
     with pytest.raises(F.FreError) as e:
-        F.footprint(p)
+        F._check(F.lib().fre_read_populations3(a.handle, F._ptr(f), F._ptr(f), F._ptr(f), f.size))
     assert e.value.status == F.FRE_EINVAL
+    with pytest.raises(F.FreError):
+        a.read(("psi",))

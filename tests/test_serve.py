@@ -142,6 +142,31 @@ def test_scheduler_admits_in_order_within_budget_and_retires_everyone():
     assert s["aggregate_mlups"] > 0
 
 
+def test_step_cap_is_exact_when_samples_are_sparse():
+    # even requests take 1e-6 strain per step: their first D sample would
+    # fall due after 100,000 steps, far beyond the step cap
+    clock = Clock()
+    rs = _requests(6, seed=4)
+
+    class Slow(FakeEngine):
+        def admit(self, req):
+            got = super().admit(req)
+            if got is not None and req.rid % 2 == 0:
+                self.members[got[0]][2] = 1e-6
+                return got[0], 1e-6
+            return got
+
+    budget = 8 * max(r.cells for r in rs) * 160
+    eng = Slow(clock, budget)
+    rep = serve.Server(eng, budget, max_members=6, chunk=500, strain_cap=25.0, step_cap=3000,
+                       clock=clock, sleep=clock.sleep).run(rs)
+    assert len(rep.outcomes) == 6
+    for o in rep.outcomes:
+        assert o.steps <= 3000
+        if o.rid % 2 == 0:
+            assert o.reason == "cap" and o.steps == 3000
+
+
 def test_engine_refusal_waits_and_retries():
     clock = Clock()
     rs = _requests(12, seed=5)
