@@ -155,6 +155,30 @@ def consistent_init_rate(n: int = 400) -> dict:
             "sample": f"{n} pre-iterations minus 0, best of 2, FP32, 256x128x128"}
 
 
+def ternary_rate(steps: int = 200) -> dict:
+    """Throughput of a ternary lattice (third order parameter psi with its
+    own population h) on the 256x128x128 shear workload: a drop of component
+    1 in a 2-3 mixture, FP32 storage, captured two-step graphs."""
+    import torch
+    from paper_2212_01617_amd import frelbm as F
+    p, phi0, u0, meta = workload(0)
+    sh = phi0.shape
+    c1 = 0.5 * (1.0 + phi0)
+    psi0 = 0.3 * (1.0 - c1)
+    phi = c1 - (1.0 - c1 - psi0)
+    p.ternary = 1
+    p.kappa3, p.M3, p.tau_h = p.kappa1 if p.use_paper_form else 4.0 * p.A, p.M, p.tau_g
+    L = F.Lattice(p, phi, None, u0, psi0=psi0, stream=torch.cuda.Stream())
+    ms, _ = time_steps(L, steps, 10, 3)
+    L.close()
+    cells = sh[0] * sh[1] * sh[2]
+    mlups = cells / (ms * 1e-3) / 1e6
+    b = 2 * 3 * 19 * 4
+    return {"value": round(mlups, 1), "unit": "MLUPS", "ms_per_step": round(ms, 5), "bytes_per_lu": b,
+            "step_frac": round(mlups * 1e6 * b / 1e9 / PEAK_HBM_GBS, 4),
+            "workload": "D3Q19 ternary shear droplet 256x128x128, walls in z, FP32 storage"}
+
+
 def four_roller_lattice(storage: int):
     """Parameters, phi0 and mask of the four-roller workload (see four_roller)."""
     from paper_2212_01617_amd import frelbm as F
@@ -330,6 +354,7 @@ def main():
     ap.add_argument("--shape", default="", help="with --kernels-only: rows,xcd for k_moments, "
                     "k_potential, k_collide, e.g. 4,1,4,1,4,1 (default shapes if empty)")
     ap.add_argument("--copy-probe", action="store_true")
+    ap.add_argument("--ternary-only", type=int, default=0, help="only the ternary leg, this many timed steps")
     ap.add_argument("--serve-steady-only", action="store_true", help=argparse.SUPPRESS)
     ap.add_argument("--no-extra", action="store_true", help="skip the four-roller and shard legs")
     ap.add_argument("--cpu-table", action="store_true",
@@ -355,6 +380,9 @@ def main():
     stream = torch.cuda.Stream()
     if args.copy_probe:
         copy_probe()
+        return
+    if args.ternary_only:
+        print(json.dumps({"mode": "ternary", **ternary_rate(args.ternary_only)}), flush=True)
         return
     if args.serve_steady_only:
         print(json.dumps({"mode": "serving-steady", **serving_steady()}), flush=True)
@@ -436,6 +464,7 @@ def main():
     if not args.no_large:
         out["large_lattice"] = large_lattice()
     out["consistent_init"] = consistent_init_rate()
+    out["ternary"] = ternary_rate()
     if not args.no_extra:
         out["four_roller"] = four_roller()
         out["shard"] = shard()
