@@ -56,7 +56,7 @@ struct Plan {
   int off[3];
   int px;          // row pitch: ext[0] rounded up to a multiple of 64
   long long ncell;  // px * ext[1] * ext[2]
-  size_t o_f, o_g, o_g0, o_h, o_h0, o_mask, o_nbm, o_M, o_C, o_CM, o_P0, o_PU, o_PD, o_XE, o_AUX, o_fill, o_part, total;
+  size_t o_f, o_g, o_g0, o_h, o_h0, o_mask, o_nbm, o_segf, o_M, o_C, o_CM, o_P0, o_PU, o_PD, o_XE, o_AUX, o_fill, o_part, total;
 };
 
 fre_status validate(const fre_params *p) {
@@ -142,6 +142,7 @@ Plan make_plan(const fre_params *p) {
   }
   P.o_mask = take((size_t)P.ncell);
   P.o_nbm = take((size_t)P.ncell * 4);
+  P.o_segf = take((size_t)P.ncell / 64);
   P.o_M = take((size_t)P.ncell * (t3 ? 16 : 8));
   P.o_C = take((size_t)P.ncell * 16);
   P.o_CM = t3 ? take((size_t)P.ncell * 8) : 0;
@@ -254,7 +255,7 @@ long long ext_index(const Plan &P, int x, int y, int z) {
 }
 
 fre_status build_mask(fre_lattice *L, const uint8_t *user_mask, std::vector<uint8_t> &mask,
-                      std::vector<uint32_t> &nbm) {
+                      std::vector<uint32_t> &nbm, std::vector<uint8_t> &segf) {
   const Plan &P = L->plan;
   const fre_params &p = L->p;
   mask.assign((size_t)P.ncell, CELL_GHOST);
@@ -306,6 +307,13 @@ fre_status build_mask(fre_lattice *L, const uint8_t *user_mask, std::vector<uint
         nbm[s] = NB_SELF_SOLID | fluid;
         if (fluid) L->fill_host.push_back((int)s);
       }
+  // 64-cell row segments whose cells are all fluid with fluid neighbours only
+  segf.assign((size_t)(P.ncell / 64), 0);
+  for (size_t k = 0; k < segf.size(); ++k) {
+    bool all = true;
+    for (size_t j = 0; j < 64 && all; ++j) all = nbm[64 * k + j] == 0u;
+    segf[k] = all ? 1 : 0;
+  }
   return FRE_OK;
 }
 
@@ -324,6 +332,7 @@ void bind_args(fre_lattice *L) {
   a.g0 = (float *)(L->base + P.o_g0);  // FP16: the g_0 plane; FP32: the half plane of g_0's low part
   a.mask = L->base + P.o_mask;
   a.nbm = (uint32_t *)(L->base + P.o_nbm);
+  a.segf = L->base + P.o_segf;
   a.M = (float2 *)(L->base + P.o_M);
   a.C = (float4 *)(L->base + P.o_C);
   a.P0 = P.o_P0 ? (float2 *)(L->base + P.o_P0) : nullptr;
@@ -406,7 +415,8 @@ fre_status lattice_init(const fre_params *p, void *device_buf, size_t bytes, voi
   if (hipGetDevice(&L->dev) != hipSuccess) { delete L; return fail(FRE_EDEVICE, "hipGetDevice failed"); }
   std::vector<uint8_t> mask;
   std::vector<uint32_t> nbm;
-  s = build_mask(L, solid_mask, mask, nbm);
+  std::vector<uint8_t> segf;
+  s = build_mask(L, solid_mask, mask, nbm, segf);
   if (s != FRE_OK) { delete L; return s; }
   bind_args(L);
   for (int k = 0; k < N_SHAPES; ++k) L->a.shape[k] = Shape{4, 1};
@@ -442,6 +452,7 @@ fre_status lattice_init(const fre_params *p, void *device_buf, size_t bytes, voi
   if (!L->fill_host.empty())
     INIT_TRY(hipMemcpyAsync(L->a.fill_list, L->fill_host.data(), L->fill_host.size() * 4, hipMemcpyHostToDevice, st));
   INIT_TRY(hipMemcpyAsync(L->a.nbm, nbm.data(), nbm.size() * 4, hipMemcpyHostToDevice, st));
+  INIT_TRY(hipMemcpyAsync(L->a.segf, segf.data(), segf.size(), hipMemcpyHostToDevice, st));
   INIT_TRY(hipMemsetAsync(L->a.C, 0, (size_t)P.ncell * 16, st));
   if (t3) {
     INIT_TRY(hipMemsetAsync(L->a.CM, 0, (size_t)P.ncell * 8, st));

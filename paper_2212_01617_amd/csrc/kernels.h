@@ -36,6 +36,7 @@ struct LaunchArgs {
   float *g0;    // FP16 storage: g_0 plane; FP32 storage: the half plane of g_0's low part
   uint8_t *mask;
   uint32_t *nbm;  // per cell: non-fluid neighbour bits, NB_SELF_SOLID
+  uint8_t *segf;  // per 64-cell row segment: 1 when every cell is fluid with fluid neighbours only
   float2 *M;    // (rho - 1, phi)
   float4 *C;    // (rho - 1, phi, Pi = rho mu_rho + phi mu_phi, mu_phi)
   float2 *P0, *PU, *PD;  // FP32: first-pass moment sums by source plane (same, below, above)
@@ -92,6 +93,7 @@ struct TileMap {
 template <int Q, int S> struct LatView {
   Pops<Q, S> P;
   const uint32_t *nbm;
+  const uint8_t *segf;  // all-fluid segment flags, or null (then nbm is always read)
   const uint8_t *mask;
   float2 *M;
   float4 *C;

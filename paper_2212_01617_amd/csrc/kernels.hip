@@ -230,6 +230,19 @@ template <class V> struct DirBits {
   __device__ static uint32_t solid_sources(uint32_t bits) { return ((bits >> 1) & ODD) | ((bits << 1) & EVEN); }
 };
 
+// Neighbour word of cell c.  A 64-cell row segment flagged all-fluid (every
+// cell fluid, every neighbour fluid) gives 0 without reading nbm: each wave
+// of the single-lattice cell kernels covers exactly one segment, so the flag
+// is one scalar load per wave in place of 256 bytes of neighbour words.
+template <int Q, int S>
+__device__ __forceinline__ uint32_t nb_word(const LatView<Q, S> &L, long long c) {
+  if (L.segf) {
+    const uint32_t sg = __builtin_amdgcn_readfirstlane((uint32_t)(c >> 6));
+    if (L.segf[sg]) return 0u;
+  }
+  return L.nbm[c];
+}
+
 // Second pass for fluid cell c: adds the unavailable sources of each group,
 // in ascending direction order, to the first-pass sums grp[cz + 1].  All
 // needed loads are issued before the sums.  With XE given (FP32), fluid
@@ -284,7 +297,7 @@ template <int Q, int S, int ODD>
 __device__ __forceinline__ void stage_moments(const LatView<Q, S> &L, int x, int y, int z) {
   using V = VSet<Q>;
   const long long c = (long long)x + (long long)L.G.px * ((long long)y + (long long)L.G.ey * z);
-  const uint32_t bits = L.nbm[c];
+  const uint32_t bits = nb_word<Q, S>(L, c);
   if (bits & NB_SELF_SOLID) return;
   const Nbr N(L.G, x, y, z);
   float df[Q], g[Q];
@@ -323,7 +336,7 @@ __device__ __forceinline__ void stage_moments(const LatView<Q, S> &L, int x, int
 template <int Q, int S, int PAR>
 __device__ __forceinline__ void stage_combine(const LatView<Q, S> &L, int x, int y, int z) {
   const long long c = (long long)x + (long long)L.G.px * ((long long)y + (long long)L.G.ey * z);
-  const uint32_t bits = L.nbm[c];
+  const uint32_t bits = nb_word<Q, S>(L, c);
   if (bits & NB_SELF_SOLID) return;
   const Nbr N(L.G, x, y, z);
   float2 grp[3];
@@ -639,7 +652,7 @@ __device__ __forceinline__ void stage_collide(const LatView<Q, S> &L, int x, int
   const long long c = (long long)x + (long long)L.G.px * ((long long)y + (long long)L.G.ey * z);
   if (!ByProduct<S>::on) {
     if (!active) return;
-    const uint32_t bits = L.nbm[c];
+    const uint32_t bits = nb_word<Q, S>(L, c);
     if (bits & NB_SELF_SOLID) return;
     const Nbr N(L.G, x, y, z);
     float rho, phi;
@@ -654,7 +667,7 @@ __device__ __forceinline__ void stage_collide(const LatView<Q, S> &L, int x, int
   bool fluid = false;
   float2 rest = make_float2(0.0f, 0.0f);
   if (active) {
-    const uint32_t bits = L.nbm[c];
+    const uint32_t bits = nb_word<Q, S>(L, c);
     fluid = !(bits & NB_SELF_SOLID);
     if (fluid) {
       const Nbr N(L.G, x, y, z);
@@ -735,7 +748,7 @@ template <int Q, int S, int ODD>
 __device__ __forceinline__ void stage_pre_collide(const LatView<Q, S> &L, int x, int y, int z) {
   using V = VSet<Q>;
   const long long c = (long long)x + (long long)L.G.px * ((long long)y + (long long)L.G.ey * z);
-  const uint32_t bits = L.nbm[c];
+  const uint32_t bits = nb_word<Q, S>(L, c);
   if (bits & NB_SELF_SOLID) return;
   const Nbr N(L.G, x, y, z);
   const float4 cc = L.C[c];
@@ -850,7 +863,7 @@ __global__ __launch_bounds__(BX *MAX_ROWS) void k_potential_zm(LatView<Q, S> L, 
     __syncthreads();
     if (tx < w && ty < h) {
       const long long c = (long long)(xlo + tx) + (long long)G.px * ((long long)(ylo + ty) + (long long)G.ey * z);
-      if (!(L.nbm[c] & NB_SELF_SOLID)) {
+      if (!(nb_word<Q, S>(L, c) & NB_SELF_SOLID)) {
         const float2 m0 = ring[sc][ty + 1][tx + 1];
         float lr, lp;
         laplacians<Q>([&](int i) {
@@ -876,6 +889,7 @@ __device__ __forceinline__ LatView<Q, S> view_of(char *base, const Inst &I) {
   LatView<Q, S> L;
   L.P = pops_of<Q, S>(base + I.f, base + I.g, (float *)(base + I.g0));
   L.nbm = (const uint32_t *)(base + I.nbm); L.mask = (const uint8_t *)(base + I.mask);
+  L.segf = nullptr;  // a batch work item need not cover one segment per wave
   L.M = (float2 *)(base + I.M); L.C = (float4 *)(base + I.C);
   L.P0 = (float2 *)(base + I.P0); L.PU = (float2 *)(base + I.PU); L.PD = (float2 *)(base + I.PD);
   L.XE = (float2 *)(base + I.XE);
@@ -1124,15 +1138,18 @@ template <int Q> struct T3View {
   Phys ph;
   const int *fill;
   int n_fill;
-  __device__ float ld(const float *a, int i, long long c) const { return ld_at<float, false>(a, blk_offset<4>(Q, i, c)); }
+  // NT: non-temporal load, for passes that read each population once and
+  // nothing else of the cell again
+  template <bool NT = false>
+  __device__ float ld(const float *a, int i, long long c) const { return ld_at<float, NT>(a, blk_offset<4>(Q, i, c)); }
   __device__ void st(float *a, int i, long long c, float v) const { st_at(a, blk_offset<4>(Q, i, c), v); }
 };
 
 // population i of fluid cell c at parity `odd` (AA pattern, as load_pops)
-template <int Q>
+template <int Q, bool NT = false>
 __device__ __forceinline__ float ld3(const T3View<Q> &T, const float *a, const Nbr &N, long long c, int odd, int i) {
   using V = VSet<Q>;
-  return (!odd || i == 0) ? T.ld(a, i, c) : T.ld(a, opp(i), N.template back<V>(i));
+  return (!odd || i == 0) ? T.template ld<NT>(a, i, c) : T.template ld<NT>(a, opp(i), N.template back<V>(i));
 }
 
 template <int Q>
@@ -1145,9 +1162,9 @@ __global__ __launch_bounds__(BX *BY) void k3_moments(T3View<Q> T, int odd) {
   float dr = 0.0f, ph = 0.0f, ps = 0.0f;
 #pragma unroll
   for (int i = 0; i < Q; ++i) {
-    dr += ld3<Q>(T, T.f, N, c, odd, i);
-    ph += ld3<Q>(T, T.g, N, c, odd, i);
-    ps += ld3<Q>(T, T.h, N, c, odd, i);
+    dr += ld3<Q, true>(T, T.f, N, c, odd, i);
+    ph += ld3<Q, true>(T, T.g, N, c, odd, i);
+    ps += ld3<Q, true>(T, T.h, N, c, odd, i);
   }
   T.M4[c] = make_float4(dr, ph, ps, 0.0f);
 }
@@ -1429,7 +1446,7 @@ template <int Q, int S>
 static LatView<Q, S> view_of_args(const LaunchArgs &a) {
   LatView<Q, S> L;
   L.P = make_pops<Q, S>(a);
-  L.nbm = a.nbm; L.mask = a.mask; L.M = a.M; L.C = a.C;
+  L.nbm = a.nbm; L.segf = a.segf; L.mask = a.mask; L.M = a.M; L.C = a.C;
   L.P0 = a.P0; L.PU = a.PU; L.PD = a.PD; L.XE = a.XE; L.AUX = a.AUX;
   L.G = a.G; L.ph = a.ph; L.fill = a.fill_list; L.n_fill = a.n_fill;
   return L;
