@@ -12,6 +12,12 @@ Peclet number ``serve.SERVE_PE``.
 
     python -m paper_2212_01617_amd.campaign --n 150 --Re 0.0625 --xi 1.5 \\
         --cas 0.5,0.7,1.0,1.5,2.0 --cap 30
+
+``--history`` instead follows D(strain) of one 3D drop in shear, for the
+interface-width and confinement study of the 3D deformation:
+
+    python -m paper_2212_01617_amd.campaign --history --radius 25 --xi 1 \\
+        --shape 256,128,128 --Re 0.5 --Pe 10 --strain 12
 """
 from __future__ import annotations
 
@@ -137,6 +143,49 @@ def four_roller_run(cas, *, steps: int = 30000, every: int = 500, storage: int =
     return rows
 
 
+def shear_history(*, radius: float = 25.0, xi: float = 2.0, shape=(256, 128, 128), Ca: float = 0.1,
+                  Re: float = 0.5, Pe: float = 10.0, strain: float = 12.0, every: float = 0.5, storage: int = 0,
+                  log=None) -> dict:
+    """A 3D drop in simple shear (the validation of Sec. 3.1): D3Q19, walls
+    normal to z moving at -+u_w, periodic x and y, a centred drop of radius
+    `radius` with interface width `xi`.  Every `every` strain units the
+    deformation D and inclination theta in the xz plane and the volume of
+    {phi > 0} are sampled, up to `strain` strain units."""
+    import math
+
+    import numpy as np
+
+    from . import diagnostics as Dg
+    from . import frelbm as F
+    from . import synth
+    from .params import derive_params
+    nx, ny, nz = shape
+    dp = derive_params(Re=Re, Ca=Ca, radius=radius, xi=xi, H=nz, Pe=Pe)
+    wu = np.zeros((3, 2, 3))
+    wu[2, 0, 0], wu[2, 1, 0] = -dp.wall_u, dp.wall_u
+    sh = (nz, ny, nx)
+    phi0 = synth.droplet_phi(sh, radius, xi, noise=1e-4, seed=0)
+    u0 = synth.shear_velocity(sh, dp.rate, axis_normal=2)
+    L = F.Lattice(F.make_params(F.FRE_D3Q19, shape, storage=storage, bc=(0, 0, 1), wall_u=wu, **dp.phys()),
+                  phi0, None, u0)
+    del phi0, u0
+    per = max(1, int(round(every / dp.rate)))
+    t, hist = 0, []
+    while t * dp.rate < strain - 1e-9:
+        L.step(per)
+        t += per
+        phi = L.read(("phi",))["phi"]
+        d = Dg.deformation(phi, plane="xz", periodic=(True, True, False))
+        hist.append({"strain": round(t * dp.rate, 3), "D": round(d.D, 4),
+                     "theta_deg": round(math.degrees(d.theta), 1), "volume": int((phi > 0).sum())})
+        if log:
+            log(f"[history] R={radius} xi={xi} strain={hist[-1]['strain']} D={hist[-1]['D']} "
+                f"theta={hist[-1]['theta_deg']}")
+    L.close()
+    return {"radius": radius, "xi": xi, "R_over_xi": radius / xi, "shape": list(shape), "Ca": Ca, "Re": Re,
+            "Pe": Pe, "taylor_D": 35.0 / 32.0 * Ca, "rate": dp.rate, "M": dp.M, "history": hist}
+
+
 def main(argv=None):
     ap = argparse.ArgumentParser(description=__doc__.split("\n\n")[0])
     ap.add_argument("--kind", type=int, default=0, help="0 D2Q9, 1 D3Q19")
@@ -151,7 +200,19 @@ def main(argv=None):
                     help="the 256x256x64 four-roller cell instead of the shear sweep (--steps, --every)")
     ap.add_argument("--steps", type=int, default=30000)
     ap.add_argument("--every", type=int, default=500)
+    ap.add_argument("--history", action="store_true",
+                    help="D(strain) of one 3D drop in shear (--radius, --xi, --shape, --Ca, --Re, --Pe, --strain)")
+    ap.add_argument("--radius", type=float, default=25.0)
+    ap.add_argument("--shape", default="256,128,128")
+    ap.add_argument("--Ca", type=float, default=0.1)
+    ap.add_argument("--strain", type=float, default=12.0)
     a = ap.parse_args(argv)
+    if a.history:
+        out = shear_history(radius=a.radius, xi=a.xi, shape=tuple(int(v) for v in a.shape.split(",")), Ca=a.Ca,
+                            Re=a.Re, Pe=a.Pe, strain=a.strain, storage=a.storage,
+                            log=lambda line: print(line, file=sys.stderr, flush=True))
+        print(json.dumps(out), flush=True)
+        return
     if a.rollers:
         rows = four_roller_run([float(c) for c in a.cas.split(",")], steps=a.steps, every=a.every,
                                storage=a.storage, Re=a.Re, xi=a.xi, Pe=a.Pe,

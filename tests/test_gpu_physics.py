@@ -129,3 +129,22 @@ def test_drop_in_shear_3d_reported():
     assert L.reduce()[6] == 0
     # the first response is of Taylor's size; later growth is reported above
     assert 0.5 < hist[0].D / (35 / 32 * Ca) < 2.0
+
+
+def test_drop_in_shear_3d_thin_interface_reaches_taylor():
+    """P8 at the C3 box (256x128x128, R = 25, Ca = 0.1, Re = 0.5, Pe = 10):
+    with R/xi = 25 the deformation after one strain unit is Taylor's
+    35/32 Ca, and the slow later growth of D, which the diffuse interface
+    causes, is much weaker than at R/xi = 12.5 (it falls with the Cahn number
+    and does not depend on the wall distance or the force discretisation)."""
+    from paper_2212_01617_amd import campaign
+    thin = campaign.shear_history(radius=25.0, xi=1.0, strain=8.0, every=1.0)
+    wide = campaign.shear_history(radius=25.0, xi=2.0, strain=8.0, every=1.0)
+    taylor = thin["taylor_D"]
+    D = {k: {h["strain"]: h["D"] for h in r["history"]} for k, r in (("thin", thin), ("wide", wide))}
+    grow = {k: D[k][8.0] - D[k][4.0] for k in D}
+    log(f"[physics] shear 3D R/xi=25: D={[D['thin'][s] for s in sorted(D['thin'])]}; "
+        f"R/xi=12.5: D={[D['wide'][s] for s in sorted(D['wide'])]}; Taylor {taylor:.4f}; "
+        f"growth 4->8 strain: {grow['thin']:.4f} vs {grow['wide']:.4f}")
+    assert 0.8 < D["thin"][1.0] / taylor < 1.2
+    assert 0 < grow["thin"] < 0.5 * grow["wide"]
