@@ -106,6 +106,34 @@ def test_d3q19_walls_box():
     _compare("d3q19_walls_box_100", ref, gpu, mask)
 
 
+@pytest.mark.parametrize("kind,shape,steps", [(0, (1, 1, 1), 9), (0, (3, 2, 1), 7), (1, (2, 2, 2), 5),
+                                              (1, (1, 3, 1), 4), (0, (9, 5, 1), 0)])
+def test_degenerate_lattices_and_zero_steps(kind, shape, steps):
+    """Lattices narrower than the stencil (every neighbour a periodic image
+    of the cell or of another cell), odd and zero step counts."""
+    nx, ny, nz = shape
+    sh = (nz, ny, nx)
+    rng = np.random.default_rng(7)
+    phi0 = rng.uniform(-0.8, 0.8, sh)
+    psi0 = rng.uniform(0.0, 0.3, sh)
+    rho0 = 1.0 + 0.01 * rng.uniform(-1, 1, sh)
+    u0 = 0.01 * rng.uniform(-1, 1, (3,) + sh)
+    if kind == 0:
+        u0[2] = 0
+    ref = O.Lattice3(O.make_params(kind, shape, **KW), *K3, phi0, psi0, rho0, u0)
+    ref.step(steps)
+    gpu = F.Lattice(F.make_params(kind, shape, ternary=K3, **KW), phi0, rho0, u0, psi0=psi0)
+    gpu.step(steps)
+    o, g = ref.observe(), gpu.read(tuple(TOL))
+    err = {k: (max(np.abs(g["u"][a] - o["u" + "xyz"[a]]).max() for a in range(3)) if k == "u"
+               else np.abs(g[k] - o[k]).max()) for k in TOL}
+    pe = [np.abs(a - b).max() for a, b in zip(ref.populations(), gpu.populations())]
+    log(f"[parity] ternary tiny{shape} t={steps}: " + " ".join(f"{k}={v:.2e}" for k, v in err.items()))
+    for k, v in TOL.items():
+        assert err[k] < v, (k, err[k])
+    assert max(pe) < POP_TOL
+
+
 def test_psi_zero_is_the_binary_lattice():
     shape = (48, 40, 1)
     phi0, _, rho0, u0 = _fields(0, shape, 9.0)
