@@ -149,8 +149,9 @@ def shear_history(*, radius: float = 25.0, xi: float = 2.0, shape=(256, 128, 128
     """A 3D drop in simple shear (the validation of Sec. 3.1): D3Q19, walls
     normal to z moving at -+u_w, periodic x and y, a centred drop of radius
     `radius` with interface width `xi`.  Every `every` strain units the
-    deformation D and inclination theta in the xz plane and the volume of
-    {phi > 0} are sampled, up to `strain` strain units."""
+    deformation D and inclination theta in the xz plane, the volume of
+    {phi > 0} and its number of components are sampled, up to `strain`
+    strain units or until the drop has broken up (two or more components)."""
     import math
 
     import numpy as np
@@ -175,15 +176,26 @@ def shear_history(*, radius: float = 25.0, xi: float = 2.0, shape=(256, 128, 128
         L.step(per)
         t += per
         phi = L.read(("phi",))["phi"]
+        comps = len(Dg.components(phi, (True, True, False)))
+        if comps == 0:
+            hist.append({"strain": round(t * dp.rate, 3), "D": None, "theta_deg": None, "volume": 0,
+                         "components": 0})
+            break
         d = Dg.deformation(phi, plane="xz", periodic=(True, True, False))
         hist.append({"strain": round(t * dp.rate, 3), "D": round(d.D, 4),
-                     "theta_deg": round(math.degrees(d.theta), 1), "volume": int((phi > 0).sum())})
+                     "theta_deg": round(math.degrees(d.theta), 1), "volume": int((phi > 0).sum()),
+                     "components": comps})
         if log:
-            log(f"[history] R={radius} xi={xi} strain={hist[-1]['strain']} D={hist[-1]['D']} "
-                f"theta={hist[-1]['theta_deg']}")
+            log(f"[history] R={radius} xi={xi} Ca={Ca} strain={hist[-1]['strain']} D={hist[-1]['D']} "
+                f"theta={hist[-1]['theta_deg']} components={comps}")
+        if comps >= 2:
+            break
     L.close()
+    outcome = "breakup" if hist and hist[-1]["components"] >= 2 else (
+        "dissolved" if hist and hist[-1]["components"] == 0 else "cap")
     return {"radius": radius, "xi": xi, "R_over_xi": radius / xi, "shape": list(shape), "Ca": Ca, "Re": Re,
-            "Pe": Pe, "taylor_D": 35.0 / 32.0 * Ca, "rate": dp.rate, "M": dp.M, "history": hist}
+            "Pe": Pe, "taylor_D": 35.0 / 32.0 * Ca, "rate": dp.rate, "M": dp.M, "outcome": outcome,
+            "history": hist}
 
 
 def main(argv=None):
