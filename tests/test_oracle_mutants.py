@@ -52,6 +52,8 @@ MUTANTS3 = [
     ("h equilibrium with mu_phi", "or_geq(kind, s->psi[x], s->muq[x], G3, u, heq);",
      "or_geq(kind, s->psi[x], s->mup[x], G3, u, heq);", 0),
     ("h bounced with phi", "hs - 2.0 * w[i] * s->psi[x] * cu / CS2", "hs - 2.0 * w[i] * s->phi[x] * cu / CS2", 0),
+    ("Laplacian of C2 with the wrong sign of psi", "0.5 * (lap_rho - lap_phi - lap_psi)",
+     "0.5 * (lap_rho - lap_phi + lap_psi)", 0),
 ]
 
 

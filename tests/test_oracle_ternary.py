@@ -13,6 +13,12 @@ C2 = (rho - phi - psi)/2, C3 = psi).
   the discrete functional with its gradient terms written with the lattice
   Laplacian (a numerical derivative of an energy assembled here);
 * the three order parameters are conserved to 1e-12 with moving walls;
+* a flat interface between any two components, the third absent, relaxes
+  to the profile that solves the discrete equilibrium of the pair
+  (C(1 - C)(1 - 2C) - alpha^2 lap_h C uniform, by Newton), the same for all
+  three pairs whatever the kappas, with the third component back at zero
+  and the continuum tanh((x - x0) / 2 alpha) profile within the lattice
+  error;
 * a drop of component 1 in component 3 obeys the Laplace law with the pair
   tension alpha (kappa1 + kappa3) / 6, which is not the (1, 2) tension."""
 import math
@@ -197,3 +203,52 @@ def test_laplace_law_of_a_pair():
     c2 = 0.5 * (o["rho"] - o["phi"] - o["psi"])
     assert np.abs(c2).max() < 2e-3
     assert np.hypot(o["ux"], o["uy"]).max() < 1e-4
+
+
+def _pair_profile(C0, al):
+    """Newton solution of C(1 - C)(1 - 2C) - alpha^2 (C[x+1] - 2C[x] + C[x-1])
+    = g (g unknown, uniform) on a periodic 1D lattice, with sum C fixed."""
+    n = C0.size
+    C, g = C0.copy(), 0.0
+    for _ in range(80):
+        lap = np.roll(C, 1) + np.roll(C, -1) - 2 * C
+        R = C * (1 - C) * (1 - 2 * C) - al * al * lap - g
+        J = np.diag((1 - 6 * C + 6 * C * C) + 2 * al * al) - al * al * (np.eye(n, k=1) + np.eye(n, k=-1))
+        J[0, -1] -= al * al
+        J[-1, 0] -= al * al
+        Jf = np.zeros((n + 1, n + 1))
+        Jf[:n, :n] = J
+        Jf[:n, n] = -1.0
+        Jf[n, :n] = 1.0
+        d = np.linalg.solve(Jf, -np.append(R, C.sum() - C0.sum()))
+        C += d[:n]
+        g += d[n]
+        if np.abs(d).max() < 1e-15:
+            break
+    return C
+
+
+def test_flat_interface_of_every_pair():
+    k1, k2, k3, al, M, n = 0.05, 0.04, 0.06, 1.5, 0.3, 64
+    x = np.arange(n)
+    slab = 0.5 * (1 + np.tanh((n / 4 - np.abs(x - (n - 1) / 2)) / (2 * al)))
+    got = {}
+    for m, q in ((0, 1), (0, 2), (1, 2)):
+        C = [np.zeros(n) for _ in range(3)]
+        C[m], C[q] = slab.copy(), 1 - slab
+        rho, phi, psi = C[0] + C[1] + C[2], C[0] - C[1], C[2]
+        sh = (1, 1, n)
+        p = O.make_params(0, (n, 1, 1), kappa1=k1, kappa2=k2, alpha=al, tau_f=1.0, tau_g=1.0, M=M)
+        L = O.Lattice3(p, k3, M, 1.0, phi.reshape(sh), psi.reshape(sh), rho.reshape(sh)).step(80000)
+        o = L.observe()
+        c = (0.5 * (o["rho"] + o["phi"] - o["psi"]).ravel(), 0.5 * (o["rho"] - o["phi"] - o["psi"]).ravel(),
+             o["psi"].ravel())
+        absent = c[3 - m - q]
+        assert max(np.ptp(o[k]) for k in ("mu_rho", "mu_phi", "mu_psi")) < 5e-7, (m, q)
+        assert np.abs(absent).max() < 3e-6, (m, q, np.abs(absent).max())
+        assert np.abs(c[m] - _pair_profile(slab, al)).max() < 5e-6, (m, q)
+        assert np.abs(c[m] - slab).max() < 5e-3          # the continuum profile, to the lattice error
+        assert np.abs(o["ux"]).max() < 1e-9
+        got[(m, q)] = c[m]
+    vals = list(got.values())
+    assert max(np.abs(a - b).max() for a in vals for b in vals) < 5e-6
