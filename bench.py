@@ -158,7 +158,8 @@ def consistent_init_rate(n: int = 400) -> dict:
 def ternary_rate(steps: int = 200) -> dict:
     """Throughput of a ternary lattice (third order parameter psi with its
     own population h) on the 256x128x128 shear workload: a drop of component
-    1 in a 2-3 mixture, FP32 storage, captured two-step graphs."""
+    1 in a 2-3 mixture, FP32 storage, captured two-step graphs.  The run is
+    checked to stay finite."""
     import torch
     from paper_2212_01617_amd import frelbm as F
     p, phi0, u0, meta = workload(0)
@@ -166,10 +167,16 @@ def ternary_rate(steps: int = 200) -> dict:
     c1 = 0.5 * (1.0 + phi0)
     psi0 = 0.3 * (1.0 - c1)
     phi = c1 - (1.0 - c1 - psi0)
+    # kappa3 = 4A, the kappa of the other two; psi's gradient stiffness is then
+    # alpha^2 ((kappa1 + kappa2) / 4 + kappa3) = 3 kappa against phi's kappa,
+    # so psi's mobility is a third of phi's to keep Gamma times the stiffness
+    # where the Cahn-Hilliard update is stable (with M3 = M this lattice
+    # diverges within 20 steps)
     p.ternary = 1
-    p.kappa3, p.M3, p.tau_h = p.kappa1 if p.use_paper_form else 4.0 * p.A, p.M, p.tau_g
+    p.kappa3, p.M3, p.tau_h = 4.0 * p.A, p.M / 3.0, p.tau_g
     L = F.Lattice(p, phi, None, u0, psi0=psi0, stream=torch.cuda.Stream())
     ms, _ = time_steps(L, steps, 10, 3)
+    L.reduce()                      # raises if any fluid cell went non-finite
     L.close()
     cells = sh[0] * sh[1] * sh[2]
     mlups = cells / (ms * 1e-3) / 1e6
