@@ -167,8 +167,9 @@ fre_status fre_lattice_init3(const fre_params *p, void *device_buf, size_t bytes
 fre_status fre_consistent_init(fre_lattice *L, const double *phi0, const double *u0, int64_t n);
 
 /* Replace the physical parameters (free energy, tau, M, wall and roller
- * velocities) of an existing lattice; shape, storage and bc must not change.
- * Takes effect for the next step. */
+ * velocities; kappa3, M3, tau_h of a ternary lattice) of an existing
+ * lattice; shape, storage, bc, the roller count and the ternary flag must
+ * not change (FRE_EINVAL).  Takes effect for the next step. */
 fre_status fre_set_params(fre_lattice *L, const fre_params *p);
 
 /* Advance n >= 0 time steps (Algorithm 1 at every fluid node, then
