@@ -477,6 +477,16 @@ __device__ __forceinline__ void force(const float4 *__restrict__ C, const Nbr &N
   for (int a = 0; a < 3; ++a) F[a] = mu_rho * gr[a] + mu_phi * gp[a] - gq[a];
 }
 
+// f_i^eq - w_i = w_i (rho - 1) + a_i (c_i . m) + w_i q_i (q_i: the
+// second-order part) rounded once to FP32: the three parts are summed in FP64.
+// Summed in FP32, each partial sum rounds, and in a region where rho, m and
+// u vary by less than an ulp every cell rounds the same way at every step:
+// the equilibrium's momentum then differs from m by the same amount in
+// every cell, and the flow drifts.
+__device__ __forceinline__ float feq_shifted(float wi, float ai, double drho, float cm, float wq) {
+  return (float)__builtin_fma((double)ai, (double)cm, __builtin_fma((double)wi, drho, (double)wq));
+}
+
 // Collision of one fluid cell and streaming of its populations (AA pattern
 // of parity ODD): every population goes to the slot it streams to.  If
 // `post` is given, the stored value of each moving population i > 0 also goes
@@ -565,13 +575,14 @@ __device__ __forceinline__ void collide_cell(const Pops<Q, S> &P, const Nbr &N, 
     if (!ODD) P.stg(opp(i), c, gs);
     else P.stg(i, N.template at<V>(i), gs);
   };
+  const double drho_d = (double)drho;
 #pragma unroll
   for (int i = 0; i < Q; ++i) {
     const float cF = V::cx(i) * F[0] + V::cy(i) * F[1] + V::cz(i) * F[2];
     const float cm = V::cx(i) * m[0] + V::cy(i) * m[1] + V::cz(i) * m[2];
     const float cu = cm * inv_rho;
     const float wi = V::w(i), ai = V::a(i);
-    const float dfeq = wi * drho + ai * cm + wi * rquad(cm, cu);                // f_i^eq - w_i
+    const float dfeq = feq_shifted(wi, ai, drho_d, cm, wi * rquad(cm, cu));     // f_i^eq - w_i
     const float src = ph.guo * (ai * cF - 3.0f * wi * uF + 3.0f * ai * cu * cF);  // Guo term
     const float fs = P.round(df[i] + ph.om_f * (dfeq - df[i]) + src);
     if (i == 0) {
@@ -1308,13 +1319,14 @@ __global__ __launch_bounds__(BX *BY) void k3_collide(T3View<Q> T) {
   const float m[3] = {j[0] + 0.5f * F[0], j[1] + 0.5f * F[1], j[2] + 0.5f * F[2]};
   const float mmr = (m[0] * m[0] + m[1] * m[1] + m[2] * m[2]) * inv_rho;
   const float uF = (m[0] * F[0] + m[1] * F[1] + m[2] * F[2]) * inv_rho;
+  const double drho_d = (double)drho;
 #pragma unroll
   for (int i = 0; i < Q; ++i) {
     const float cF = V::cx(i) * F[0] + V::cy(i) * F[1] + V::cz(i) * F[2];
     const float cm = V::cx(i) * m[0] + V::cy(i) * m[1] + V::cz(i) * m[2];
     const float cu = cm * inv_rho;
     const float wi = V::w(i), ai = V::a(i);
-    const float dfeq = wi * drho + ai * cm + wi * (4.5f * cm * cu - 1.5f * mmr);
+    const float dfeq = feq_shifted(wi, ai, drho_d, cm, wi * (4.5f * cm * cu - 1.5f * mmr));
     const float src = T.ph.guo * (ai * cF - 3.0f * wi * uF + 3.0f * ai * cu * cF);
     const float fs = df[i] + T.ph.om_f * (dfeq - df[i]) + src;
     if (!ODD || i == 0) T.st(T.f, i == 0 ? 0 : opp(i), c, fs);
