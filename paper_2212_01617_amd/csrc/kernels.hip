@@ -1149,6 +1149,7 @@ template <int Q> struct T3View {
   Phys ph;
   const int *fill;
   int n_fill;
+  TileMap tm;  // block order of k3_moments and k3_collide (64 x 4 tiles)
   // NT: non-temporal load, for passes that read each population once and
   // nothing else of the cell again
   template <bool NT = false>
@@ -1167,7 +1168,7 @@ template <int Q>
 __global__ __launch_bounds__(BX *BY) void k3_moments(T3View<Q> T, int odd) {
   int x, y, z;
   long long c;
-  if (!cell_of_thread(T.G, x, y, z, c)) return;
+  if (!cell_of_tile(T.G, T.tm, x, y, z, c)) return;
   if (T.nbm[c] & NB_SELF_SOLID) return;
   const Nbr N(T.G, x, y, z);
   float dr = 0.0f, ph = 0.0f, ps = 0.0f;
@@ -1297,7 +1298,7 @@ __global__ __launch_bounds__(BX *BY) void k3_collide(T3View<Q> T) {
   using V = VSet<Q>;
   int x, y, z;
   long long c;
-  if (!cell_of_thread(T.G, x, y, z, c)) return;
+  if (!cell_of_tile(T.G, T.tm, x, y, z, c)) return;
   const uint32_t bits = T.nbm[c];
   if (bits & NB_SELF_SOLID) return;
   const Nbr N(T.G, x, y, z);
@@ -1661,10 +1662,22 @@ static T3View<Q> t3_view(const LaunchArgs &a) {
   return T;
 }
 
+// the population passes over 64 x BY tiles in the XCD-aware block order
+// of the binary cell kernels (a tile's x neighbours on the same XCD, so the
+// cache lines that odd-parity streaming shares across a tile edge are
+// fetched once)
+template <int Q>
+static dim3 t3_tiles(const LaunchArgs &a, T3View<Q> &T) {
+  const dim3 grid = tile_grid(a.G, BY);
+  T.tm = TileMap(a.G.ex, a.G.ey, BY, (int)grid.x, 1);
+  return grid;
+}
+
 template <int Q>
 static void t3_couple(const LaunchArgs &a, int odd) {
-  const T3View<Q> T = t3_view<Q>(a);
-  k3_moments<Q><<<cell_grid(a.G), cell_block(), 0, a.stream>>>(T, odd);
+  T3View<Q> T = t3_view<Q>(a);
+  const dim3 tiles = t3_tiles<Q>(a, T);
+  k3_moments<Q><<<tiles, cell_block(), 0, a.stream>>>(T, odd);
   if (a.n_fill) k3_fill<Q, 0><<<fill_blocks(a.n_fill), 256, 0, a.stream>>>(T);
   k3_potential<Q><<<cell_grid(a.G), cell_block(), 0, a.stream>>>(T);
   if (a.n_fill) k3_fill<Q, 1><<<fill_blocks(a.n_fill), 256, 0, a.stream>>>(T);
@@ -1673,9 +1686,10 @@ static void t3_couple(const LaunchArgs &a, int odd) {
 template <int Q>
 static void t3_step(const LaunchArgs &a, int odd) {
   t3_couple<Q>(a, odd);
-  const T3View<Q> T = t3_view<Q>(a);
-  if (odd) k3_collide<Q, 1><<<cell_grid(a.G), cell_block(), 0, a.stream>>>(T);
-  else k3_collide<Q, 0><<<cell_grid(a.G), cell_block(), 0, a.stream>>>(T);
+  T3View<Q> T = t3_view<Q>(a);
+  const dim3 tiles = t3_tiles<Q>(a, T);
+  if (odd) k3_collide<Q, 1><<<tiles, cell_block(), 0, a.stream>>>(T);
+  else k3_collide<Q, 0><<<tiles, cell_block(), 0, a.stream>>>(T);
 }
 
 void launch_step3(const LaunchArgs &a, int odd) {
