@@ -63,7 +63,7 @@ def measured_traffic():
         return None
 
 
-def workload(storage: int, shape=(256, 128, 128), R: float = 25.0):
+def workload(storage: int, shape=(256, 128, 128), R: float = 25.0, sr: bool = False):
     """The shear-droplet lattice: D3Q19, walls in z moving at -+u_w, periodic
     x and y, a drop of radius R mid-domain, Ca = 0.1, Re = 1, xi = 2."""
     from paper_2212_01617_amd import frelbm as F
@@ -78,7 +78,8 @@ def workload(storage: int, shape=(256, 128, 128), R: float = 25.0):
     phi0 = synth.droplet_phi(sh, R, xi, noise=1e-4, seed=0)
     u0 = synth.shear_velocity(sh, gamma, axis_normal=2)
     phys = dp.phys()
-    p = F.make_params(F.FRE_D3Q19, (nx, ny, nz), storage=storage, bc=(0, 0, 1), wall_u=wu, **phys)
+    p = F.make_params(F.FRE_D3Q19, (nx, ny, nz), storage=storage, bc=(0, 0, 1), wall_u=wu,
+                      stochastic_rounding=sr, **phys)
     return p, phi0, u0, dict(shape=(nx, ny, nz), wall_u=wu, phys=phys)
 
 
@@ -411,8 +412,8 @@ def main():
         return
 
     res = {}
-    for storage in ((0,) if args.no_fp16 else (0, 1)):
-        p, phi0, u0, meta = workload(storage)
+    for storage in ((0,) if args.no_fp16 else (0, 1, 2)):  # 2: FP16 with stochastic rounding
+        p, phi0, u0, meta = workload(min(storage, 1), sr=storage == 2)
         L = F.Lattice(p, phi0, None, u0, stream=stream)
         tuned = L.autotune(10) if not args.no_tune else None
         ms, all_ms = time_steps(L, args.steps, args.warmup, args.reps)
@@ -465,6 +466,12 @@ def main():
                              "bytes_per_lu": b16, "step_frac": round(m16 * 1e6 * b16 / 1e9 / PEAK_HBM_GBS, 4),
                              "kernels_ms": {k: round(v, 5) for k, v in r16["prof"].items()},
                              "launch_shape": {k: {"rows": v[0], "xcd": v[1]} for k, v in r16["shape"].items()}}
+    if 2 in res:
+        r2 = res[2]
+        m2 = r2["n"] / (r2["ms"] * 1e-3) / 1e6
+        out["fp16_store"]["stochastic_rounding"] = {
+            "value": round(m2, 1), "unit": "MLUPS", "ms_per_step": round(r2["ms"], 5),
+            "kernels_ms": {k: round(v, 5) for k, v in r2["prof"].items()}}
     for v in res.values():
         v["L"].close()
     res.clear()

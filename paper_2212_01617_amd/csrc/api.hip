@@ -56,7 +56,7 @@ struct Plan {
   int off[3];
   int px;          // row pitch: ext[0] rounded up to a multiple of 64
   long long ncell;  // px * ext[1] * ext[2]
-  size_t o_f, o_g, o_g0, o_h, o_h0, o_mask, o_nbm, o_segf, o_M, o_C, o_CM, o_P0, o_PU, o_PD, o_XE, o_AUX, o_fill, o_part, total;
+  size_t o_f, o_g, o_g0, o_h, o_h0, o_ctr, o_mask, o_nbm, o_segf, o_M, o_C, o_CM, o_P0, o_PU, o_PD, o_XE, o_AUX, o_fill, o_part, total;
 };
 
 fre_status validate(const fre_params *p) {
@@ -64,6 +64,10 @@ fre_status validate(const fre_params *p) {
   if (p->kind != FRE_D2Q9 && p->kind != FRE_D3Q19) return fail(FRE_EINVAL, "kind %d not D2Q9/D3Q19", p->kind);
   if (p->storage != FRE_FP32 && p->storage != FRE_FP16) return fail(FRE_EINVAL, "storage %d", p->storage);
   if (p->ternary != 0 && p->ternary != 1) return fail(FRE_EINVAL, "ternary must be 0 or 1 (got %d)", p->ternary);
+  if (p->fp16_rounding != 0 && p->fp16_rounding != 1)
+    return fail(FRE_EINVAL, "fp16_rounding must be 0 or 1 (got %d)", p->fp16_rounding);
+  if (p->fp16_rounding && (p->storage != FRE_FP16 || p->ternary))
+    return fail(FRE_EINVAL, "stochastic rounding (fp16_rounding = 1) needs FP16 storage of a binary lattice");
   if (p->ternary) {
     if (p->storage != FRE_FP32) return fail(FRE_EINVAL, "ternary lattices need FP32 storage");
     if (!(p->kappa3 > 0) || !std::isfinite(p->kappa3)) return fail(FRE_EINVAL, "kappa3 must be > 0");
@@ -140,6 +144,9 @@ Plan make_plan(const fre_params *p) {
     P.o_h = take((size_t)P.q * P.ncell * 4);
     P.o_h0 = take((size_t)P.ncell * 2);
   }
+  // the step counter of stochastic rounding, inside the population range
+  // (checkpoints carry it)
+  P.o_ctr = p->fp16_rounding ? take(256) : 0;
   P.o_mask = take((size_t)P.ncell);
   P.o_nbm = take((size_t)P.ncell * 4);
   P.o_segf = take((size_t)P.ncell / 64);
@@ -333,6 +340,7 @@ void bind_args(fre_lattice *L) {
   a.mask = L->base + P.o_mask;
   a.nbm = (uint32_t *)(L->base + P.o_nbm);
   a.segf = L->base + P.o_segf;
+  a.ctr = P.o_ctr ? (uint32_t *)(L->base + P.o_ctr) : nullptr;
   a.M = (float2 *)(L->base + P.o_M);
   a.C = (float4 *)(L->base + P.o_C);
   a.P0 = P.o_P0 ? (float2 *)(L->base + P.o_P0) : nullptr;
@@ -538,8 +546,8 @@ fre_status fre_set_params(fre_lattice *L, const fre_params *p) {
   const fre_params &o = L->p;
   if (p->kind != o.kind || p->nx != o.nx || p->ny != o.ny || p->nz != o.nz || p->storage != o.storage ||
       p->bc[0] != o.bc[0] || p->bc[1] != o.bc[1] || p->bc[2] != o.bc[2] || p->n_rollers != o.n_rollers ||
-      p->ternary != o.ternary)
-    return fail(FRE_EINVAL, "shape, storage, bc, roller count and the ternary flag cannot change");
+      p->ternary != o.ternary || p->fp16_rounding != o.fp16_rounding)
+    return fail(FRE_EINVAL, "shape, storage, bc, roller count, the ternary flag and fp16_rounding cannot change");
   L->p = *p;
   L->a.ph = make_phys(p);
   reset_graph(L);
@@ -1233,6 +1241,7 @@ fre_status fre_batch_add(fre_batch *B, fre_lattice *L, int32_t *slot) {
   if (!B || !L || !slot) return fail(FRE_EINVAL, "NULL argument");
   if (L->batch) return fail(FRE_EINVAL, "lattice is already a batch member");
   if (L->p.ternary) return fail(FRE_EINVAL, "ternary lattices are stepped on their own");
+  if (L->p.fp16_rounding) return fail(FRE_EINVAL, "lattices with stochastic rounding are stepped on their own");
   if (L->state) return fail(FRE_ESTATE, "lattice is in the failed state");
   int free_slot = -1, members = 0;
   for (int k = 0; k < B->max_slots; ++k) {

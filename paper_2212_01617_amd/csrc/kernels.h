@@ -37,6 +37,7 @@ struct LaunchArgs {
   uint8_t *mask;
   uint32_t *nbm;  // per cell: non-fluid neighbour bits, NB_SELF_SOLID
   uint8_t *segf;  // per 64-cell row segment: 1 when every cell is fluid with fluid neighbours only
+  uint32_t *ctr;  // FP16 storage with stochastic rounding: the step counter (else null)
   float2 *M;    // (rho - 1, phi)
   float4 *C;    // (rho - 1, phi, Pi = rho mu_rho + phi mu_phi, mu_phi)
   float2 *P0, *PU, *PD;  // FP32: first-pass moment sums by source plane (same, below, above)
@@ -58,8 +59,8 @@ struct LaunchArgs {
 template <int Q, int S> inline Pops<Q, S> make_pops(const LaunchArgs &a);
 template <> inline Pops<9, 0> make_pops<9, 0>(const LaunchArgs &a) { return Pops<9, 0>{(float *)a.f, (float *)a.g, (__half *)a.g0}; }
 template <> inline Pops<19, 0> make_pops<19, 0>(const LaunchArgs &a) { return Pops<19, 0>{(float *)a.f, (float *)a.g, (__half *)a.g0}; }
-template <> inline Pops<9, 1> make_pops<9, 1>(const LaunchArgs &a) { return Pops<9, 1>{(__half *)a.f, (__half *)a.g, a.g0}; }
-template <> inline Pops<19, 1> make_pops<19, 1>(const LaunchArgs &a) { return Pops<19, 1>{(__half *)a.f, (__half *)a.g, a.g0}; }
+template <> inline Pops<9, 1> make_pops<9, 1>(const LaunchArgs &a) { return Pops<9, 1>{(__half *)a.f, (__half *)a.g, a.g0, a.ctr}; }
+template <> inline Pops<19, 1> make_pops<19, 1>(const LaunchArgs &a) { return Pops<19, 1>{(__half *)a.f, (__half *)a.g, a.g0, a.ctr}; }
 
 // Device view of one lattice for the kernels of one (velocity set, storage)
 // class.
@@ -105,6 +106,7 @@ template <int Q, int S> struct LatView {
   const int *fill;
   int n_fill;
   TileMap tm;  // block order of the single-lattice tile kernels
+  int tick;    // the moments pass of a step advances the rounding step counter
 };
 
 // One slot of a batch, as stored in device memory.  Arrays are given as

@@ -509,11 +509,11 @@ __device__ __forceinline__ float feq_shifted(float wi, float ai, double drho, fl
 // alone, tau_g^-1 sum_{i>0} (g_i - g_i^eq), which equals (g_0^eq - g_0) / tau_g
 // since g_0^eq complements the others to phi, and added to hi + lo with the
 // rounding error of the sum kept (TwoSum, Knuth).
-template <int Q, int S, int ODD, int NT>
+template <int Q, int S, int ODD, int NT, bool SR = false>
 __device__ __forceinline__ void collide_cell(const Pops<Q, S> &P, const Nbr &N, long long c,
                                              const float4 *__restrict__ C,
                                              const Phys &ph, float (*post)[NT], int tid, float &rho_out,
-                                             float &phi_out, float2 &rest_out) {
+                                             float &phi_out, float2 &rest_out, uint32_t &rs) {
   using V = VSet<Q>;
   constexpr bool X = S == 0;  // g_0 as hi + lo
   const float4 cc = C[c];
@@ -569,7 +569,7 @@ __device__ __forceinline__ void collide_cell(const Pops<Q, S> &P, const Nbr &N, 
     const float cu = cm * inv_rho;
     const float geq = V::w(i) * ph.gam3 * mu_phi + phi * (V::a(i) * cu + V::w(i) * (rquad(cm, cu) * inv_rho));
     geq_rest += geq;
-    const float gs = P.round(g[i] + ph.om_g * (geq - g[i]));
+    const float gs = P.template round_at<SR>(g[i] + ph.om_g * (geq - g[i]), rs);
     if (post) post[Q - 1 + i - 1][tid] = gs;
     // streamed: slot (x, opp(i)) after an even step, (x + c_i, i) after an odd one
     if (!ODD) P.stg(opp(i), c, gs);
@@ -584,7 +584,7 @@ __device__ __forceinline__ void collide_cell(const Pops<Q, S> &P, const Nbr &N, 
     const float wi = V::w(i), ai = V::a(i);
     const float dfeq = feq_shifted(wi, ai, drho_d, cm, wi * rquad(cm, cu));     // f_i^eq - w_i
     const float src = ph.guo * (ai * cF - 3.0f * wi * uF + 3.0f * ai * cu * cF);  // Guo term
-    const float fs = P.round(df[i] + ph.om_f * (dfeq - df[i]) + src);
+    const float fs = P.template round_at<SR>(df[i] + ph.om_f * (dfeq - df[i]) + src, rs);
     if (i == 0) {
       P.stf(0, c, fs);
       rest_out.x = fs;
@@ -625,10 +625,10 @@ __device__ __forceinline__ void collide_cell(const Pops<Q, S> &P, const Nbr &N, 
 // i) after an even step, (x, opp(i)) after an odd one.  Only cells next to
 // a solid take this path; keeping it after the branch-free main loop (rather
 // than a branch per direction inside it) holds the register count down.
-template <int Q, int S, int ODD, bool WITH_G = true>
+template <int Q, int S, int ODD, bool WITH_G = true, bool SR = false>
 __device__ __forceinline__ void bounce_back(const Pops<Q, S> &P, const Nbr &N, long long c, uint32_t bits,
                                          const uint8_t *__restrict__ mask, const Geom &G, const Phys &ph,
-                                         int x, int y, int z, float rho, float phi) {
+                                         int x, int y, int z, float rho, float phi, uint32_t &rs) {
   using V = VSet<Q>;
 #pragma unroll
   for (int i = 1; i < Q; ++i) {
@@ -642,7 +642,8 @@ __device__ __forceinline__ void bounce_back(const Pops<Q, S> &P, const Nbr &N, l
     float uw[3];
     body_velocity<V>(G, ph, mask[n], x, y, z, xs, ys, zs, i, uw);
     const float k = 6.0f * V::w(i) * (V::cx(i) * uw[0] + V::cy(i) * uw[1] + V::cz(i) * uw[2]);
-    const float fb = P.round(fs - k * rho), gb = P.round(gs - k * phi);
+    const float fb = P.template round_at<SR>(fs - k * rho, rs);
+    const float gb = P.template round_at<SR>(gs - k * phi, rs);
     const int bp = ODD ? opp(i) : i;
     const long long bc = ODD ? c : n;
     P.stf(bp, bc, fb);
@@ -656,7 +657,7 @@ __device__ __forceinline__ void bounce_back(const Pops<Q, S> &P, const Nbr &N, l
 // first pass of the moment groups of its column: S0 for this plane, UP for
 // the plane above and DN for the plane below (all their sources lie in this
 // plane), from the tile's post-collision values.
-template <int Q, int S, int ODD>
+template <int Q, int S, int ODD, bool SR = false>
 __device__ __forceinline__ void stage_collide(const LatView<Q, S> &L, int x, int y, int z, bool active) {
   using V = VSet<Q>;
   constexpr int NT = BX * COLLIDE_ROWS;
@@ -668,8 +669,9 @@ __device__ __forceinline__ void stage_collide(const LatView<Q, S> &L, int x, int
     const Nbr N(L.G, x, y, z);
     float rho, phi;
     float2 rest;
-    collide_cell<Q, S, ODD, NT>(L.P, N, c, L.C, L.ph, nullptr, 0, rho, phi, rest);
-    if (bits != 0u) bounce_back<Q, S, ODD>(L.P, N, c, bits, L.mask, L.G, L.ph, x, y, z, rho, phi);
+    uint32_t rs = SR ? sr_seed(c, L.P.step_key()) : 0u;
+    collide_cell<Q, S, ODD, NT, SR>(L.P, N, c, L.C, L.ph, nullptr, 0, rho, phi, rest, rs);
+    if (bits != 0u) bounce_back<Q, S, ODD, true, SR>(L.P, N, c, bits, L.mask, L.G, L.ph, x, y, z, rho, phi, rs);
     return;
   }
   __shared__ float post[2 * (Q - 1)][NT];
@@ -683,8 +685,9 @@ __device__ __forceinline__ void stage_collide(const LatView<Q, S> &L, int x, int
     if (fluid) {
       const Nbr N(L.G, x, y, z);
       float rho, phi;
-      collide_cell<Q, S, ODD, NT>(L.P, N, c, L.C, L.ph, post, tid, rho, phi, rest);
-      if (bits != 0u) bounce_back<Q, S, ODD>(L.P, N, c, bits, L.mask, L.G, L.ph, x, y, z, rho, phi);
+      uint32_t rs = 0u;
+      collide_cell<Q, S, ODD, NT>(L.P, N, c, L.C, L.ph, post, tid, rho, phi, rest, rs);
+      if (bits != 0u) bounce_back<Q, S, ODD>(L.P, N, c, bits, L.mask, L.G, L.ph, x, y, z, rho, phi, rs);
     }
   }
   live[tid] = fluid ? 1 : 0;
@@ -789,7 +792,8 @@ __device__ __forceinline__ void stage_pre_collide(const LatView<Q, S> &L, int x,
     if (!ODD) L.P.stf(opp(i), c, fs);
     else L.P.stf(i, N.template at<V>(i), fs);
   }
-  if (bits != 0u) bounce_back<Q, S, ODD, false>(L.P, N, c, bits, L.mask, L.G, L.ph, x, y, z, rho, 0.0f);
+  uint32_t rs = 0u;
+  if (bits != 0u) bounce_back<Q, S, ODD, false>(L.P, N, c, bits, L.mask, L.G, L.ph, x, y, z, rho, 0.0f, rs);
 }
 
 // Per-cell stages other than collide (ODD: parity of the state they read).
@@ -805,14 +809,19 @@ __device__ __forceinline__ void run_stage(const LatView<Q, S> &L, int x, int y, 
 // The collide keeps the compiler's register choice (3 waves per SIMD for
 // D3Q19): capped at 128 VGPRs (4 waves) it spills 52-56 bytes per lane in FP16
 // storage and was measured 16% slower (186 against 160 us at 256x128x128).
-template <int Q, int S, int STAGE, int ODD>
+template <int Q, int S, int STAGE, int ODD, bool SR = false>
 __global__ __launch_bounds__(BX *MAX_ROWS) void k_cells(LatView<Q, S> L) {
   int x, y, z;
   long long c;
   const bool in = cell_of_tile(L.G, L.tm, x, y, z, c);
   if (STAGE == ST_COLLIDE) {
-    stage_collide<Q, S, ODD>(L, x, y, z, in);
+    stage_collide<Q, S, ODD, SR>(L, x, y, z, in);
     return;
+  }
+  if constexpr (S == 1 && STAGE == ST_MOMENTS) {
+    // a step's moments pass runs before its collide, after the previous
+    // collide: the counter the collide reads advances once per step
+    if (L.tick && L.P.ctr && blockIdx.x == 0 && threadIdx.x == 0 && threadIdx.y == 0) L.P.ctr[0] += 1u;
   }
   if (in) run_stage<Q, S, STAGE, ODD>(L, x, y, z);
 }
@@ -906,6 +915,7 @@ __device__ __forceinline__ LatView<Q, S> view_of(char *base, const Inst &I) {
   L.XE = (float2 *)(base + I.XE);
   L.AUX = nullptr;
   L.G = I.G; L.ph = I.ph; L.fill = (const int *)(base + I.fill); L.n_fill = I.n_fill;
+  L.tick = 0;
   return L;
 }
 
@@ -1462,6 +1472,7 @@ static LatView<Q, S> view_of_args(const LaunchArgs &a) {
   L.nbm = a.nbm; L.segf = a.segf; L.mask = a.mask; L.M = a.M; L.C = a.C;
   L.P0 = a.P0; L.PU = a.PU; L.PD = a.PD; L.XE = a.XE; L.AUX = a.AUX;
   L.G = a.G; L.ph = a.ph; L.fill = a.fill_list; L.n_fill = a.n_fill;
+  L.tick = 0;
   return L;
 }
 
@@ -1469,12 +1480,18 @@ static LatView<Q, S> view_of_args(const LaunchArgs &a) {
 // k_combine -- uses shape 0; with the by-product the collide tile always has
 // COLLIDE_ROWS rows and only its block order varies).
 template <int Q, int S, int STAGE>
-static void cells_launch(const LaunchArgs &a, int odd) {
+static void cells_launch(const LaunchArgs &a, int odd, int tick = 0) {
   LatView<Q, S> L = view_of_args<Q, S>(a);
+  L.tick = tick;
   const Shape sh = a.shape[STAGE <= ST_COLLIDE ? STAGE : SHAPE_MOMENTS];
   const int rows = (STAGE == ST_COLLIDE && ByProduct<S>::on) ? COLLIDE_ROWS : sh.rows;
   const dim3 grid = tile_grid(a.G, rows), block(BX, rows, 1);
   L.tm = TileMap(a.G.ex, a.G.ey, rows, (int)grid.x, sh.xcd);
+  if (S == 1 && STAGE == ST_COLLIDE && a.ctr) {  // FP16 storage, stochastic rounding
+    if (odd) k_cells<Q, S, STAGE, 1, true><<<grid, block, 0, a.stream>>>(L);
+    else k_cells<Q, S, STAGE, 0, true><<<grid, block, 0, a.stream>>>(L);
+    return;
+  }
   if (odd) k_cells<Q, S, STAGE, 1><<<grid, block, 0, a.stream>>>(L);
   else k_cells<Q, S, STAGE, 0><<<grid, block, 0, a.stream>>>(L);
 }
@@ -1485,7 +1502,7 @@ static void fill_launch(const LaunchArgs &a) {
 }
 
 template <int Q, int S>
-static void moments_launch(const LaunchArgs &a, int odd) { cells_launch<Q, S, ST_MOMENTS>(a, odd); }
+static void moments_launch(const LaunchArgs &a, int odd, int tick = 0) { cells_launch<Q, S, ST_MOMENTS>(a, odd, tick); }
 
 // The z-marching potential: planes per block chosen so that the grid has
 // about 2048 blocks (8 per CU).
@@ -1524,7 +1541,7 @@ static void step_seq(const LaunchArgs &a, int odd, hipEvent_t *ev) {
   int k = 0;
   if (ev) (void)hipEventRecord(ev[k++], a.stream);
   if (!ByProduct<S>::on) {
-    moments_launch<Q, S>(a, odd);
+    moments_launch<Q, S>(a, odd, 1);  // the step's moments advance the rounding counter
     if (ev) (void)hipEventRecord(ev[k++], a.stream);
   }
   couple_seq<Q, S>(a, ev, k);

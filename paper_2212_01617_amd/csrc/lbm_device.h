@@ -209,6 +209,49 @@ __device__ __forceinline__ void st_at(T *base, uint32_t off, T v) {
   *(T *)((char *)base + off) = v;
 }
 
+// Stochastic rounding to half (FP16 storage with fp16_rounding = 1).  Each
+// cell draws a seed per step, a hash of the cell index and the step counter
+// (a 32-bit integer finalizer: two multiply-xorshift rounds), and every value
+// it stores takes the next number of a xorshift32 stream (Marsaglia, 2003)
+// from that seed.  The rounding of one value is unbiased for any stream whose
+// numbers are uniform; the hash keeps cells and steps apart.
+__device__ __forceinline__ uint32_t sr_seed(long long c, uint32_t step) {
+  uint32_t h = (uint32_t)c * 0x9E3779B1u ^ step * 0x85EBCA77u;
+  h ^= h >> 16;
+  h *= 0x7FEB352Du;
+  h ^= h >> 15;
+  h *= 0x846CA68Bu;
+  h ^= h >> 16;
+  return h | 1u;  // xorshift32 needs a nonzero state
+}
+
+__device__ __forceinline__ uint32_t sr_next(uint32_t x) {
+  x ^= x << 13;
+  x ^= x >> 17;
+  x ^= x << 5;
+  return x;
+}
+
+// v rounded to one of the two halves next to it, the upper one with
+// probability equal to v's distance from the lower one over their spacing,
+// for r uniform in [0, 2^32): unbiased, so a rounding error that
+// round-to-nearest would repeat in every cell and at every step (a nearly
+// uniform flow) averages out instead.  Where halves are normal (|v| >= 2^-14)
+// their grid keeps the top 10 of FP32's 23 mantissa bits: adding r's low 13
+// bits under them and clearing those bits rounds the magnitude up exactly
+// when the carry reaches the kept bits.  Below, the grid is the multiples of
+// 2^-24: v 2^24 (exact) is rounded to an integer, up when its fractional part
+// exceeds a uniform draw from r's top 24 bits.  Both are formed and one
+// selected (a branch here costs the collide a third of its occupancy).
+// Magnitudes beyond the largest half become inf or nan, as a plain
+// conversion would make them inf.
+__device__ __forceinline__ float sr_half(float v, uint32_t r) {
+  const float tn = __uint_as_float((__float_as_uint(v) + (r & 0x1fffu)) & ~0x1fffu);
+  const float y = v * 0x1p24f, k = floorf(y);
+  const float ts = (k + ((float)(r >> 8) * 0x1p-24f < y - k ? 1.0f : 0.0f)) * 0x1p-24f;
+  return fabsf(v) >= 0x1p-14f ? tn : ts;
+}
+
 template <int Q, int S> struct Pops;
 
 template <int Q> struct Pops<Q, 0> {
@@ -220,6 +263,9 @@ template <int Q> struct Pops<Q, 0> {
   __half *g0l;
   // the value a store keeps (identity for FP32)
   __device__ __forceinline__ float round(float v) const { return v; }
+  template <bool SR>
+  __device__ __forceinline__ float round_at(float v, uint32_t &) const { return v; }
+  __device__ __forceinline__ uint32_t step_key() const { return 0u; }
   __device__ __forceinline__ float ldg0lo(long long c) const { return __half2float(g0l[c]) * 0x1p-24f; }
   __device__ __forceinline__ void stg0lo(long long c, float lo) const { g0l[c] = __float2half_rn(lo * 0x1p24f); }
   __device__ __forceinline__ float ldf(int i, long long c) const { return ld_at(f, blk_offset<4>(Q, i, c)); }
@@ -233,8 +279,23 @@ template <int Q> struct Pops<Q, 0> {
 template <int Q> struct Pops<Q, 1> {
   __half *f, *g;  // g: q planes like f, plane 0 unused
   float *g0;      // g_0
+  // step counter of stochastic rounding (null: round to nearest even)
+  uint32_t *ctr = nullptr;
   // the value a half store keeps (g_0 is stored in FP32 and not rounded)
   __device__ __forceinline__ float round(float v) const { return __half2float(__float2half_rn(v)); }
+  // the same, rounded stochastically with SR from the cell's stream rs (a
+  // separate instantiation, so the round-to-nearest kernels keep their
+  // register budget)
+  template <bool SR>
+  __device__ __forceinline__ float round_at(float v, uint32_t &rs) const {
+    if constexpr (SR) {
+      rs = sr_next(rs);
+      return sr_half(v, rs);
+    } else {
+      return round(v);
+    }
+  }
+  __device__ __forceinline__ uint32_t step_key() const { return ctr ? ctr[0] : 0u; }
   __device__ __forceinline__ float ldf(int i, long long c) const { return __half2float(ld_at(f, blk_offset<2>(Q, i, c))); }
   __device__ __forceinline__ float ldg(int i, long long c) const {
     return i == 0 ? ld_at(g0, (uint32_t)c * 4u) : __half2float(ld_at(g, blk_offset<2>(Q, i, c)));

@@ -42,7 +42,7 @@ class fre_params(C.Structure):
         ("kind", C.c_int32), ("nx", C.c_int32), ("ny", C.c_int32), ("nz", C.c_int32),
         ("storage", C.c_int32), ("bc", C.c_int32 * 3),
         ("wall_u", ((C.c_double * 3) * 2) * 3),
-        ("n_rollers", C.c_int32), ("reserved0", C.c_int32),
+        ("n_rollers", C.c_int32), ("fp16_rounding", C.c_int32),
         ("rollers", fre_roller * 4),
         ("A", C.c_double), ("kappa", C.c_double),
         ("kappa1", C.c_double), ("kappa2", C.c_double), ("alpha", C.c_double),
@@ -124,10 +124,11 @@ def _ptr(a: np.ndarray):
 
 def make_params(kind, shape, *, storage=FRE_FP32, bc=(0, 0, 0), wall_u=None, rollers=(),
                 A=None, kappa=None, kappa1=None, kappa2=None, alpha=None,
-                tau_f=1.0, tau_g=1.0, M=0.1, ternary=None) -> fre_params:
+                tau_f=1.0, tau_g=1.0, M=0.1, ternary=None, stochastic_rounding=False) -> fre_params:
     """shape = (nx, ny, nz); rollers = [(center(3), omega, axis, radius)];
     give either (A, kappa) or (kappa1, kappa2, alpha).  A ternary lattice
-    takes ternary=(kappa3, M3, tau_h)."""
+    takes ternary=(kappa3, M3, tau_h).  stochastic_rounding (FP16 storage)
+    sets fp16_rounding = 1."""
     p = fre_params()
     p.kind = kind
     p.nx, p.ny, p.nz = shape
@@ -159,6 +160,7 @@ def make_params(kind, shape, *, storage=FRE_FP32, bc=(0, 0, 0), wall_u=None, rol
     if ternary is not None:
         p.ternary = 1
         p.kappa3, p.M3, p.tau_h = ternary
+    p.fp16_rounding = 1 if stochastic_rounding else 0
     return p
 
 

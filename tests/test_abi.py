@@ -82,6 +82,25 @@ def test_ternary_flag_is_0_or_1(lib):
     assert ei.value.status == F.FRE_EINVAL
 
 
+@pytest.mark.parametrize("bad", [
+    dict(stochastic_rounding=True),                                                   # FP32 storage
+    dict(stochastic_rounding=True, storage=F.FRE_FP16, ternary=(0.1, 0.05, 1.0)),     # ternary
+])
+def test_stochastic_rounding_needs_binary_fp16(lib, bad):
+    with pytest.raises(F.FreError) as ei:
+        F.footprint(_ok_params(**bad))
+    assert ei.value.status == F.FRE_EINVAL
+    assert "fp16_rounding" in str(ei.value) or "FP32" in str(ei.value)
+    p = _ok_params(storage=F.FRE_FP16)
+    p.fp16_rounding = 2
+    with pytest.raises(F.FreError) as ei:
+        F.footprint(p)
+    assert ei.value.status == F.FRE_EINVAL
+    # accepted with FP16 storage, and the counter adds to the footprint
+    assert F.footprint(_ok_params(storage=F.FRE_FP16, stochastic_rounding=True)) > F.footprint(
+        _ok_params(storage=F.FRE_FP16))
+
+
 def test_ternary_footprint_holds_the_third_population(lib):
     q, n = 19, 16 * 8 * 8
     assert F.footprint(_ok_params(ternary=(0.1, 0.05, 1.0))) >= F.footprint(_ok_params()) + q * n * 4 - 64 * n

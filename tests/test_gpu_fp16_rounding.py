@@ -1,0 +1,139 @@
+"""FP16 storage with stochastic rounding (fp16_rounding = 1), through the C
+ABI.
+
+* One step from a uniform state: every cell computes the same post-collision
+  value v, and each stored half must be one of the two halves around v (v from
+  the FP64 oracle stepped from the same stored populations), the upper one in
+  a fraction of the cells that matches (v - lo) / (hi - lo) within sampling
+  error: the rounding is unbiased.  Round-to-nearest stores the nearer half
+  in every cell.
+* Parity with the FP64 oracle over 200 steps of the 3D shear case at the
+  bar of round-to-nearest FP16 storage.
+* Bitwise reproducible: captured graphs and launch-by-launch stepping agree,
+  and a checkpoint (which carries the step counter) resumes the run bitwise.
+The long-horizon effect (the 2D channel drift) is checked in the long-run
+tests."""
+import numpy as np
+import pytest
+import torch
+
+from oracle import oracle as O
+from paper_2212_01617_amd import frelbm as F
+
+from _pair import case_inputs, ensure_gpu_lib, field_errors, log, oracle_twin
+
+pytestmark = pytest.mark.gpu
+
+PHYS = dict(A=5.89e-3, kappa=2.36e-2, tau_f=1.0, tau_g=1.75, M=5.26)
+
+
+@pytest.fixture(scope="module", autouse=True)
+def _lib():
+    assert torch.cuda.is_available(), "GPU tests need a GPU"
+    ensure_gpu_lib()
+
+
+def _halves_around(x):
+    """(lo, hi): the neighbouring halves with lo <= x <= hi (x float64)."""
+    h = x.astype(np.float16)
+    hf = h.astype(np.float64)
+    other = np.where(x > hf, np.nextafter(h, np.float16(np.inf)), np.nextafter(h, np.float16(-np.inf)))
+    of = other.astype(np.float64)
+    return np.minimum(hf, of), np.maximum(hf, of)
+
+
+@pytest.mark.parametrize("kind,shape", [(0, (64, 64, 1)), (1, (32, 16, 16))])
+def test_one_step_from_a_uniform_state_is_unbiased(kind, shape):
+    nx, ny, nz = shape
+    sh = (nz, ny, nx)
+    phi0 = np.full(sh, 0.3)
+    rho0 = np.full(sh, 1.0123)
+    u0 = np.zeros((3,) + sh)
+    u0[0], u0[1] = 0.0113, -0.0047
+    if kind == 1:
+        u0[2] = 0.0061
+    _, w = O.tables(kind)
+    q = len(w)
+    out = {}
+    for sr in (False, True):
+        p = F.make_params(kind, shape, storage=F.FRE_FP16, stochastic_rounding=sr, **PHYS)
+        L = F.Lattice(p, phi0, rho0, u0)
+        f0, g0 = L.populations()
+        ref = oracle_twin(p, phi0, rho0, u0)
+        ref.set_populations(f0, g0)
+        ref.step(1)
+        vf, vg = ref.populations()
+        L.step(1)
+        sf, sg = L.populations()
+        L.close()
+        out[sr] = (vf, vg, sf, sg)
+    ncell = nx * ny * nz
+    checked = 0
+    for sr, (vf, vg, sf, sg) in out.items():
+        # the stored values: f_i - w_i for every i, g_i for i > 0 (g_0 is FP32)
+        for name, v, s, shift, first in (("f", vf, sf, w, 0), ("g", vg, sg, np.zeros(q), 1)):
+            for i in range(first, q):
+                vi = v[i].reshape(-1) - shift[i]
+                si = s[i].reshape(-1) - shift[i]
+                assert np.ptp(vi) < 1e-12, (name, i)   # a uniform state stays uniform
+                lo, hi = _halves_around(vi[:1])
+                lo, hi = float(lo[0]), float(hi[0])
+                # the read-back adds w_i in FP32: match each value to a half
+                # within 2% of the half step
+                tol = 0.02 * (hi - lo)
+                is_lo, is_hi = np.abs(si - lo) < tol, np.abs(si - hi) < tol
+                at_lo, at_hi = np.count_nonzero(is_lo), np.count_nonzero(is_hi)
+                assert at_lo + at_hi == ncell, (sr, name, i, lo, hi, np.unique(si)[:6])
+                frac = (vi[0] - lo) / (hi - lo)
+                if not sr:
+                    if abs(frac - 0.5) > 0.01:
+                        assert (at_hi if frac > 0.5 else at_lo) == ncell, (name, i, frac)
+                    continue
+                got = at_hi / ncell
+                sigma = np.sqrt(max(frac * (1 - frac), 1e-4) / ncell)
+                # v differs from the kernel's FP32 value by far less than 1% of a half step
+                assert abs(got - frac) < 5 * sigma + 0.01, (name, i, got, frac)
+                checked += 1
+    log(f"[sr] kind={kind} {shape}: {checked} stored slots matched the unbiased fraction")
+    assert checked >= q
+
+
+def test_parity_with_the_oracle_at_the_fp16_bar():
+    shape = (40, 24, 20)
+    uw = 0.017
+    wu = np.zeros((3, 2, 3))
+    wu[2, 0, 0], wu[2, 1, 0] = -uw, uw
+    phi0, _, u0 = case_inputs(1, shape, radius=6, xi=2.0, shear=(2 * uw / 20, 2))
+    po = O.make_params(1, shape, bc=(0, 0, 1), wall_u=wu, **PHYS)
+    ref = O.Lattice(po, phi0, None, u0)
+    ref.step(200)
+    p = F.make_params(1, shape, storage=F.FRE_FP16, stochastic_rounding=True, bc=(0, 0, 1), wall_u=wu, **PHYS)
+    gpu = F.Lattice(p, phi0, None, u0, stream=torch.cuda.Stream())
+    gpu.step(200)
+    err = field_errors(ref, gpu)
+    log("[parity] fp16_stochastic: " + " ".join(f"{k}={v:.2e}" for k, v in err.items()))
+    # the same bars as round-to-nearest FP16 storage
+    assert err["phi"] < 2.5e-5 and err["u"] < 1.5e-5 and err["rho"] < 1.6e-5
+
+
+@pytest.mark.parametrize("kind,shape", [(0, (48, 40, 1)), (1, (24, 16, 12))])
+def test_graph_eager_and_checkpoint_bitwise(kind, shape):
+    phi0, rho0, u0 = case_inputs(kind, shape, radius=5, xi=2.0, noise=1e-3, seed=3, rho_amp=0.01, u_amp=0.01)
+    p = F.make_params(kind, shape, storage=F.FRE_FP16, stochastic_rounding=True, **PHYS)
+    a = F.Lattice(p, phi0, rho0, u0, stream=torch.cuda.Stream())  # captured graphs
+    b = F.Lattice(p, phi0, rho0, u0)                               # one launch at a time
+    a.step(37)
+    b.step(37)
+    for x, y in zip(a.populations(), b.populations()):
+        assert np.array_equal(x, y)
+    blob = a.save()
+    a.step(41)
+    c = F.Lattice(p, phi0, rho0, u0)
+    c.load(blob)
+    c.step(41)
+    for x, y in zip(a.populations(), c.populations()):
+        assert np.array_equal(x, y)
+    # the rounding depends on the step: the run differs from round-to-nearest
+    d = F.Lattice(F.make_params(kind, shape, storage=F.FRE_FP16, **PHYS), phi0, rho0, u0)
+    d.step(78)
+    assert not np.array_equal(a.populations()[0], d.populations()[0])
