@@ -137,3 +137,20 @@ def test_graph_eager_and_checkpoint_bitwise(kind, shape):
     d = F.Lattice(F.make_params(kind, shape, storage=F.FRE_FP16, **PHYS), phi0, rho0, u0)
     d.step(78)
     assert not np.array_equal(a.populations()[0], d.populations()[0])
+
+
+def test_autotune_keeps_the_run_and_its_counter():
+    """Tuning times steps and restores the state, the rounding step counter
+    included: a tuned run continues bitwise as an untuned twin."""
+    shape = (64, 32, 16)
+    phi0, rho0, u0 = case_inputs(1, shape, radius=6, xi=2.0, noise=1e-3, seed=4, rho_amp=0.01, u_amp=0.01)
+    p = F.make_params(1, shape, storage=F.FRE_FP16, stochastic_rounding=True, **PHYS)
+    a = F.Lattice(p, phi0, rho0, u0, stream=torch.cuda.Stream())
+    b = F.Lattice(p, phi0, rho0, u0, stream=torch.cuda.Stream())
+    a.step(11)
+    b.step(11)
+    a.autotune(4)
+    a.step(23)
+    b.step(23)
+    for x, y in zip(a.populations(), b.populations()):
+        assert np.array_equal(x, y)
