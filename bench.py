@@ -418,7 +418,7 @@ def main():
         tuned = L.autotune(10) if not args.no_tune else None
         ms, all_ms = time_steps(L, args.steps, args.warmup, args.reps)
         n_fluid = meta["shape"][0] * meta["shape"][1] * meta["shape"][2]
-        prof = L.profile(20)
+        prof = L.profile(100)   # per-kernel means over 100 individually launched steps
         ok = L.reduce()
         res[storage] = dict(ms=ms, all_ms=all_ms, n=n_fluid, prof=prof, L=L, meta=meta,
                             p=p, phi0=phi0, u0=u0, sums=ok, shape=L.launch_shape())
