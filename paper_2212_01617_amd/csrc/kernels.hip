@@ -1487,10 +1487,12 @@ static void cells_launch(const LaunchArgs &a, int odd, int tick = 0) {
   const int rows = (STAGE == ST_COLLIDE && ByProduct<S>::on) ? COLLIDE_ROWS : sh.rows;
   const dim3 grid = tile_grid(a.G, rows), block(BX, rows, 1);
   L.tm = TileMap(a.G.ex, a.G.ey, rows, (int)grid.x, sh.xcd);
-  if (S == 1 && STAGE == ST_COLLIDE && a.ctr) {  // FP16 storage, stochastic rounding
-    if (odd) k_cells<Q, S, STAGE, 1, true><<<grid, block, 0, a.stream>>>(L);
-    else k_cells<Q, S, STAGE, 0, true><<<grid, block, 0, a.stream>>>(L);
-    return;
+  if constexpr (S == 1 && STAGE == ST_COLLIDE) {
+    if (a.ctr) {  // stochastic rounding
+      if (odd) k_cells<Q, S, STAGE, 1, true><<<grid, block, 0, a.stream>>>(L);
+      else k_cells<Q, S, STAGE, 0, true><<<grid, block, 0, a.stream>>>(L);
+      return;
+    }
   }
   if (odd) k_cells<Q, S, STAGE, 1><<<grid, block, 0, a.stream>>>(L);
   else k_cells<Q, S, STAGE, 0><<<grid, block, 0, a.stream>>>(L);

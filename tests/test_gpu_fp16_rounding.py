@@ -19,6 +19,7 @@ import torch
 
 from oracle import oracle as O
 from paper_2212_01617_amd import frelbm as F
+from paper_2212_01617_amd import synth
 
 from _pair import case_inputs, ensure_gpu_lib, field_errors, log, oracle_twin
 
@@ -114,6 +115,35 @@ def test_parity_with_the_oracle_at_the_fp16_bar():
     log("[parity] fp16_stochastic: " + " ".join(f"{k}={v:.2e}" for k, v in err.items()))
     # the same bars as round-to-nearest FP16 storage
     assert err["phi"] < 2.5e-5 and err["u"] < 1.5e-5 and err["rho"] < 1.6e-5
+
+
+def test_rollers_parity_with_the_oracle():
+    """The roller bounce-back stores through the stochastic rounding too:
+    the D2Q9 four-roller cell after 200 steps, against the oracle, beside
+    the same run rounded to nearest."""
+    n = 64
+    cs, signs = synth.four_roller_geometry(n, n, 8.0)
+    mask = synth.roller_mask((1, n, n), cs, 8.0)
+    om = 0.01 / 8.0
+    rollers = [((c[0], c[1], 0.0), s * om, 2, 8.0) for c, s in zip(cs, signs)]
+    phys = dict(A=3.07e-3, kappa=1.23e-2, tau_f=1.0, tau_g=1.15, M=5.26)
+    phi0, _, _ = case_inputs(0, (n, n, 1), radius=8, xi=2.0, noise=1e-4, seed=3)
+    ref = O.Lattice(O.make_params(0, (n, n, 1), rollers=[r[:3] for r in rollers], **phys), phi0, None, None, mask)
+    ref.step(200)
+    errs = {}
+    for sr in (False, True):
+        p = F.make_params(0, (n, n, 1), storage=F.FRE_FP16, rollers=rollers, stochastic_rounding=sr, **phys)
+        gpu = F.Lattice(p, phi0, None, None, mask)
+        gpu.step(200)
+        errs[sr] = field_errors(ref, gpu)
+        gpu.close()
+    for sr, err in errs.items():
+        log(f"[parity] rollers_d2q9_fp16{'_stochastic' if sr else ''}: "
+            + " ".join(f"{k}={v:.2e}" for k, v in err.items()))
+    # measured: phi 1.6e-5, u 5.9e-6, rho 6.2e-6 (round-to-nearest 1.4e-5,
+    # 4.7e-6, 5.5e-6); held at about 3x
+    e = errs[True]
+    assert e["phi"] < 5e-5 and e["u"] < 2e-5 and e["rho"] < 2e-5
 
 
 @pytest.mark.parametrize("kind,shape", [(0, (48, 40, 1)), (1, (24, 16, 12))])
