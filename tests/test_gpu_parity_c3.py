@@ -8,8 +8,9 @@
   R=6.25) after 2000 steps: every field, and the Taylor deformation D
   computed the same way from both phi fields, within 1%.
 * FP16 storage on the copy: the deviation of phi, u and D is stated.
-* FP16 storage on the full lattice, stepped as the benchmark steps it: the
-  deviation after 20 steps is stated.
+* FP16 storage on the full lattice (rounded to nearest, and stochastically),
+  stepped as the benchmark steps it: the deviation after 20 steps is
+  stated.
 """
 import sys
 import os
@@ -77,6 +78,19 @@ def test_full_size_c3_fp16_storage_error_stated(full_oracle):
     err = field_errors(full_oracle, gpu)
     log("[parity] c3_full_fp16_20: " + " ".join(f"{k}={v:.2e}" for k, v in err.items()))
     # stated error of FP16 storage after 20 steps on the full lattice
+    assert err["phi"] < 5e-5 and err["u"] < 2e-5 and err["rho"] < 2e-5
+    gpu.close()
+
+
+def test_full_size_c3_fp16_stochastic_rounding_error_stated(full_oracle):
+    """The benchmark's stochastic-rounding FP16 leg, in its launch
+    configuration, at the round-to-nearest FP16 bars."""
+    p, phi0, u0, meta = bench.workload(1, sr=True)
+    gpu = F.Lattice(p, phi0, None, u0, stream=torch.cuda.Stream())
+    gpu.autotune(3)
+    gpu.step(20)
+    err = field_errors(full_oracle, gpu)
+    log("[parity] c3_full_fp16_stochastic_20: " + " ".join(f"{k}={v:.2e}" for k, v in err.items()))
     assert err["phi"] < 5e-5 and err["u"] < 2e-5 and err["rho"] < 2e-5
     gpu.close()
 
