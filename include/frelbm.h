@@ -109,7 +109,7 @@ typedef struct fre_roller {
  *    (so checkpoints carry it).  Round-to-nearest repeats the same rounding
  *    error in every cell of a nearly uniform flow at every step; the
  *    stochastic rounding is unbiased, and long runs drift far less, for
- *    about 15% of the FP16 step.  Results stay deterministic (bitwise
+ *    about 10% of the FP16 step.  Results stay deterministic (bitwise
  *    reproducible, graph or not).
  *    Lattices with fp16_rounding = 1 are stepped alone (not in batches).
  *    Must be 0 with FP32 storage or a ternary lattice.

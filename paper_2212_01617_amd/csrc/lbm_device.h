@@ -232,24 +232,25 @@ __device__ __forceinline__ uint32_t sr_next(uint32_t x) {
   return x;
 }
 
-// v rounded to one of the two halves next to it, the upper one with
-// probability equal to v's distance from the lower one over their spacing,
-// for r uniform in [0, 2^32): unbiased, so a rounding error that
-// round-to-nearest would repeat in every cell and at every step (a nearly
-// uniform flow) averages out instead.  Where halves are normal (|v| >= 2^-14)
-// their grid keeps the top 10 of FP32's 23 mantissa bits: adding r's low 13
-// bits under them and clearing those bits rounds the magnitude up exactly
-// when the carry reaches the kept bits.  Below, the grid is the multiples of
-// 2^-24: v 2^24 (exact) is rounded to an integer, up when its fractional part
-// exceeds a uniform draw from r's top 24 bits.  Both are formed and one
-// selected (a branch here costs the collide a third of its occupancy).
+// v rounded to one of the two halves next to it, the one farther from zero
+// with probability equal to v's distance from the nearer-to-zero one over
+// their spacing, for r uniform in [0, 2^32): unbiased, so a rounding error
+// that round-to-nearest would repeat in every cell and at every step (a
+// nearly uniform flow) averages out instead.  Where halves are normal
+// (|v| >= 2^-14) their grid keeps the top 10 of FP32's 23 mantissa bits:
+// adding r's low 13 bits under them and clearing those bits rounds the
+// magnitude up exactly when the carry reaches the kept bits, with exactly
+// the right probability.  Below 2^-14 the halves are the multiples of 2^-24,
+// which is the normal grid of [2^-14, 2^-13): |v| is moved there by adding
+// 2^-14, rounded the same way, and moved back (exact).  That one add rounds
+// below 2^-37, so there the probability is right to 2^-14 of a step.
 // Magnitudes beyond the largest half become inf or nan, as a plain
 // conversion would make them inf.
 __device__ __forceinline__ float sr_half(float v, uint32_t r) {
-  const float tn = __uint_as_float((__float_as_uint(v) + (r & 0x1fffu)) & ~0x1fffu);
-  const float y = v * 0x1p24f, k = floorf(y);
-  const float ts = (k + ((float)(r >> 8) * 0x1p-24f < y - k ? 1.0f : 0.0f)) * 0x1p-24f;
-  return fabsf(v) >= 0x1p-14f ? tn : ts;
+  const float a = fabsf(v);
+  const float off = a < 0x1p-14f ? 0x1p-14f : 0.0f;
+  const float t = __uint_as_float((__float_as_uint(a + off) + (r & 0x1fffu)) & ~0x1fffu) - off;
+  return copysignf(t, v);
 }
 
 template <int Q, int S> struct Pops;
