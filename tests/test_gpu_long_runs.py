@@ -108,6 +108,6 @@ def test_shear_2d_40000_steps_fp16_stochastic(golden):
     err, rel = _run("shear_2d", golden, storage=F.FRE_FP16, sr=True)
     # unbiased rounding: the step-to-step repetition of the rounding error
     # that round-to-nearest integrates in this channel averages out.
-    # measured: phi 1.7e-3, u 4.9e-6, D 7.7e-5 relative (round-to-nearest:
+    # measured: phi 1.6e-3, u 4.5e-6, D 6.0e-5 relative (round-to-nearest:
     # 6.3e-2, 3.2e-4, 16%); held at about 3x
     assert err["phi"] < 5e-3 and err["u"] < 1.5e-5 and rel < 2.5e-4
