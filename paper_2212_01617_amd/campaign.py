@@ -145,13 +145,15 @@ def four_roller_run(cas, *, steps: int = 30000, every: int = 500, storage: int =
 
 def shear_history(*, radius: float = 25.0, xi: float = 2.0, shape=(256, 128, 128), Ca: float = 0.1,
                   Re: float = 0.5, Pe: float = 10.0, strain: float = 12.0, every: float = 0.5, storage: int = 0,
-                  log=None) -> dict:
+                  stochastic_rounding: bool = False, log=None) -> dict:
     """A 3D drop in simple shear (the validation of Sec. 3.1): D3Q19, walls
     normal to z moving at -+u_w, periodic x and y, a centred drop of radius
     `radius` with interface width `xi`.  Every `every` strain units the
     deformation D and inclination theta in the xz plane, the volume of
     {phi > 0} and its number of components are sampled, up to `strain`
-    strain units or until the drop has broken up (two or more components)."""
+    strain units or until the drop has broken up (two or more components).
+    FP16 storage may round its stores stochastically (far less drift over
+    long runs).  The launch shapes are tuned for the lattice first."""
     import math
 
     import numpy as np
@@ -167,9 +169,11 @@ def shear_history(*, radius: float = 25.0, xi: float = 2.0, shape=(256, 128, 128
     sh = (nz, ny, nx)
     phi0 = synth.droplet_phi(sh, radius, xi, noise=1e-4, seed=0)
     u0 = synth.shear_velocity(sh, dp.rate, axis_normal=2)
-    L = F.Lattice(F.make_params(F.FRE_D3Q19, shape, storage=storage, bc=(0, 0, 1), wall_u=wu, **dp.phys()),
+    L = F.Lattice(F.make_params(F.FRE_D3Q19, shape, storage=storage, bc=(0, 0, 1), wall_u=wu,
+                                stochastic_rounding=stochastic_rounding, **dp.phys()),
                   phi0, None, u0)
     del phi0, u0
+    L.autotune(4)
     per = max(1, int(round(every / dp.rate)))
     t, hist = 0, []
     while t * dp.rate < strain - 1e-9:
@@ -194,8 +198,8 @@ def shear_history(*, radius: float = 25.0, xi: float = 2.0, shape=(256, 128, 128
     outcome = "breakup" if hist and hist[-1]["components"] >= 2 else (
         "dissolved" if hist and hist[-1]["components"] == 0 else "cap")
     return {"radius": radius, "xi": xi, "R_over_xi": radius / xi, "shape": list(shape), "Ca": Ca, "Re": Re,
-            "Pe": Pe, "taylor_D": 35.0 / 32.0 * Ca, "rate": dp.rate, "M": dp.M, "outcome": outcome,
-            "history": hist}
+            "Pe": Pe, "taylor_D": 35.0 / 32.0 * Ca, "rate": dp.rate, "M": dp.M, "storage": storage,
+            "stochastic_rounding": bool(stochastic_rounding), "outcome": outcome, "history": hist}
 
 
 def main(argv=None):
@@ -218,10 +222,11 @@ def main(argv=None):
     ap.add_argument("--shape", default="256,128,128")
     ap.add_argument("--Ca", type=float, default=0.1)
     ap.add_argument("--strain", type=float, default=12.0)
+    ap.add_argument("--sr", action="store_true", help="with --storage 1: stochastic rounding of the stores")
     a = ap.parse_args(argv)
     if a.history:
         out = shear_history(radius=a.radius, xi=a.xi, shape=tuple(int(v) for v in a.shape.split(",")), Ca=a.Ca,
-                            Re=a.Re, Pe=a.Pe, strain=a.strain, storage=a.storage,
+                            Re=a.Re, Pe=a.Pe, strain=a.strain, storage=a.storage, stochastic_rounding=a.sr,
                             log=lambda line: print(line, file=sys.stderr, flush=True))
         print(json.dumps(out), flush=True)
         return
