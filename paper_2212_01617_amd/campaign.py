@@ -145,7 +145,7 @@ def four_roller_run(cas, *, steps: int = 30000, every: int = 500, storage: int =
 
 def shear_history(*, radius: float = 25.0, xi: float = 2.0, shape=(256, 128, 128), Ca: float = 0.1,
                   Re: float = 0.5, Pe: float = 10.0, strain: float = 12.0, every: float = 0.5, storage: int = 0,
-                  stochastic_rounding: bool = False, log=None) -> dict:
+                  stochastic_rounding: bool = False, tau_f: float = 1.0, log=None) -> dict:
     """A 3D drop in simple shear (the validation of Sec. 3.1): D3Q19, walls
     normal to z moving at -+u_w, periodic x and y, a centred drop of radius
     `radius` with interface width `xi`.  Every `every` strain units the
@@ -153,7 +153,9 @@ def shear_history(*, radius: float = 25.0, xi: float = 2.0, shape=(256, 128, 128
     {phi > 0} and its number of components are sampled, up to `strain`
     strain units or until the drop has broken up (two or more components).
     FP16 storage may round its stores stochastically (far less drift over
-    long runs).  The launch shapes are tuned for the lattice first."""
+    long runs).  The launch shapes are tuned for the lattice first.  A
+    larger tau_f (viscosity) at the same Re, Ca, Pe and Cahn number takes
+    proportionally fewer steps per strain unit."""
     import math
 
     import numpy as np
@@ -163,7 +165,7 @@ def shear_history(*, radius: float = 25.0, xi: float = 2.0, shape=(256, 128, 128
     from . import synth
     from .params import derive_params
     nx, ny, nz = shape
-    dp = derive_params(Re=Re, Ca=Ca, radius=radius, xi=xi, H=nz, Pe=Pe)
+    dp = derive_params(Re=Re, Ca=Ca, radius=radius, xi=xi, H=nz, Pe=Pe, tau_f=tau_f)
     wu = np.zeros((3, 2, 3))
     wu[2, 0, 0], wu[2, 1, 0] = -dp.wall_u, dp.wall_u
     sh = (nz, ny, nx)
@@ -198,7 +200,7 @@ def shear_history(*, radius: float = 25.0, xi: float = 2.0, shape=(256, 128, 128
     outcome = "breakup" if hist and hist[-1]["components"] >= 2 else (
         "dissolved" if hist and hist[-1]["components"] == 0 else "cap")
     return {"radius": radius, "xi": xi, "R_over_xi": radius / xi, "shape": list(shape), "Ca": Ca, "Re": Re,
-            "Pe": Pe, "taylor_D": 35.0 / 32.0 * Ca, "rate": dp.rate, "M": dp.M, "storage": storage,
+            "Pe": Pe, "tau_f": tau_f, "taylor_D": 35.0 / 32.0 * Ca, "rate": dp.rate, "M": dp.M, "storage": storage,
             "stochastic_rounding": bool(stochastic_rounding), "outcome": outcome, "history": hist}
 
 
@@ -223,10 +225,12 @@ def main(argv=None):
     ap.add_argument("--Ca", type=float, default=0.1)
     ap.add_argument("--strain", type=float, default=12.0)
     ap.add_argument("--sr", action="store_true", help="with --storage 1: stochastic rounding of the stores")
+    ap.add_argument("--tau-f", type=float, default=1.0, help="with --history: relaxation time of f")
     a = ap.parse_args(argv)
     if a.history:
         out = shear_history(radius=a.radius, xi=a.xi, shape=tuple(int(v) for v in a.shape.split(",")), Ca=a.Ca,
                             Re=a.Re, Pe=a.Pe, strain=a.strain, storage=a.storage, stochastic_rounding=a.sr,
+                            tau_f=a.tau_f,
                             log=lambda line: print(line, file=sys.stderr, flush=True))
         print(json.dumps(out), flush=True)
         return
