@@ -1103,6 +1103,7 @@ Inst inst_of(const fre_lattice *L, const void *base) {
   I.g0 = L->a.g0 ? rel(L->a.g0, base) : 0;
   I.mask = rel(L->a.mask, base);
   I.nbm = rel(L->a.nbm, base);
+  I.segf = rel(L->a.segf, base);
   I.M = rel(L->a.M, base);
   I.C = rel(L->a.C, base);
   I.P0 = L->a.P0 ? rel(L->a.P0, base) : 0;
@@ -1119,6 +1120,25 @@ void batch_reset_graph(fre_batch *B) {
   B->graph_ok = false;
 }
 
+// Work-list order for the XCDs.  The persistent cell kernels walk a class's
+// list grid-stride over a grid that is a multiple of 8 blocks, so item w
+// runs on XCD w % 8 (workgroups go to the XCDs round-robin, each with its own
+// L2).  Rows of tiles (one member, plane and tile row: the tiles along x)
+// are dealt to the 8 XCDs in turn, and the list takes the XCDs' items in
+// turn, so that a tile's x neighbours run on its own XCD and the cache lines
+// that an x-shifted access shares across a tile edge are fetched once.
+// Members of different widths can leave the XCDs' shares unequal; once
+// some run out, the remaining items keep their order but not their XCD.
+constexpr int NXCD_HOST = 8;
+
+void xcd_interleave(std::vector<int4> (&rows)[NXCD_HOST], std::vector<int4> &out) {
+  size_t most = 0;
+  for (const auto &q : rows) most = std::max(most, q.size());
+  for (size_t j = 0; j < most; ++j)
+    for (const auto &q : rows)
+      if (j < q.size()) out.push_back(q[j]);
+}
+
 // Rebuild and upload the instance table and the work lists, grouped by
 // class; the ranges tell each class's persistent kernels what to walk.
 fre_status batch_rebuild(fre_batch *B) {
@@ -1131,17 +1151,23 @@ fre_status batch_rebuild(fre_batch *B) {
   for (int cls = 0; cls < N_BATCH_CLASSES; ++cls) {
     B->h_range[4 * cls + 0] = (int)B->h_work.size();
     B->h_range[4 * cls + 2] = (int)B->h_fill.size();
+    std::vector<int4> rows_of_xcd[NXCD_HOST];
+    int nrows = 0;
     for (size_t k = 0; k < B->slot.size(); ++k) {
       fre_lattice *L = B->slot[k];
       if (!L || batch_class(L->a.q, L->a.storage) != cls) continue;
       classes |= 1u << cls;
       B->h_inst[k] = inst_of(L, B->base);
       const Geom &G = L->a.G;
+      const int gx = (G.ex + 63) / 64;
       for (int z = 0; z < G.ez; ++z)
-        for (int by = 0; by < (G.ey + B->rows - 1) / B->rows; ++by)
-          for (int bx = 0; bx < (G.ex + 63) / 64; ++bx) B->h_work.push_back(make_int4((int)k, bx, by, z));
+        for (int by = 0; by < (G.ey + B->rows - 1) / B->rows; ++by) {
+          auto &q = rows_of_xcd[nrows++ % NXCD_HOST];
+          for (int bx = 0; bx < gx; ++bx) q.push_back(make_int4((int)k, bx, by, z));
+        }
       for (int s : L->fill_host) B->h_fill.push_back(make_int2((int)k, s));
     }
+    xcd_interleave(rows_of_xcd, B->h_work);
     B->h_range[4 * cls + 1] = (int)B->h_work.size() - B->h_range[4 * cls + 0];
     B->h_range[4 * cls + 3] = (int)B->h_fill.size() - B->h_range[4 * cls + 2];
   }

@@ -115,7 +115,7 @@ template <int Q, int S> struct LatView {
 struct Inst {
   Geom G;
   Phys ph;
-  long long f, g, g0, mask, nbm, M, C, P0, PU, PD, XE, fill;
+  long long f, g, g0, mask, nbm, segf, M, C, P0, PU, PD, XE, fill;
   int n_fill;
 };
 

@@ -909,7 +909,7 @@ __device__ __forceinline__ LatView<Q, S> view_of(char *base, const Inst &I) {
   LatView<Q, S> L;
   L.P = pops_of<Q, S>(base + I.f, base + I.g, (float *)(base + I.g0));
   L.nbm = (const uint32_t *)(base + I.nbm); L.mask = (const uint8_t *)(base + I.mask);
-  L.segf = nullptr;  // a batch work item need not cover one segment per wave
+  L.segf = (const uint8_t *)(base + I.segf);  // a work item is a 64-wide tile: one segment per wave
   L.M = (float2 *)(base + I.M); L.C = (float4 *)(base + I.C);
   L.P0 = (float2 *)(base + I.P0); L.PU = (float2 *)(base + I.PU); L.PD = (float2 *)(base + I.PD);
   L.XE = (float2 *)(base + I.XE);
