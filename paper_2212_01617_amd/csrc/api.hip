@@ -226,11 +226,12 @@ struct fre_batch {
   int max_slots, cap_work, cap_fill;
   Inst *d_inst;
   int4 *d_work;
+  int4 *d_cols;  // potential columns
   int2 *d_fill;
-  int *d_range;  // [N_BATCH_CLASSES][cells start, n, fills start, n]
+  int *d_range;  // [N_BATCH_CLASSES][BATCH_RANGE]: see BatchArgs
   std::vector<fre_lattice *> slot;
   std::vector<Inst> h_inst;
-  std::vector<int4> h_work;
+  std::vector<int4> h_work, h_cols;
   std::vector<int2> h_fill;
   std::vector<int> h_range;
   int parity;         // common AA parity of the members
@@ -1067,7 +1068,7 @@ void fre_lattice_destroy(fre_lattice *L) {
 namespace {
 
 struct BatchPlan {
-  size_t o_inst, o_work, o_fill, o_range, total;
+  size_t o_inst, o_work, o_cols, o_fill, o_range, total;
 };
 
 BatchPlan batch_plan(int max_slots, int64_t max_work, int64_t max_fill) {
@@ -1076,8 +1077,9 @@ BatchPlan batch_plan(int max_slots, int64_t max_work, int64_t max_fill) {
   auto take = [&](size_t b) { size_t at = o; o = align_up(o + b, kAlign); return at; };
   P.o_inst = take((size_t)max_slots * sizeof(Inst));
   P.o_work = take((size_t)max_work * sizeof(int4));
+  P.o_cols = take((size_t)max_work * sizeof(int4));  // a column holds at least one tile
   P.o_fill = take((size_t)max_fill * sizeof(int2));
-  P.o_range = take(4 * N_BATCH_CLASSES * sizeof(int));
+  P.o_range = take(BATCH_RANGE * N_BATCH_CLASSES * sizeof(int));
   P.total = o;
   return P;
 }
@@ -1145,31 +1147,50 @@ fre_status batch_rebuild(fre_batch *B) {
   HIP_TRY(hipStreamSynchronize(B->stream));
   B->h_inst.assign(B->slot.size(), Inst{});
   B->h_work.clear();
+  B->h_cols.clear();
   B->h_fill.clear();
-  B->h_range.assign(4 * N_BATCH_CLASSES, 0);
+  B->h_range.assign(BATCH_RANGE * N_BATCH_CLASSES, 0);
   unsigned classes = 0;
   for (int cls = 0; cls < N_BATCH_CLASSES; ++cls) {
-    B->h_range[4 * cls + 0] = (int)B->h_work.size();
-    B->h_range[4 * cls + 2] = (int)B->h_fill.size();
-    std::vector<int4> rows_of_xcd[NXCD_HOST];
-    int nrows = 0;
+    int *rg = &B->h_range[BATCH_RANGE * cls];
+    rg[0] = (int)B->h_work.size();
+    rg[2] = (int)B->h_fill.size();
+    rg[4] = (int)B->h_cols.size();
+    std::vector<int4> rows_of_xcd[NXCD_HOST], cols_of_xcd[NXCD_HOST];
+    int nrows = 0, ncolrows = 0;
+    // planes per potential column: about 8 columns per CU over the class,
+    // as the single-lattice potential's grid, at most 16 planes
+    int64_t column_planes = 0;
+    for (fre_lattice *L : B->slot)
+      if (L && batch_class(L->a.q, L->a.storage) == cls)
+        column_planes += (int64_t)((L->a.G.ex + 63) / 64) * ((L->a.G.ey + B->rows - 1) / B->rows) * L->a.G.ez;
+    const int64_t target = 8 * (int64_t)B->ncu;
+    const int tz = (int)std::max<int64_t>(1, std::min<int64_t>(16, (column_planes + target - 1) / target));
+    rg[6] = tz;
     for (size_t k = 0; k < B->slot.size(); ++k) {
       fre_lattice *L = B->slot[k];
       if (!L || batch_class(L->a.q, L->a.storage) != cls) continue;
       classes |= 1u << cls;
       B->h_inst[k] = inst_of(L, B->base);
       const Geom &G = L->a.G;
-      const int gx = (G.ex + 63) / 64;
+      const int gx = (G.ex + 63) / 64, gy = (G.ey + B->rows - 1) / B->rows;
       for (int z = 0; z < G.ez; ++z)
-        for (int by = 0; by < (G.ey + B->rows - 1) / B->rows; ++by) {
+        for (int by = 0; by < gy; ++by) {
           auto &q = rows_of_xcd[nrows++ % NXCD_HOST];
+          for (int bx = 0; bx < gx; ++bx) q.push_back(make_int4((int)k, bx, by, z));
+        }
+      for (int z = 0; z < G.ez; z += tz)
+        for (int by = 0; by < gy; ++by) {
+          auto &q = cols_of_xcd[ncolrows++ % NXCD_HOST];
           for (int bx = 0; bx < gx; ++bx) q.push_back(make_int4((int)k, bx, by, z));
         }
       for (int s : L->fill_host) B->h_fill.push_back(make_int2((int)k, s));
     }
     xcd_interleave(rows_of_xcd, B->h_work);
-    B->h_range[4 * cls + 1] = (int)B->h_work.size() - B->h_range[4 * cls + 0];
-    B->h_range[4 * cls + 3] = (int)B->h_fill.size() - B->h_range[4 * cls + 2];
+    xcd_interleave(cols_of_xcd, B->h_cols);
+    rg[1] = (int)B->h_work.size() - rg[0];
+    rg[3] = (int)B->h_fill.size() - rg[2];
+    rg[5] = (int)B->h_cols.size() - rg[4];
   }
   if ((int64_t)B->h_work.size() > B->cap_work || (int64_t)B->h_fill.size() > B->cap_fill)
     return fail(FRE_ENOMEM, "batch work lists exceed their capacity (%zu/%d cells, %zu/%d fills)",
@@ -1178,9 +1199,11 @@ fre_status batch_rebuild(fre_batch *B) {
     HIP_TRY(hipMemcpyAsync(B->d_inst, B->h_inst.data(), B->h_inst.size() * sizeof(Inst), hipMemcpyHostToDevice, B->stream));
   if (!B->h_work.empty())
     HIP_TRY(hipMemcpyAsync(B->d_work, B->h_work.data(), B->h_work.size() * sizeof(int4), hipMemcpyHostToDevice, B->stream));
+  if (!B->h_cols.empty())
+    HIP_TRY(hipMemcpyAsync(B->d_cols, B->h_cols.data(), B->h_cols.size() * sizeof(int4), hipMemcpyHostToDevice, B->stream));
   if (!B->h_fill.empty())
     HIP_TRY(hipMemcpyAsync(B->d_fill, B->h_fill.data(), B->h_fill.size() * sizeof(int2), hipMemcpyHostToDevice, B->stream));
-  HIP_TRY(hipMemcpyAsync(B->d_range, B->h_range.data(), 4 * N_BATCH_CLASSES * sizeof(int), hipMemcpyHostToDevice, B->stream));
+  HIP_TRY(hipMemcpyAsync(B->d_range, B->h_range.data(), BATCH_RANGE * N_BATCH_CLASSES * sizeof(int), hipMemcpyHostToDevice, B->stream));
   HIP_TRY(hipStreamSynchronize(B->stream));
   if (classes != B->classes) batch_reset_graph(B);  // the graph launches one sequence per class
   B->classes = classes;
@@ -1192,10 +1215,12 @@ BatchArgs batch_args(const fre_batch *B) {
   b.base = (char *)B->base;
   b.inst = B->d_inst;
   b.work = B->d_work;
+  b.cols = B->d_cols;
   b.fill = B->d_fill;
   b.range = B->d_range;
   b.grid_cells = B->grid_cells;
   b.grid_fill = B->grid_fill;
+  b.grid_cols = 8 * B->ncu;
   b.rows = B->rows;
   b.stream = B->stream;
   return b;
@@ -1241,6 +1266,7 @@ fre_status fre_batch_create(void *device_buf, size_t bytes, void *hip_stream, in
   B->cap_fill = (int)max_fill;
   B->d_inst = (Inst *)(B->base + P.o_inst);
   B->d_work = (int4 *)(B->base + P.o_work);
+  B->d_cols = (int4 *)(B->base + P.o_cols);
   B->d_fill = (int2 *)(B->base + P.o_fill);
   B->d_range = (int *)(B->base + P.o_range);
   B->slot.assign(max_slots, nullptr);

@@ -126,15 +126,19 @@ template <> __host__ __device__ inline Pops<19, 0> pops_of<19, 0>(void *f, void 
 template <> __host__ __device__ inline Pops<9, 1> pops_of<9, 1>(void *f, void *g, float *g0) { return Pops<9, 1>{(__half *)f, (__half *)g, g0}; }
 template <> __host__ __device__ inline Pops<19, 1> pops_of<19, 1>(void *f, void *g, float *g0) { return Pops<19, 1>{(__half *)f, (__half *)g, g0}; }
 
-// Device tables of a batch.  range[4*cls + 0..1]: start and length of the
-// class's cell work items; range[4*cls + 2..3]: the same for fill items.
+// Device tables of a batch.  range[BATCH_RANGE*cls + 0..1]: start and
+// length of the class's cell work items; + 2..3: the same for fill items;
+// + 4..5: the same for potential columns, + 6: planes per column.
+constexpr int BATCH_RANGE = 8;
 struct BatchArgs {
   char *base;  // origin of the Inst offsets
   const Inst *inst;
   const int4 *work;
+  const int4 *cols;  // potential columns (slot, block-x, block-y, first plane)
   const int2 *fill;
   const int *range;
   int grid_cells, grid_fill;
+  int grid_cols;  // potential columns: 8 blocks per CU (the LDS ring fits 10)
   int rows;  // rows of 64 cells per work item (and per block)
   hipStream_t stream;
 };

@@ -839,19 +839,20 @@ __global__ __launch_bounds__(256) void k_fill(LatView<Q, S> L) {
 // keeps three planes of M (with a one-cell halo in x and y) in a ring, so
 // each M value is read from memory about once per block instead of once per
 // neighbour.  Same arithmetic as stage_potential.
+constexpr int RING_W = BX + 2;
+using PotRing = float2[3][MAX_ROWS + 2][RING_W];
+
+// The potential of planes [z0, z1) of the 64 x blockDim.y column (bx, by);
+// every thread of the block takes part (barriers), and the ring is free
+// again on return.
 template <int Q, int S>
-__global__ __launch_bounds__(BX *MAX_ROWS) void k_potential_zm(LatView<Q, S> L, int tz) {
+__device__ __forceinline__ void potential_column(const LatView<Q, S> &L, PotRing &ring, int bx, int by, int z0,
+                                                 int z1) {
   using V = VSet<Q>;
-  constexpr int HW = BX + 2;
-  __shared__ float2 ring[3][MAX_ROWS + 2][HW];
+  constexpr int HW = RING_W;
   const Geom &G = L.G;
   const int rows = (int)blockDim.y;
-  uint32_t ubx, ur;
-  tile_of_block(L.tm, blockIdx.x, ubx, ur);
-  const uint32_t uch = udiv(ur, L.tm.dgy);
-  const int bx = (int)ubx, by = (int)(ur - uch * (uint32_t)L.tm.gy), ch = (int)uch;
   const int xlo = bx * BX, ylo = by * rows;
-  const int z0 = ch * tz, z1 = min(z0 + tz, G.ez);
   const int w = min(BX, G.ex - xlo), h = min(rows, G.ey - ylo);  // cells of the tile on the lattice
   const int tid = threadIdx.y * BX + threadIdx.x, nth = BX * rows;
   const int hcells = (rows + 2) * HW;
@@ -897,6 +898,16 @@ __global__ __launch_bounds__(BX *MAX_ROWS) void k_potential_zm(LatView<Q, S> L, 
   }
 }
 
+template <int Q, int S>
+__global__ __launch_bounds__(BX *MAX_ROWS) void k_potential_zm(LatView<Q, S> L, int tz) {
+  __shared__ PotRing ring;
+  uint32_t ubx, ur;
+  tile_of_block(L.tm, blockIdx.x, ubx, ur);
+  const uint32_t uch = udiv(ur, L.tm.dgy);
+  const int by = (int)(ur - uch * (uint32_t)L.tm.gy), z0 = (int)uch * tz;
+  potential_column<Q, S>(L, ring, (int)ubx, by, z0, min(z0 + tz, L.G.ez));
+}
+
 // ---------------------------------------------------------------------------
 // Batched persistent kernels: a fixed grid walks a device-side work list of
 // (slot, block-x, block-y, z) items (or (slot, cell) fill items) for the
@@ -934,6 +945,21 @@ __global__ __launch_bounds__(BX *MAX_ROWS) void k_batch_cells(char *base, const 
     } else if (in) {
       run_stage<Q, S, STAGE, ODD>(L, x, y, z);
     }
+  }
+}
+
+// The batch potential: z-marching columns (slot, block-x, block-y, first
+// plane) of range[2] planes each, as k_potential_zm marches them.
+template <int Q, int S>
+__global__ __launch_bounds__(BX *MAX_ROWS) void k_batch_potential(char *base, const Inst *__restrict__ inst,
+                                                               const int4 *__restrict__ cols,
+                                                               const int *__restrict__ range) {
+  __shared__ PotRing ring;
+  const int start = range[0], n = range[1], tz = range[2];
+  for (int w = blockIdx.x; w < n; w += gridDim.x) {
+    const int4 it = cols[start + w];
+    const LatView<Q, S> L = view_of<Q, S>(base, inst[it.x]);
+    potential_column<Q, S>(L, ring, it.y, it.z, it.w, min(it.w + tz, L.G.ez));
   }
 }
 
@@ -1633,14 +1659,14 @@ void launch_read_pops(const LaunchArgs &a, int odd, float *out, long long c0, in
 // [start, n]).
 template <int Q, int S>
 static void batch_step_impl(const BatchArgs &b, int cls, int odd) {
-  const int *rc = b.range + 4 * cls, *rf = rc + 2;
+  const int *rc = b.range + BATCH_RANGE * cls, *rf = rc + 2, *rp = rc + 4;
   const dim3 bl(BX, b.rows, 1);
   if (!ByProduct<S>::on) {
     if (odd) k_batch_cells<Q, S, ST_MOMENTS, 1><<<b.grid_cells, bl, 0, b.stream>>>(b.base, b.inst, b.work, rc);
     else k_batch_cells<Q, S, ST_MOMENTS, 0><<<b.grid_cells, bl, 0, b.stream>>>(b.base, b.inst, b.work, rc);
   }
   k_batch_fill<Q, S, 0><<<b.grid_fill, 256, 0, b.stream>>>(b.base, b.inst, b.fill, rf);
-  k_batch_cells<Q, S, ST_POTENTIAL, 0><<<b.grid_cells, bl, 0, b.stream>>>(b.base, b.inst, b.work, rc);
+  k_batch_potential<Q, S><<<b.grid_cols, bl, 0, b.stream>>>(b.base, b.inst, b.cols, rp);
   k_batch_fill<Q, S, 1><<<b.grid_fill, 256, 0, b.stream>>>(b.base, b.inst, b.fill, rf);
   if (odd) k_batch_cells<Q, S, ST_COLLIDE, 1><<<b.grid_cells, bl, 0, b.stream>>>(b.base, b.inst, b.work, rc);
   else k_batch_cells<Q, S, ST_COLLIDE, 0><<<b.grid_cells, bl, 0, b.stream>>>(b.base, b.inst, b.work, rc);
