@@ -292,7 +292,9 @@ void fre_lattice_destroy(fre_lattice *L);
 
 /* Device bytes of a batch's tables for max_slots lattices, max_work cell
  * work items and max_fill solid-boundary items in total (see
- * fre_lattice_batch_needs).  No device work. */
+ * fre_lattice_batch_needs): the instance table, the cell-tile list, the
+ * list of potential columns (at most one per tile) and the fill list.  No
+ * device work. */
 fre_status fre_batch_footprint(int32_t max_slots, int64_t max_work, int64_t max_fill, size_t *bytes);
 
 /* Work items a lattice adds to a batch: cell tiles of 64 x 4 cells and
