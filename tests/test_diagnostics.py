@@ -171,3 +171,18 @@ def test_steady_tracker():
     assert steady_at is not None and 2.0 <= steady_at <= 6.0
     o = Dg.SteadyTracker(dt=0.1, window=2.0, tol=5e-4)
     assert not any(o.add(0.1 * (k + 1), 0.2 + 1e-3 * math.sin(k)) for k in range(60))
+
+
+def test_plane_sum_moments_equal_the_direct_form():
+    """centred_moments (from the three plane sums) against second_moments of
+    the rolled indicator, on random fields and periodicities, 2D and 3D."""
+    rng = np.random.default_rng(11)
+    for trial in range(30):
+        nz = 1 if trial % 3 == 0 else int(rng.integers(2, 30))
+        ny, nx = (int(v) for v in rng.integers(2, 40, 2))
+        C = rng.uniform(0.0, 1.0, (nz, ny, nx)) ** 4
+        per = tuple(bool(v) for v in rng.integers(0, 2, 3))
+        c0, T0 = Dg.second_moments(Dg.centred(C, per)[0])
+        c1, T1 = Dg.centred_moments(C, per)
+        assert np.allclose(c1, c0, rtol=0, atol=1e-9 * (1 + np.abs(c0).max()))
+        assert np.allclose(T1, T0, rtol=0, atol=1e-9 * np.abs(T0).max())
