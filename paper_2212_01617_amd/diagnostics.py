@@ -199,8 +199,10 @@ def components(phi: np.ndarray, periodic=(True, True, True), min_cells: int = 8)
             if ra != rb:
                 parent[max(ra, rb)] = min(ra, rb)
     roots = np.array([find(i) for i in range(n + 1)])
-    sizes = np.bincount(roots[lab.ravel()], minlength=n + 1)
-    sizes[0] = 0
+    # cells per label, then per merged component (label 0 is the matrix)
+    per_label = np.bincount(lab.ravel(), minlength=n + 1)
+    per_label[0] = 0
+    sizes = np.bincount(roots, weights=per_label, minlength=n + 1).astype(np.int64)
     out = sorted((int(s) for s in sizes if s >= min_cells), reverse=True)
     return out
 
