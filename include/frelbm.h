@@ -181,7 +181,10 @@ fre_status fre_consistent_init(fre_lattice *L, const double *phi0, const double 
 /* Replace the physical parameters (free energy, tau, M, wall and roller
  * velocities; kappa3, M3, tau_h of a ternary lattice) of an existing
  * lattice; shape, storage, bc, the roller count and the ternary flag must
- * not change (FRE_EINVAL).  Takes effect for the next step. */
+ * not change (FRE_EINVAL), and a batch member refuses (FRE_ESTATE).  Takes
+ * effect for the next step: steps already queued on the lattice's stream run
+ * with the old parameters (the call waits for them when it drops the
+ * lattice's captured graph).  On any error the lattice is left unchanged. */
 fre_status fre_set_params(fre_lattice *L, const fre_params *p);
 
 /* Advance n >= 0 time steps (Algorithm 1 at every fluid node, then

@@ -246,8 +246,15 @@ struct fre_batch {
 
 namespace {
 
+// Launches of the captured graph may still be queued on the stream, and the
+// executable holds their kernel arguments: destroying it before they have
+// run lets them read whatever reuses that memory (for example the arguments
+// of the next graph, with new parameters), so the stream is drained first.
 void reset_graph(fre_lattice *L) {
-  if (L->graph_ok) (void)hipGraphExecDestroy(L->graph);
+  if (L->graph_ok) {
+    (void)hipStreamSynchronize(L->a.stream);
+    (void)hipGraphExecDestroy(L->graph);
+  }
   L->graph_ok = false;
 }
 
@@ -1117,8 +1124,12 @@ Inst inst_of(const fre_lattice *L, const void *base) {
   return I;
 }
 
+// As reset_graph: the batch's queued graph launches finish first.
 void batch_reset_graph(fre_batch *B) {
-  if (B->graph_ok) (void)hipGraphExecDestroy(B->graph);
+  if (B->graph_ok) {
+    (void)hipStreamSynchronize(B->stream);
+    (void)hipGraphExecDestroy(B->graph);
+  }
   B->graph_ok = false;
 }
 

@@ -1,0 +1,159 @@
+"""fre_set_params on the GPU: the physical parameters of a lattice replaced
+between steps -- the free energy and mobility (Sec. 2.2), the relaxation
+times, and the moving-wall and roller velocities that enter through the
+bounce-back (Sec. 2.3) -- take effect at the next step, also on the captured
+graph path.
+
+The oracle side continues the same way: an oracle lattice with the old
+parameters is stepped to the switch, and one with the new parameters takes
+over its populations (its state is exactly the post-stream populations) and
+is stepped on.  Every field and population is compared with the GPU run at
+the FP32 bar (FP16 storage at the stated FP16 bar)."""
+import numpy as np
+import pytest
+import torch
+
+from paper_2212_01617_amd import frelbm as F
+from paper_2212_01617_amd import synth
+
+from _pair import FP16_BAR, case_inputs, ensure_gpu_lib, field_errors, log, oracle_twin, pop_errors
+
+pytestmark = pytest.mark.gpu
+
+TOL = {"rho": 1e-5, "phi": 1e-5, "u": 1e-5, "mu_rho": 1e-6, "mu_phi": 1e-6, "P": 1e-6}
+
+
+@pytest.fixture(scope="module", autouse=True)
+def _lib():
+    assert torch.cuda.is_available(), "GPU tests need a GPU"
+    ensure_gpu_lib()
+
+
+def _oracle_switch(p1, p2, n1, n2, phi0, rho0=None, u0=None, mask=None):
+    a = oracle_twin(p1, phi0, rho0, u0, mask).step(n1)
+    f, g = a.populations()
+    b = oracle_twin(p2, phi0, rho0, u0, mask)
+    b.set_populations(f, g)
+    return b.step(n2)
+
+
+def _compare(tag, ref, gpu, storage):
+    err = field_errors(ref, gpu)
+    pf, pg = pop_errors(ref, gpu)
+    log(f"[parity] {tag}: " + " ".join(f"{k}={v:.2e}" for k, v in err.items()) + f" f={pf:.2e} g={pg:.2e}")
+    if storage == F.FRE_FP32:
+        for k, v in TOL.items():
+            assert err[k] < v, (tag, k, err[k])
+        assert pf < 1e-5 and pg < 1e-5, (tag, pf, pg)
+    else:
+        for k, v in FP16_BAR.items():
+            assert err[k] < v, (tag, k, err[k])
+    return err
+
+
+def _walls(axis, lo, hi):
+    wu = np.zeros((3, 2, 3))
+    wu[axis, 0, 0] = lo
+    wu[axis, 1, 0] = hi
+    return wu
+
+
+@pytest.mark.parametrize("storage", [F.FRE_FP32, F.FRE_FP16])
+def test_shear_d2q9_new_wall_speed_free_energy_and_relaxation(storage):
+    # 70 x 24: two 64-wide blocks, the second ragged; 60 steps with the first
+    # parameters (graph path), then 61 with the second (odd: the AA parity
+    # and the graph's two-step pairing both change at the switch)
+    shape = (70, 24, 1)
+    phi0, _, u0 = case_inputs(0, shape, radius=7, xi=2.0, noise=1e-4, seed=21, shear=(2 * 0.008 / 24, 1))
+    p1 = F.make_params(0, shape, storage=storage, bc=(0, 1, 0), wall_u=_walls(1, -0.008, 0.008),
+                       A=2e-3, kappa=8e-3, tau_f=1.0, tau_g=1.0, M=4.0)
+    p2 = F.make_params(0, shape, storage=storage, bc=(0, 1, 0), wall_u=_walls(1, 0.012, -0.004),
+                       kappa1=0.012, kappa2=0.007, alpha=1.6, tau_f=0.8, tau_g=1.3, M=2.5)
+    gpu = F.Lattice(p1, phi0, None, u0, stream=torch.cuda.Stream())
+    gpu.step(60)
+    gpu.set_params(p2)
+    gpu.step(61)
+    ref = _oracle_switch(p1, p2, 60, 61, phi0, None, u0)
+    _compare(f"set_params_shear_d2q9_s{storage}", ref, gpu, storage)
+    gpu.close()
+
+
+def test_shear_d3q19_walls_z_new_wall_speed():
+    shape = (40, 24, 20)
+    phi0, _, u0 = case_inputs(1, shape, radius=6, xi=2.0, shear=(2 * 0.017 / 20, 2))
+    # both sets in the stable range of the Cahn-Hilliard update (with
+    # tau_g = 1.25 at M = 5.26 the oracle itself diverges within 80 steps)
+    kw = dict(storage=F.FRE_FP32, bc=(0, 0, 1))
+    p1 = F.make_params(1, shape, wall_u=_walls(2, -0.017, 0.017), A=5.89e-3, kappa=2.36e-2,
+                       tau_f=1.0, tau_g=1.75, M=5.26, **kw)
+    p2 = F.make_params(1, shape, wall_u=_walls(2, -0.03, 0.01), A=4.5e-3, kappa=1.8e-2,
+                       tau_f=0.9, tau_g=1.5, M=3.0, **kw)
+    gpu = F.Lattice(p1, phi0, None, u0, stream=torch.cuda.Stream())
+    gpu.step(40)
+    gpu.set_params(p2)
+    gpu.step(40)
+    ref = _oracle_switch(p1, p2, 40, 40, phi0, None, u0)
+    _compare("set_params_shear_d3q19", ref, gpu, F.FRE_FP32)
+    gpu.close()
+
+
+def test_rollers_d2q9_new_roller_speed():
+    n = 64
+    cs, signs = synth.four_roller_geometry(n, n, 8.0)
+    mask = synth.roller_mask((1, n, n), cs, 8.0)
+    phi0, _, _ = case_inputs(0, (n, n, 1), radius=8, xi=2.0, noise=1e-4, seed=3)
+    kw = dict(storage=F.FRE_FP32, A=3.07e-3, kappa=1.23e-2, tau_f=1.0, tau_g=1.15, M=5.26)
+
+    def rollers(om):
+        return [((c[0], c[1], 0.0), s * om, 2, 8.0) for c, s in zip(cs, signs)]
+
+    p1 = F.make_params(0, (n, n, 1), rollers=rollers(0.01 / 8.0), **kw)
+    p2 = F.make_params(0, (n, n, 1), rollers=rollers(-0.006 / 8.0), **kw)
+    gpu = F.Lattice(p1, phi0, None, None, mask, stream=torch.cuda.Stream())
+    gpu.step(100)
+    gpu.set_params(p2)
+    gpu.step(100)
+    ref = _oracle_switch(p1, p2, 100, 100, phi0, None, None, mask)
+    _compare("set_params_rollers_d2q9", ref, gpu, F.FRE_FP32)
+    gpu.close()
+
+
+def test_refused_changes_leave_the_lattice_as_it_was():
+    shape = (40, 16, 1)
+    phi0, _, _ = case_inputs(0, shape, radius=5, xi=1.5, noise=1e-4, seed=8)
+    kw = dict(A=0.04, kappa=0.09, tau_f=1.0, tau_g=1.0, M=0.1)
+    p1 = F.make_params(0, shape, **kw)
+    gpu = F.Lattice(p1, phi0, stream=torch.cuda.Stream())
+    gpu.step(20)
+    bad = [
+        F.make_params(0, (48, 16, 1), **kw),                                  # shape
+        F.make_params(0, shape, storage=F.FRE_FP16, **kw),                    # storage
+        F.make_params(0, shape, bc=(0, 1, 0), **kw),                          # boundary conditions
+        F.make_params(0, shape, A=0.04, kappa=0.09, tau_f=0.5, tau_g=1.0, M=0.1),   # tau_f <= 1/2
+        F.make_params(0, shape, A=0.04, kappa=0.09, tau_f=1.0, tau_g=1.0, M=-0.1),  # M <= 0
+    ]
+    for p in bad:
+        with pytest.raises(F.FreError) as ei:
+            gpu.set_params(p)
+        assert ei.value.status == F.FRE_EINVAL
+    gpu.step(21)
+    ref = oracle_twin(p1, phi0).step(41)
+    _compare("set_params_refused", ref, gpu, F.FRE_FP32)
+    gpu.close()
+
+
+def test_batch_member_refuses_new_parameters():
+    shape = (40, 16, 1)
+    phi0, _, _ = case_inputs(0, shape, radius=5, xi=1.5, noise=1e-4, seed=9)
+    p = F.make_params(0, shape, A=0.04, kappa=0.09, tau_f=1.0, tau_g=1.0, M=0.1)
+    s = torch.cuda.Stream()
+    gpu = F.Lattice(p, phi0, stream=s)
+    w, f = F.Batch.needs(gpu)
+    b = F.Batch(max_slots=2, max_work=w, max_fill=f, stream=s)
+    slot = b.add(gpu)
+    with pytest.raises(F.FreError) as ei:
+        gpu.set_params(F.make_params(0, shape, A=0.04, kappa=0.09, tau_f=0.9, tau_g=1.0, M=0.1))
+    assert ei.value.status == F.FRE_ESTATE
+    b.remove(slot)
+    b.close()
+    gpu.close()
