@@ -1000,3 +1000,18 @@ void or3_get_populations(const or_state *s, double *f_out, double *g_out,
       h_out[(long)i * N + u] = s->kind[e] == OR_FLUID ? s->h[e * s->q + i] : 0.0;
   }
 }
+
+/* Replace the ternary populations of the fluid cells (layout [q][N] each,
+ * as or3_get_populations); solid cells keep theirs.  The state of a ternary
+ * lattice between steps is exactly these post-stream populations, so a
+ * lattice given another's populations continues that run. */
+void or3_set_populations(or_state *s, const double *f_in, const double *g_in,
+                         const double *h_in) {
+  or_set_populations(s, f_in, g_in);
+  long N = (long)s->p.nx * s->p.ny * s->p.nz;
+  for (long u = 0; u < N; ++u) {
+    long e = or_user_to_ext(s, u);
+    if (s->kind[e] != OR_FLUID) continue;
+    for (int i = 0; i < s->q; ++i) s->h[e * s->q + i] = h_in[(long)i * N + u];
+  }
+}

@@ -93,6 +93,7 @@ def lib():
         L.or3_step.argtypes = [C.c_void_p, C.c_long]
         L.or3_observe.argtypes = [C.c_void_p, dp]
         L.or3_get_populations.argtypes = [C.c_void_p, dp, dp, dp]
+        L.or3_set_populations.argtypes = [C.c_void_p, dp, dp, dp]
         _lib = L
     return _lib
 
@@ -322,3 +323,7 @@ class Lattice3:
         h = np.zeros(self.q * self.N)
         lib().or3_get_populations(self._h, _dp(f), _dp(g), _dp(h))
         return tuple(a.reshape(self.q, *self.shape) for a in (f, g, h))
+
+    def set_populations(self, f, g, h):
+        f, g, h = (np.ascontiguousarray(np.asarray(a, np.float64).reshape(-1)) for a in (f, g, h))
+        lib().or3_set_populations(self._h, _dp(f), _dp(g), _dp(h))

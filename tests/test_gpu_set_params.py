@@ -157,3 +157,39 @@ def test_batch_member_refuses_new_parameters():
     b.remove(slot)
     b.close()
     gpu.close()
+
+
+def test_ternary_new_kappa3_mobility_and_relaxation():
+    # a ternary lattice (third order parameter psi with population h): the
+    # new kappa3, psi's mobility M3 and relaxation time tau_h, phi's tau_g and
+    # the wall speed take effect together
+    from oracle import oracle as O
+    from test_gpu_ternary import KW, TOL, _fields
+
+    shape, bc = (70, 20, 1), (0, 1, 0)
+    k1, k2 = (0.2, 0.07, 0.9), (0.26, 0.05, 1.2)
+    kw2 = {**KW, "tau_g": 1.3}
+    phi0, psi0, rho0, u0 = _fields(0, shape, 5.0, seed=6)
+    p1 = F.make_params(0, shape, bc=bc, wall_u=_walls(1, -0.01, 0.01), ternary=k1, **KW)
+    p2 = F.make_params(0, shape, bc=bc, wall_u=_walls(1, 0.004, 0.015), ternary=k2, **kw2)
+    gpu = F.Lattice(p1, phi0, rho0, u0, psi0=psi0, stream=torch.cuda.Stream())
+    gpu.step(60)
+    gpu.set_params(p2)
+    gpu.step(61)
+    a = O.Lattice3(O.make_params(0, shape, bc=bc, wall_u=_walls(1, -0.01, 0.01), **KW), *k1,
+                   phi0, psi0, rho0, u0).step(60)
+    ref = O.Lattice3(O.make_params(0, shape, bc=bc, wall_u=_walls(1, 0.004, 0.015), **kw2), *k2,
+                     phi0, psi0, rho0, u0)
+    ref.set_populations(*a.populations())
+    ref.step(61)
+    o = ref.observe()
+    g = gpu.read(tuple(TOL))
+    err = {k: (max(np.abs(g["u"][c] - o["u" + "xyz"[c]]).max() for c in range(2)) if k == "u"
+               else np.abs(g[k] - o[k]).max()) for k in TOL}
+    pe = [np.abs(x - y).max() for x, y in zip(ref.populations(), gpu.populations())]
+    log("[parity] set_params_ternary: " + " ".join(f"{k}={v:.2e}" for k, v in err.items())
+        + " f={:.2e} g={:.2e} h={:.2e}".format(*pe))
+    for k, v in TOL.items():
+        assert err[k] < v, (k, err[k])
+    assert max(pe) < 1e-5, pe
+    gpu.close()

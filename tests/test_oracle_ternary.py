@@ -252,3 +252,28 @@ def test_flat_interface_of_every_pair():
         got[(m, q)] = c[m]
     vals = list(got.values())
     assert max(np.abs(a - b).max() for a in vals for b in vals) < 5e-6
+
+
+def test_population_hand_over_continues_the_run():
+    # the state between steps is the post-stream populations: a lattice made
+    # from other fields that takes over another's populations continues its
+    # run exactly (moving walls and a solid box, which keeps its own cells)
+    kind, shape, bc = 1, (12, 10, 8), (0, 0, 1)
+    wu = np.zeros((3, 2, 3)); wu[2, 0, 0] = -0.01; wu[2, 1, 0] = 0.01
+    mask = np.zeros((8, 10, 12), np.uint8); mask[3:5, 4:6, 2:4] = 1
+    phi0, psi0, rho0, u0 = _fields(kind, shape, seed=3)
+    p = O.make_params(kind, shape, bc=bc, wall_u=wu, **KW)
+    whole = O.Lattice3(p, 0.2, 0.07, 0.9, phi0, psi0, rho0, u0, mask).step(120)
+    first = O.Lattice3(p, 0.2, 0.07, 0.9, phi0, psi0, rho0, u0, mask).step(60)
+    other = _fields(kind, shape, seed=4)
+    second = O.Lattice3(p, 0.2, 0.07, 0.9, *other, mask)
+    pops = first.populations()
+    second.set_populations(*pops)
+    for a, b in zip(second.populations(), pops):
+        assert np.array_equal(a, b)
+    second.step(60)
+    for a, b in zip(second.populations(), whole.populations()):
+        assert np.array_equal(a, b)
+    ow, os_ = whole.observe(), second.observe()
+    for k in ("rho", "phi", "psi", "ux", "mu_psi", "P"):
+        assert np.array_equal(ow[k], os_[k]), k
