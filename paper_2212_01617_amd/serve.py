@@ -182,11 +182,18 @@ class Server:
         """Step count at which member m is next sampled."""
         return min(m.next_sample, self.step_cap)
 
-    def _sample(self, m: _Member, now: float):
-        """Sample D (and breakup); return the retirement reason or None."""
+    def _read(self, m: _Member):
+        """phi of member m at its current step (None for a run gone
+        non-finite), with that step."""
         try:
-            phi = self.engine.phi(m.handle)
+            return m, m.t, self.engine.phi(m.handle)
         except RunFailed:
+            return m, m.t, None
+
+    def _decide(self, m: _Member, t: int, phi):
+        """From phi sampled at step t: sample D (and breakup); return the
+        retirement reason or None."""
+        if phi is None:
             return "failed"
         req = m.req
         per = self.engine.periodic(req)
@@ -198,10 +205,10 @@ class Server:
         plane = "xz" if (req.flow == "shear" and req.kind == 1) else "xy"
         solid = self.engine.solid(m.handle) if hasattr(self.engine, "solid") else None
         m.D = Dg.deformation(phi, plane=plane, periodic=per, solid=solid).D
-        strain = m.t * m.rate
+        strain = t * m.rate
         if m.tracker.add(strain, m.D):
             return "steady"
-        if strain >= self.strain_cap or m.t >= self.step_cap:
+        if strain >= self.strain_cap or t >= self.step_cap:
             return "cap"
         return None
 
@@ -221,6 +228,7 @@ class Server:
             self.engine.prepare(ok)   # per-geometry set-up, before the clock starts
         pending = deque(ok)
         active: list[_Member] = []
+        samples = []   # (member, step, phi) read at the end of the last chunk
         used = 0
         lu = 0.0
         peak_bytes = peak_members = 0
@@ -248,28 +256,38 @@ class Server:
                     self.sleep(max(0.0, pending[0].arrival - (self.clock() - t0)))
                 continue
             # step up to the next sample that falls due (or the step cap, which
-            # a slow request may reach before its first sample), at most one chunk
-            n = min(self.chunk, min(self._due(m) - m.t for m in active))
-            n = max(n, 1)
-            self.engine.step(n)
-            lu += n * sum(m.req.cells for m in active)
+            # a slow request may reach before its first sample), at most one
+            # chunk; a member sampled at the step cap retires and sets no bound
+            live = [m for m in active if m.t < self.step_cap]
+            n = min([self.chunk] + [self._due(m) - m.t for m in live]) if live else 0
+            n = max(n, 1) if live else 0
+            if n:
+                self.engine.step(n)   # asynchronous: the samples below are decided meanwhile
+            # decide the samples read at the end of the previous chunk; a
+            # member that retires has been stepped once more, which its
+            # outcome does not count
             done = []
-            for m in active:
-                m.t += n
-                if m.t >= self._due(m):
-                    if m.t >= m.next_sample:
-                        m.next_sample += m.sample_every
-                    reason = self._sample(m, self.clock() - t0)
-                    if reason:
-                        done.append((m, reason))
-            for m, reason in done:
+            for m, t, phi in samples:
+                reason = self._decide(m, t, phi)
+                if reason:
+                    done.append((m, reason, t))
+            samples = []
+            retiring = {id(m) for m, _, _ in done}
+            lu += n * sum(m.req.cells for m in active if id(m) not in retiring)
+            for m, reason, t in done:
                 self.engine.retire(m.handle)
                 active.remove(m)
                 used -= self.engine.footprint(m.req)
                 outcomes.append(Outcome(m.req.rid, reason, m.req.arrival, m.admitted, self.clock() - t0,
-                                        m.t, m.t * m.rate, m.D, m.req.cells))
+                                        t, t * m.rate, m.D, m.req.cells))
                 if self.on_retire:
                     self.on_retire(outcomes[-1])
+            for m in active:
+                m.t += n
+                if n and m.t >= self._due(m):
+                    if m.t >= m.next_sample:
+                        m.next_sample += m.sample_every
+                    samples.append(self._read(m))
         wall = self.clock() - t0
         return Report(outcomes, wall, lu, peak_bytes, peak_members)
 
