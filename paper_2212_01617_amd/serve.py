@@ -284,7 +284,7 @@ class Server:
                     self.on_retire(outcomes[-1])
             for m in active:
                 m.t += n
-                if n and m.t >= self._due(m):
+                if m.t >= self._due(m):
                     if m.t >= m.next_sample:
                         m.next_sample += m.sample_every
                     samples.append(self._read(m))

@@ -256,3 +256,16 @@ def test_lattice_inputs_follow_the_request():
     assert sum(om) == pytest.approx(0.0) and all(abs(abs(o) - abs(om[0])) < 1e-15 for o in om)
     # the droplet clears the rollers
     assert np.all(phi2[mask2 > 0] < 0)
+
+
+def test_zero_step_cap_samples_once_and_retires():
+    # members admitted at the cap are sampled at step 0 and retire without
+    # any step being taken
+    clock = Clock()
+    rs = _requests(6, seed=5)
+    eng = FakeEngine(clock, budget=1 << 40)
+    srv = serve.Server(eng, 1 << 40, max_members=8, chunk=100, step_cap=0, clock=clock, sleep=clock.sleep)
+    rep = srv.run(rs)
+    assert sorted(o.rid for o in rep.outcomes) == sorted(r.rid for r in rs)
+    assert all(o.reason == "cap" and o.steps == 0 for o in rep.outcomes)
+    assert rep.lattice_updates == 0 and not eng.members
