@@ -269,3 +269,34 @@ def test_zero_step_cap_samples_once_and_retires():
     assert sorted(o.rid for o in rep.outcomes) == sorted(r.rid for r in rs)
     assert all(o.reason == "cap" and o.steps == 0 for o in rep.outcomes)
     assert rep.lattice_updates == 0 and not eng.members
+
+
+def test_counted_updates_stop_at_each_retirement_step():
+    # samples are decided while the next chunk runs, so a retiring member is
+    # stepped once more; its outcome and the aggregate count only the steps
+    # up to the sample it retired on
+    clock = Clock()
+    rs = _requests(10, seed=6)
+    eng = FakeEngine(clock, budget=1 << 40)
+    stepped = {}
+    base_step, base_retire = eng.step, eng.retire
+
+    def step(n):
+        for m in eng.members.values():
+            stepped[m[0].rid] = stepped.get(m[0].rid, 0) + n
+        base_step(n)
+
+    def retire(h):
+        eng.final = getattr(eng, "final", {})
+        rid = eng.members[h][0].rid
+        eng.final[rid] = stepped.get(rid, 0)
+        base_retire(h)
+
+    eng.step, eng.retire = step, retire
+    rep = serve.Server(eng, 1 << 40, max_members=4, chunk=300, strain_cap=4.0, step_cap=20_000,
+                       clock=clock, sleep=clock.sleep).run(rs)
+    assert len(rep.outcomes) == len(rs)
+    for o in rep.outcomes:
+        assert o.steps <= eng.final[o.rid] <= o.steps + 300
+        assert abs(o.strain - o.steps * (1e-3 if rs[o.rid].Re >= 0.105 else 1e-6)) < 1e-12
+    assert rep.lattice_updates == sum(o.steps * o.cells for o in rep.outcomes)
