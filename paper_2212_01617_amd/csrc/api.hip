@@ -5,8 +5,8 @@
 // (rho - 1, phi), the coupling values (rho - 1, phi, Pi, mu_phi), the FP32
 // path's partial moment sums, an auxiliary float4 field, the list of solid
 // cells next to fluid, and the reduction partials.  Steps are enqueued on the caller's stream; on a
-// non-default stream a pair of steps (even + odd AA parity) is captured once
-// into a HIP graph and replayed.
+// non-default stream runs of 16 steps, and pairs of steps (even + odd AA
+// parity), are captured once into HIP graphs and replayed.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -215,6 +215,8 @@ struct fre_lattice {
   std::vector<int> fill_host;
   hipGraphExec_t graph;  // two steps starting at even parity
   bool graph_ok;
+  hipGraphExec_t graph_run;  // kGraphRun steps starting at even parity
+  bool graph_run_ok;
   fre_batch *batch;      // non-null while the lattice is a batch member
   int dev;               // device current at init
 };
@@ -250,12 +252,14 @@ namespace {
 // executable holds their kernel arguments: destroying it before they have
 // run lets them read whatever reuses that memory (for example the arguments
 // of the next graph, with new parameters), so the stream is drained first.
+// Steps per graph launch of a lattice's long runs (even).
+constexpr int kGraphRun = 16;
+
 void reset_graph(fre_lattice *L) {
-  if (L->graph_ok) {
-    (void)hipStreamSynchronize(L->a.stream);
-    (void)hipGraphExecDestroy(L->graph);
-  }
-  L->graph_ok = false;
+  if (L->graph_ok || L->graph_run_ok) (void)hipStreamSynchronize(L->a.stream);
+  if (L->graph_ok) (void)hipGraphExecDestroy(L->graph);
+  if (L->graph_run_ok) (void)hipGraphExecDestroy(L->graph_run);
+  L->graph_ok = L->graph_run_ok = false;
 }
 
 // A batch member's state is advanced on the batch's stream: wait for it
@@ -427,7 +431,7 @@ fre_status lattice_init(const fre_params *p, void *device_buf, size_t bytes, voi
   L->n_user = N;
   L->t = 0;
   L->state = 0;
-  L->graph_ok = false;
+  L->graph_ok = L->graph_run_ok = false;
   if (hipGetDevice(&L->dev) != hipSuccess) { delete L; return fail(FRE_EDEVICE, "hipGetDevice failed"); }
   std::vector<uint8_t> mask;
   std::vector<uint32_t> nbm;
@@ -586,23 +590,46 @@ fre_status fre_step(fre_lattice *L, int64_t n) {
     if (s != FRE_OK) return s;
     --n;
   }
-  if (!L->graph_ok) {
+  // a graph of `pairs` even + odd step pairs
+  auto capture = [&](int pairs, hipGraphExec_t *out) -> fre_status {
     hipGraph_t g;
     HIP_TRY(hipStreamBeginCapture(st, hipStreamCaptureModeThreadLocal));
-    launch_lattice_step(L->a, 0);
-    launch_lattice_step(L->a, 1);
+    for (int k = 0; k < pairs; ++k) {
+      launch_lattice_step(L->a, 0);
+      launch_lattice_step(L->a, 1);
+    }
     hipError_t e = hipStreamEndCapture(st, &g);
     if (e != hipSuccess) return fail(FRE_EDEVICE, "graph capture failed: %s", hipGetErrorString(e));
-    e = hipGraphInstantiate(&L->graph, g, nullptr, nullptr, 0);
+    e = hipGraphInstantiate(out, g, nullptr, nullptr, 0);
     (void)hipGraphDestroy(g);
     if (e != hipSuccess) return fail(FRE_EDEVICE, "graph instantiate failed: %s", hipGetErrorString(e));
-    L->graph_ok = true;
+    return FRE_OK;
+  };
+  // runs of kGraphRun steps (each graph launch leaves the GPU idle for a few
+  // microseconds, so longer graphs leave it idle less often), then pairs
+  if (n >= kGraphRun) {
+    if (!L->graph_run_ok) {
+      fre_status s = capture(kGraphRun / 2, &L->graph_run);
+      if (s != FRE_OK) return s;
+      L->graph_run_ok = true;
+    }
+    for (; n >= kGraphRun; n -= kGraphRun) {
+      HIP_TRY(hipGraphLaunch(L->graph_run, st));
+      L->t += kGraphRun;
+    }
   }
-  for (int64_t k = 0; k + 1 < n; k += 2) {
-    HIP_TRY(hipGraphLaunch(L->graph, st));
-    L->t += 2;
+  if (n >= 2) {
+    if (!L->graph_ok) {
+      fre_status s = capture(1, &L->graph);
+      if (s != FRE_OK) return s;
+      L->graph_ok = true;
+    }
+    for (; n >= 2; n -= 2) {
+      HIP_TRY(hipGraphLaunch(L->graph, st));
+      L->t += 2;
+    }
   }
-  if (n & 1) return one();
+  if (n) return one();
   return FRE_OK;
 }
 
