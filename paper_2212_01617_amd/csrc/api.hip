@@ -241,8 +241,10 @@ struct fre_batch {
   int rows;           // rows of 64 cells per work item
   int blocks_per_cu;  // persistent grid of the cell kernels
   int ncu;
-  hipGraphExec_t graph;
+  hipGraphExec_t graph;      // two steps starting at even parity
   bool graph_ok;
+  hipGraphExec_t graph_run;  // kGraphRun steps starting at even parity
+  bool graph_run_ok;
   int grid_cells, grid_fill;
 };
 
@@ -1153,11 +1155,10 @@ Inst inst_of(const fre_lattice *L, const void *base) {
 
 // As reset_graph: the batch's queued graph launches finish first.
 void batch_reset_graph(fre_batch *B) {
-  if (B->graph_ok) {
-    (void)hipStreamSynchronize(B->stream);
-    (void)hipGraphExecDestroy(B->graph);
-  }
-  B->graph_ok = false;
+  if (B->graph_ok || B->graph_run_ok) (void)hipStreamSynchronize(B->stream);
+  if (B->graph_ok) (void)hipGraphExecDestroy(B->graph);
+  if (B->graph_run_ok) (void)hipGraphExecDestroy(B->graph_run);
+  B->graph_ok = B->graph_run_ok = false;
 }
 
 // Work-list order for the XCDs.  The persistent cell kernels walk a class's
@@ -1310,7 +1311,7 @@ fre_status fre_batch_create(void *device_buf, size_t bytes, void *hip_stream, in
   B->slot.assign(max_slots, nullptr);
   B->parity = 0;
   B->classes = 0;
-  B->graph_ok = false;
+  B->graph_ok = B->graph_run_ok = false;
   int dev = 0, ncu = 256;
   if (hipGetDevice(&dev) == hipSuccess) {
     int v = 0;
@@ -1391,24 +1392,36 @@ fre_status fre_batch_step(fre_batch *B, int64_t n) {
     for (int64_t k = 0; k < n && s == FRE_OK; ++k) s = one();
   } else {
     if (B->parity) { s = one(); --n; }
-    if (s == FRE_OK && !B->graph_ok) {
+    // a graph of `pairs` even + odd step pairs
+    auto capture = [&](int pairs, hipGraphExec_t *out) -> fre_status {
       hipGraph_t g;
       HIP_TRY(hipStreamBeginCapture(st, hipStreamCaptureModeThreadLocal));
-      batch_launch_step(B, 0);
-      batch_launch_step(B, 1);
+      for (int k = 0; k < pairs; ++k) {
+        batch_launch_step(B, 0);
+        batch_launch_step(B, 1);
+      }
       hipError_t e = hipStreamEndCapture(st, &g);
       if (e != hipSuccess) return fail(FRE_EDEVICE, "batch graph capture failed: %s", hipGetErrorString(e));
-      e = hipGraphInstantiate(&B->graph, g, nullptr, nullptr, 0);
+      e = hipGraphInstantiate(out, g, nullptr, nullptr, 0);
       (void)hipGraphDestroy(g);
       if (e != hipSuccess) return fail(FRE_EDEVICE, "batch graph instantiate failed: %s", hipGetErrorString(e));
-      B->graph_ok = true;
-    }
-    for (int64_t k = 0; s == FRE_OK && k + 1 < n; k += 2) {
-      hipError_t e = hipGraphLaunch(B->graph, st);
-      if (e != hipSuccess) s = fail(FRE_EDEVICE, "batch graph launch failed: %s", hipGetErrorString(e));
-      else done += 2;
-    }
-    if (s == FRE_OK && (n & 1)) s = one();
+      return FRE_OK;
+    };
+    // runs of kGraphRun steps, then pairs, as for a single lattice
+    auto replay = [&](hipGraphExec_t *gx, bool *ok, int steps) {
+      if (s == FRE_OK && n >= steps && !*ok) {
+        s = capture(steps / 2, gx);
+        *ok = s == FRE_OK;
+      }
+      for (; s == FRE_OK && n >= steps; n -= steps) {
+        hipError_t e = hipGraphLaunch(*gx, st);
+        if (e != hipSuccess) s = fail(FRE_EDEVICE, "batch graph launch failed: %s", hipGetErrorString(e));
+        else done += steps;
+      }
+    };
+    replay(&B->graph_run, &B->graph_run_ok, kGraphRun);
+    replay(&B->graph, &B->graph_ok, 2);
+    if (s == FRE_OK && n) s = one();
   }
   for (fre_lattice *L : B->slot)
     if (L) L->t += done;
