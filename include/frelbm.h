@@ -189,6 +189,9 @@ fre_status fre_set_params(fre_lattice *L, const fre_params *p);
 
 /* Advance n >= 0 time steps (Algorithm 1 at every fluid node, then
  * streaming with moving bounce-back), asynchronously on the bound stream.
+ * On a non-default stream the steps are replayed from HIP graphs captured
+ * on first use (runs of 16 steps, then pairs); on the default stream they
+ * are launched one by one.  Both give bitwise the same state.
  * Returns FRE_ESTATE if the lattice has failed. */
 fre_status fre_step(fre_lattice *L, int64_t n);
 
